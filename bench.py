@@ -1,0 +1,208 @@
+"""Benchmark of the R-STHOSVD hot path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision f32]
+
+A step is one whole decomposition (every mode: sketch, power step, CholeskyQR2,
+projection + Gram, Jacobi EVD, factor, truncation) of a tensor already
+resident in HBM.  Prints one JSON line with the tensor throughput (GB/s of
+input per second), the roofline of the dominant kernel measured live with HIP
+events, and the FP64 oracle timed on the host over a bounded sample.
+"""
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, GB/s
+PEAKS_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_counts(dims, ranks, p, q, elem, order=None):
+    """Per-mode algorithmic bytes / flops of the minimal pass structure:
+    (2 + q) reads of the current tensor, B written and read once, the
+    truncated tensor written once."""
+    d = list(dims)
+    order = list(range(len(dims))) if order is None else list(order)
+    modes = []
+    for n in order:
+        M = int(np.prod(d))
+        I = d[n]
+        J = M // I
+        K = min(ranks[n] + p, I, J)
+        R = ranks[n]
+        byts = elem * ((2 + q) * M + 2 * K * J + R * J)
+        flops = (4 + 4 * q) * K * M + 2 * K * K * J + 2 * R * K * J
+        modes.append(dict(mode=n, M=M, I=I, J=J, K=K, R=R, bytes=byts, flops=flops,
+                          power_bytes=elem * M, power_flops=4 * K * M,
+                          sketch_bytes=elem * M, sketch_flops=2 * K * M))
+        d[n] = R
+    return modes
+
+
+def expected_rel_error(dims, ranks, noise, core_norm2):
+    """Closed-form E when the subspaces capture the signal: the noise outside
+    the Tucker subspace over the total norm."""
+    M = float(np.prod(dims))
+    frac = 1.0 - float(np.prod([r / i for r, i in zip(ranks, dims)]))
+    n2 = noise ** 2 * M
+    return math.sqrt(n2 * frac / (core_norm2 + n2))
+
+
+def cpu_baseline(x, w):
+    """Time the FP64 oracle on a bounded sample: the leading slabs of the
+    last mode, same ranks / p / q / seed."""
+    from oracle.tucker import r_sthosvd as oracle_r_sthosvd
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    dims = x.shape
+    slab = int(np.prod(dims[:-1]))
+    # the smallest valid sample: R_N + 1 leading slabs of the last mode
+    s = min(int(w["target"][-1]) + 1, dims[-1])
+    sub = x[..., :s].astype(np.float64)
+    t0 = time.perf_counter()
+    oracle_r_sthosvd(sub, w["target"], w["p"], w["q"], w["seed"])
+    t = time.perf_counter() - t0
+    nbytes = slab * s * x.dtype.itemsize
+    return {"value": nbytes / t / 1e9, "unit": "GB/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"R-STHOSVD of the leading {s} of {dims[-1]} last-mode slabs "
+                      f"({'x'.join(str(v) for v in dims[:-1])}x{s}, {nbytes / 1e9:.2f} GB as "
+                      f"{x.dtype.name}), oracle incl. its explicit-residual E, {t:.1f} s, "
+                      f"host cpu_count={os.cpu_count()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="r_sthosvd_200x4_r25")
+    ap.add_argument("--precision", default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=5)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2001_07124_amd import api
+    from paper_2001_07124_amd.inputs import WORKLOADS, tucker_tensor
+
+    w = dict(WORKLOADS[args.workload])
+    prec = args.precision or w["prec"]
+    dims, ranks = w["dims"], w["target"]
+    log(f"[bench] generating {args.workload} dims={dims}")
+    t0 = time.perf_counter()
+    x, core, _ = tucker_tensor(dims, w["ranks"], seed=w["data_seed"], factors=w["factors"],
+                               decay=w["decay"], noise=w["noise"], dtype=w["dtype"])
+    log(f"[bench] generated in {time.perf_counter() - t0:.1f}s; uploading")
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    xd = api.to_device(x, dev)
+    torch.cuda.synchronize()
+    tt = torch.float64 if w["dtype"] == np.float64 else torch.float32
+    dec = api.Decomposer(dims, ranks, algo=w["algo"], p=w["p"], q=w["q"], seed=w["seed"],
+                         dtype=tt, precision=prec, device=dev)
+    log(f"[bench] workspace {dec.ws_bytes / 1e9:.2f} GB; warmup {args.warmup}")
+    for _ in range(args.warmup):
+        dec.run(xd)
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    stream = torch.cuda.current_stream(dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        dec.run(xd)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms = ev0.elapsed_time(ev1) / args.steps
+    res = dec.result()
+    e_gpu = res.rel_error
+    elem = np.dtype(w["dtype"]).itemsize
+    tensor_bytes = float(np.prod(dims)) * elem
+    value = tensor_bytes / (ms * 1e-3) / 1e9
+    modes = algorithmic_counts(dims, ranks, w["p"], w["q"], elem)
+    alg_bytes = sum(m["bytes"] for m in modes)
+    alg_flops = sum(m["flops"] for m in modes)
+    path_roof_ms = alg_bytes / (HBM_PEAK_GBPS * 1e9) * 1e3
+    log(f"[bench] {ms:.3f} ms/step, E={e_gpu:.6f}")
+
+    # dominant kernel: the fused power pass (or the sketch when q = 0) of the
+    # first mode, timed live through its step-level entry point with events
+    m0 = modes[0]
+    view = (1, dims[0], int(np.prod(dims[1:])))
+    flat = xd.as_strided((xd.numel(),), (1,))
+    if w["q"] > 0:
+        qmat = torch.linalg.qr(torch.randn(dims[0], m0["K"], dtype=torch.float64))[0].to(dev, tt)
+        fn = lambda: api.power(flat, view, qmat)  # noqa: E731
+        kb, kf, kname = m0["power_bytes"], m0["power_flops"], "k_stream<OP_POWER> (mode 1)"
+    else:
+        fn = lambda: api.sketch(flat, view, m0["K"], 0, 0, 2)  # noqa: E731
+        kb, kf, kname = m0["sketch_bytes"], m0["sketch_flops"], "k_stream<OP_SKETCH> (mode 1)"
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.kernel_reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    kms = e0.elapsed_time(e1) / args.kernel_reps
+    k_gbps = kb / (kms * 1e-3) / 1e9
+    k_tflops = kf / (kms * 1e-3) / 1e12
+    peak_tf = PEAKS_TFLOPS["f64" if elem == 8 else ("bf16" if prec == "bf16" else "f32")]
+    mfma_frac = k_tflops / peak_tf
+    hbm_frac = k_gbps / HBM_PEAK_GBPS
+    if mfma_frac > hbm_frac:
+        roofline = {"bound": "mfma", "achieved": round(k_tflops, 3), "peak": peak_tf,
+                    "unit": "TFLOP/s", "frac": round(mfma_frac, 4), "traffic": None}
+    else:
+        roofline = {"bound": "hbm", "achieved": round(k_gbps, 1), "peak": HBM_PEAK_GBPS,
+                    "unit": "GB/s", "frac": round(hbm_frac, 4), "traffic": None}
+    roofline.update({"kernel": kname, "kernel_ms": round(kms, 4),
+                     "algorithmic_bytes": kb, "algorithmic_flops": kf})
+
+    out = {
+        "metric": "R-STHOSVD tensor GB/s (% HBM roofline) at 1e-3 rel err",
+        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f32", "f64": "f64", "bf16": "bf16"}[prec], "data": "synthetic",
+        "config": {"workload": args.workload, "dims": list(dims), "ranks": list(ranks),
+                   "p": w["p"], "q": w["q"], "precision": prec, "algo": w["algo"]},
+        "rel_error": e_gpu,
+        "rel_error_expected": expected_rel_error(dims, w["ranks"], w["noise"],
+                                                 float(np.sum(core ** 2))),
+        "path": {"algorithmic_bytes": alg_bytes, "algorithmic_flops": alg_flops,
+                 "algorithmic_GBps": round(alg_bytes / (ms * 1e-3) / 1e9, 1),
+                 "hbm_roofline_ms": round(path_roof_ms, 4),
+                 "hbm_roofline_frac": round(path_roof_ms / ms, 4)},
+        "roofline": roofline,
+        "wall_s_timed": round(t_wall, 3),
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on a bounded host sample")
+        out["cpu_baseline"] = cpu_baseline(x, w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

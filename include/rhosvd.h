@@ -1,0 +1,209 @@
+/*
+ * rhosvd.h — C ABI of the MI355X (gfx950) randomized HOSVD library.
+ *
+ * The library computes a Tucker decomposition [[G; U_1, ..., U_N]] of a dense
+ * tensor X with the random-projection HOSVD (Algorithm 6 of Ahmadi-Asl et al.,
+ * "Randomized Algorithms for Computation of Tucker Decomposition and Higher
+ * Order SVD (HOSVD)") or its sequentially truncated variant R-STHOSVD
+ * (Algorithm 8, which applies the basic randomized SVD of Algorithm 1 to the
+ * current n-unfolding for each mode in turn).  Inputs follow the problem
+ * statement of those algorithms: a tensor, a target multilinear rank
+ * (R_1..R_N), an oversampling p and a power-iteration count q (Algorithm 1).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Layout.  Tensors are dense and first-index-fastest: element
+ *   (i_1, ..., i_N) (0-based) lives at offset i_1 + I_1 (i_2 + I_2 (i_3 + ...)).
+ *   With this layout the n-unfolding of Section 2 (column index
+ *   j = sum_{k != n} i_k J_k, J_k = prod_{m<k, m!=n} I_m) is a strided view:
+ *   element (i_n, j) with j = l + L t sits at l + L (i_n + I_n t), where
+ *   L = prod_{m<n} I_m.  Matrices are column-major.
+ * - Memory.  `data`, `core`, `factors[n]`, `report`, `workspace` and every
+ *   buffer named "device" are device pointers on the context's device; the
+ *   caller allocates and owns them.  Arrays named "host" are read during the
+ *   call only.  The library never allocates device memory except inside
+ *   rhosvd_create (nothing) — all scratch comes from the caller's workspace.
+ * - Streams.  `stream` is a hipStream_t passed as void*; NULL is the default
+ *   stream.  Every compute call only *enqueues* work and returns; outputs are
+ *   valid once the stream has been synchronised.
+ * - Errors.  Every argument is validated before anything is enqueued; a
+ *   rejected call returns RHOSVD_EINVAL (or RHOSVD_EUNSUPPORTED for a valid
+ *   problem outside the implemented limits) and has no side effects.  A HIP
+ *   failure returns RHOSVD_EHIP; rhosvd_last_hip_error() gives the code.
+ *   Numerical warnings are reported asynchronously in rhosvd_report.flags.
+ *   No call throws or aborts.
+ * - Omega.  The Gaussian test matrices are generated in the kernels from
+ *   Philox4x32-10 (Salmon et al., SC'11): entry (j, k) of the J x K matrix of
+ *   mode n has linear index e = k J + j, counter (e>>2 low, e>>2 high, n, tag),
+ *   key (seed low, seed high), output word e & 3, uniform
+ *   u = ((x >> 9) + 0.5) 2^-23 and Box-Muller on word pairs (0,1), (2,3).
+ *   tag = 1 for RP-HOSVD, 2 for R-STHOSVD.
+ */
+#ifndef RHOSVD_H
+#define RHOSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RHOSVD_MAX_ORDER 16
+#define RHOSVD_MAX_K 128      /* largest sketch width K = R + p handled */
+
+typedef enum {
+    RHOSVD_OK = 0,
+    RHOSVD_EINVAL = 1,        /* invalid argument; nothing was enqueued */
+    RHOSVD_ENOMEM = 2,        /* workspace smaller than rhosvd_workspace_size */
+    RHOSVD_EHIP = 3,          /* a HIP runtime call failed */
+    RHOSVD_ENUMERIC = 4,      /* reserved */
+    RHOSVD_EBUSY = 5,         /* reserved */
+    RHOSVD_EUNSUPPORTED = 6   /* valid problem beyond the implemented limits */
+} rhosvd_status;
+
+enum { RHOSVD_F32 = 0, RHOSVD_F64 = 1 };                     /* tensor dtypes */
+enum { RHOSVD_RP_HOSVD = 0, RHOSVD_R_STHOSVD = 1 };          /* algorithms */
+/* Precision of the streaming contractions (inputs of the matrix cores);
+ * accumulation is FP32 (FP64 for RHOSVD_PREC_F64); Gram matrices, Cholesky
+ * and eigen-decompositions are always FP64. */
+enum { RHOSVD_PREC_F64 = 0, RHOSVD_PREC_F32 = 1, RHOSVD_PREC_BF16 = 2 };
+
+/* report.flags bits (warnings, set on the device) */
+#define RHOSVD_FLAG_K_CAPPED     0x1u  /* some K_n < R_n + p (capped by I_n or J_n) */
+#define RHOSVD_FLAG_CQR_SHIFTED  0x2u  /* a Gram matrix needed the shifted Cholesky */
+#define RHOSVD_FLAG_EVD_NOCONV   0x4u  /* Jacobi EVD hit its sweep limit */
+#define RHOSVD_FLAG_QR_HOUSEHOLDER 0x8u /* CholeskyQR broke down even with the shift (Y numerically
+                                           rank deficient); that basis came from Householder QR */
+
+/* params.flags bits */
+#define RHOSVD_OPT_NONE 0u
+
+typedef struct rhosvd_ctx rhosvd_ctx;
+
+typedef struct {
+    int32_t order;            /* N, 2..16 */
+    const int64_t* dims;      /* host, N extents, each >= 1 */
+    int32_t dtype;            /* RHOSVD_F32 or RHOSVD_F64 */
+    const void* data;         /* device, prod(dims) elements, first-index-fastest */
+} rhosvd_tensor;
+
+typedef struct {
+    int32_t algo;             /* RHOSVD_RP_HOSVD or RHOSVD_R_STHOSVD */
+    const int32_t* ranks;     /* host, N target ranks, 1 <= R_n <= I_n */
+    int32_t oversample;       /* p >= 0; K_n = min(R_n + p, I_n, J_n) */
+    int32_t power_iters;      /* q, 0..8 */
+    uint64_t seed;            /* Omega key */
+    const int32_t* mode_order;/* host permutation of 0..N-1 or NULL (ascending); R-STHOSVD only */
+    int32_t precision;        /* RHOSVD_PREC_*; F64 requires F64 data */
+    uint32_t flags;           /* RHOSVD_OPT_*, must be 0 */
+} rhosvd_params;
+
+/* Written by the device at the end of rhosvd_decompose (stream order). */
+typedef struct {
+    double norm_x2;           /* ||X||_F^2, FP64 accumulation */
+    double norm_core2;        /* ||G||_F^2 */
+    int32_t order;
+    int32_t k_used[RHOSVD_MAX_ORDER];
+    uint32_t flags;           /* RHOSVD_FLAG_* */
+    double sigma[RHOSVD_MAX_ORDER][RHOSVD_MAX_K]; /* per mode, R_n leading singular values, descending */
+} rhosvd_report;
+
+typedef struct {
+    void* core;               /* device, R_1 x ... x R_N, first-index-fastest, dtype of X */
+    void* const* factors;     /* host array of N device pointers: U_n, I_n x R_n column-major, dtype of X */
+    void* report;             /* device, sizeof(rhosvd_report) bytes, or NULL */
+} rhosvd_output;
+
+/* Human-readable name of a status code (static string). */
+const char* rhosvd_status_string(int32_t status);
+
+/* HIP error code of the most recent RHOSVD_EHIP on this thread (0 if none). */
+int32_t rhosvd_last_hip_error(void);
+
+/* Create a context bound to HIP device `device` (records its CU count and
+ * limits; allocates no device memory).  EINVAL for a NULL out-pointer or a
+ * device index out of range, EHIP if the runtime fails. */
+int32_t rhosvd_create(rhosvd_ctx** ctx, int32_t device);
+void rhosvd_destroy(rhosvd_ctx* ctx);
+
+/* Bytes of device workspace rhosvd_decompose needs for this problem.
+ * Pure host computation (no HIP call); EINVAL/EUNSUPPORTED as for decompose. */
+int32_t rhosvd_workspace_size(const rhosvd_tensor* x, const rhosvd_params* p, size_t* bytes);
+
+/* Enqueue the whole decomposition on `stream` (Algorithm 6 or 8, every step
+ * on the GPU).  X is read only.  Outputs: core, factors, optional report.
+ * The workspace must hold at least rhosvd_workspace_size bytes (ENOMEM
+ * otherwise) and be 256-byte aligned; it must not be reused by other work
+ * until the stream has passed this call. */
+int32_t rhosvd_decompose(rhosvd_ctx* ctx, const rhosvd_tensor* x, const rhosvd_params* p,
+                         void* workspace, size_t ws_bytes, const rhosvd_output* out,
+                         void* stream);
+
+/* Relative error E = sqrt(max(0, ||X||^2 - ||G||^2)) / ||X|| (Section 8,
+ * eq. Relativeerror, via the orthogonal-projection identity of Section 5.1)
+ * from a host copy of the report. */
+double rhosvd_report_rel_error(const rhosvd_report* r);
+
+/* ---- Step-level entry points (one hot-path step each; used by the per-step
+ * parity tests and available to callers that compose their own pipeline).
+ * The tensor view (L, I, T) is the n-unfolding of Section 2: element (i, j)
+ * with j = l + L t at src[l + L (i + I t)], J = L T columns.  dtype selects
+ * float (RHOSVD_F32) or double (RHOSVD_F64) for src and outputs. ---- */
+
+/* Fill out (J x K column-major, dtype) with Omega of (seed, mode, tag).
+ * Test kernel for the in-kernel generator (Algorithm 1 step 1). */
+int32_t rhosvd_omega_fill(rhosvd_ctx* ctx, uint64_t seed, int32_t mode, int32_t tag,
+                          int64_t J, int32_t K, int32_t dtype, void* out, void* stream);
+
+/* Sketch Y = S_(n) Omega (Algorithm 1 step 2 with q = 0; Algorithm 6 step 3).
+ * y: device, I x K column-major, double.  If norm2 != NULL it receives
+ * ||S||^2 (device double).  Workspace: rhosvd_step_workspace_size. */
+int32_t rhosvd_sketch(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t precision,
+                      int64_t L, int64_t I, int64_t T, int32_t K, uint64_t seed,
+                      int32_t mode, int32_t tag, double* y, double* norm2,
+                      void* workspace, size_t ws_bytes, void* stream);
+
+/* One fused power step Y = S_(n) (S_(n)^T Q) (Algorithm 1 step 2, q > 0).
+ * q_in: device, I x K column-major, dtype; y: device, I x K double. */
+int32_t rhosvd_power(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t precision,
+                     int64_t L, int64_t I, int64_t T, int32_t K, const void* q_in,
+                     double* y, void* workspace, size_t ws_bytes, void* stream);
+
+/* Mode-n product out = S x_n M^T with M (I x Kout column-major, dtype;
+ * NULL means the identity, which needs Kout == I),
+ * written folded: out[l + L (k + Kout t)].  If gram != NULL it also receives
+ * the Kout x Kout matrix B B^T of the (Kout x J) unfolding B of out (device
+ * double, column-major) — Algorithm 1 step 4 plus the Gram for step 5.
+ * If norm2 != NULL it receives ||out||^2 (device double). */
+int32_t rhosvd_ttm(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t precision,
+                   int64_t L, int64_t I, int64_t T, int32_t Kout, const void* m,
+                   void* out, double* gram, double* norm2,
+                   void* workspace, size_t ws_bytes, void* stream);
+
+/* Orthonormal basis of Y (I x K column-major double, I >= K) by CholeskyQR2
+ * with an FP64 Gram/Cholesky and a shifted first pass when the Gram is not
+ * numerically positive definite (Algorithm 1 step 3).  q_out: dtype-typed
+ * I x K.  work: device scratch of 2 I K doubles whose first I K doubles hold
+ * the FP64 Q on return.  flags (optional device uint32) gets
+ * RHOSVD_FLAG_CQR_SHIFTED or-ed in. */
+int32_t rhosvd_orthonormalize(rhosvd_ctx* ctx, const double* y, int64_t I, int32_t K,
+                              int32_t dtype, void* q_out, double* work, uint32_t* flags,
+                              void* stream);
+
+/* Symmetric eigen-decomposition C = V diag(lambda) V^T of a K x K matrix
+ * (device double, column-major) by cyclic Jacobi in FP64, eigenvalues sorted
+ * descending (Algorithm 1 step 5 through the Gram of B).  v: K x K double,
+ * lambda: K doubles (device).  flags as above (RHOSVD_FLAG_EVD_NOCONV). */
+int32_t rhosvd_sym_evd(rhosvd_ctx* ctx, const double* c, int32_t K, double* v,
+                       double* lambda, uint32_t* flags, void* stream);
+
+/* Bytes of workspace the step-level calls need for a view (I, K) with at
+ * most J columns. */
+size_t rhosvd_step_workspace_size(int64_t I, int32_t K, int64_t J);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RHOSVD_H */

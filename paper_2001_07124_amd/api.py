@@ -1,0 +1,311 @@
+"""Python binding of the randomized HOSVD library (argument marshalling only).
+
+PyTorch supplies device memory and the stream; every arithmetic step runs in
+the HIP kernels of librhosvd.so.  Tensors follow the library layout: an
+order-N tensor of extents (I_1, ..., I_N) is first-index-fastest, i.e. a torch
+tensor with Fortran strides (see `to_device`), or a flat 1-D buffer plus
+explicit `dims`.  Column-major matrices are returned as transposed views of
+contiguous tensors, so `U.shape == (I_n, R_n)` with strides (1, I_n).
+"""
+import ctypes
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_ctx_cache = {}
+
+
+def _context(device_index):
+    lib = L.load()
+    c = _ctx_cache.get(device_index)
+    if c is None:
+        c = ctypes.c_void_p()
+        L.check(lib.rhosvd_create(ctypes.byref(c), int(device_index)), "rhosvd_create")
+        _ctx_cache[device_index] = c
+    return c
+
+
+def _dtype_code(dt):
+    if dt == torch.float32:
+        return L.F32
+    if dt == torch.float64:
+        return L.F64
+    raise TypeError("tensor dtype must be float32 or float64")
+
+
+_PREC = {"f64": L.PREC_F64, "f32": L.PREC_F32, "bf16": L.PREC_BF16}
+
+
+def _prec_code(precision, dt):
+    if precision is None:
+        return L.PREC_F64 if dt == torch.float64 else L.PREC_F32
+    return _PREC[precision]
+
+
+def fortran_strides(dims):
+    s, out = 1, []
+    for d in dims:
+        out.append(s)
+        s *= int(d)
+    return tuple(out)
+
+
+def to_device(a, device="cuda"):
+    """Copy a NumPy array to the device as a first-index-fastest torch tensor."""
+    a = np.asarray(a)
+    flat = torch.from_numpy(np.ascontiguousarray(a.reshape(-1, order="F")))
+    dev = flat.to(device)
+    return dev.as_strided(tuple(a.shape), fortran_strides(a.shape))
+
+
+def empty_fortran(dims, dtype, device):
+    n = int(np.prod(dims)) if len(dims) else 1
+    flat = torch.empty(max(n, 1), dtype=dtype, device=device)
+    return flat.as_strided(tuple(int(d) for d in dims), fortran_strides(dims))
+
+
+def empty_colmajor(rows, cols, dtype, device):
+    return torch.empty((int(cols), int(rows)), dtype=dtype, device=device).t()
+
+
+def to_numpy_fortran(t):
+    """Host copy of a first-index-fastest device tensor (shape preserved)."""
+    dims = tuple(t.shape)
+    n = int(np.prod(dims))
+    flat = t.as_strided((n,), (1,)).cpu().numpy()
+    return flat.reshape(dims, order="F")
+
+
+def _check_fortran(x, dims):
+    if not x.is_cuda:
+        raise ValueError("x must be a device tensor")
+    if dims is None:
+        dims = tuple(x.shape)
+        if x.dim() > 1 and x.stride() != fortran_strides(dims) and x.numel() > 1:
+            raise ValueError("x must be first-index-fastest (Fortran strides); use to_device()")
+    else:
+        dims = tuple(int(d) for d in dims)
+        if x.numel() != int(np.prod(dims)) or not (x.is_contiguous() or x.dim() == 1):
+            raise ValueError("flat x must hold prod(dims) contiguous elements")
+    return dims
+
+
+def _stream(stream, device):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+@dataclass
+class Decomposition:
+    core: torch.Tensor
+    factors: List[torch.Tensor]
+    report_buf: torch.Tensor
+    order: int
+    _report: Optional[L.Report] = field(default=None, repr=False)
+
+    def report(self):
+        """Host copy of the device report (synchronises the device)."""
+        if self._report is None:
+            torch.cuda.synchronize(self.report_buf.device)
+            raw = self.report_buf.cpu().numpy().tobytes()
+            self._report = L.Report.from_buffer_copy(raw)
+        return self._report
+
+    @property
+    def rel_error(self):
+        return float(L.load().rhosvd_report_rel_error(ctypes.byref(self.report())))
+
+    @property
+    def norm_x2(self):
+        return self.report().norm_x2
+
+    @property
+    def norm_core2(self):
+        return self.report().norm_core2
+
+    @property
+    def flags(self):
+        return int(self.report().flags)
+
+    @property
+    def k_used(self):
+        return [int(self.report().k_used[n]) for n in range(self.order)]
+
+    def sigma(self, n):
+        r = self.factors[n].shape[1]
+        return np.array([self.report().sigma[n][i] for i in range(r)])
+
+
+class Decomposer:
+    """A reusable decomposition: validates once, owns workspace and outputs.
+
+    run() enqueues the whole pipeline on the stream and returns at once;
+    result() returns the output tensors and the report."""
+
+    def __init__(self, dims, ranks, *, algo="r_sthosvd", p=10, q=1, seed=0,
+                 dtype=torch.float32, precision=None, mode_order=None, device=None):
+        self.lib = L.load()
+        self.device = torch.device(device) if device is not None else torch.device(
+            "cuda", torch.cuda.current_device())
+        self.dev_index = self.device.index if self.device.index is not None else 0
+        self.ctx = _context(self.dev_index)
+        self.dims = tuple(int(d) for d in dims)
+        self.ranks = tuple(int(r) for r in ranks)
+        self.N = len(self.dims)
+        self.dtype = dtype
+        self._dims_c = (ctypes.c_int64 * self.N)(*self.dims)
+        self._ranks_c = (ctypes.c_int32 * self.N)(*self.ranks)
+        self._order_c = None if mode_order is None else (ctypes.c_int32 * self.N)(*mode_order)
+        self.tensor = L.Tensor(self.N, self._dims_c, _dtype_code(dtype), None)
+        algo_code = {"r_sthosvd": L.R_STHOSVD, "rp_hosvd": L.RP_HOSVD}[algo]
+        self.params = L.Params(algo_code, self._ranks_c, int(p), int(q), int(seed),
+                               self._order_c, _prec_code(precision, dtype), 0)
+        ws = ctypes.c_size_t(0)
+        L.check(self.lib.rhosvd_workspace_size(ctypes.byref(self.tensor),
+                                                ctypes.byref(self.params), ctypes.byref(ws)),
+                "rhosvd_workspace_size")
+        self.ws_bytes = int(ws.value)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.core = empty_fortran(self.ranks, dtype, self.device)
+        self.factors = [empty_colmajor(i, r, dtype, self.device) for i, r in zip(self.dims, self.ranks)]
+        self.report_buf = torch.zeros(ctypes.sizeof(L.Report), dtype=torch.uint8, device=self.device)
+        self._fac_c = (ctypes.c_void_p * self.N)(*[f.data_ptr() for f in self.factors])
+        self.out = L.Output(self.core.data_ptr(), self._fac_c, self.report_buf.data_ptr())
+
+    def run(self, x, stream=None):
+        _check_fortran(x, self.dims if x.dim() == 1 else None)
+        if x.dtype != self.dtype or x.device != self.device:
+            raise ValueError("x dtype/device differ from the planned ones")
+        self.tensor.data = x.data_ptr()
+        L.check(self.lib.rhosvd_decompose(self.ctx, ctypes.byref(self.tensor),
+                                          ctypes.byref(self.params),
+                                          ctypes.c_void_p(self.workspace.data_ptr()),
+                                          self.ws_bytes, ctypes.byref(self.out),
+                                          _stream(stream, self.device)),
+                "rhosvd_decompose")
+
+    def result(self):
+        return Decomposition(core=self.core, factors=self.factors, report_buf=self.report_buf,
+                             order=self.N)
+
+
+def decompose(x, ranks, *, algo="r_sthosvd", p=10, q=1, seed=0, precision=None,
+              mode_order=None, dims=None, stream=None):
+    """One decomposition of x (device tensor, first-index-fastest)."""
+    dims = _check_fortran(x, dims)
+    d = Decomposer(dims, ranks, algo=algo, p=p, q=q, seed=seed, dtype=x.dtype,
+                   precision=precision, mode_order=mode_order, device=x.device)
+    d.run(x, stream)
+    return d.result()
+
+
+def r_sthosvd(x, ranks, p=10, q=1, seed=0, **kw):
+    """R-STHOSVD (Algorithm 8 with Algorithm 1 per mode)."""
+    return decompose(x, ranks, algo="r_sthosvd", p=p, q=q, seed=seed, **kw)
+
+
+def rp_hosvd(x, ranks, p=10, q=0, seed=0, **kw):
+    """RP-HOSVD (Algorithm 6; the K-sized core is truncated by a small THOSVD)."""
+    return decompose(x, ranks, algo="rp_hosvd", p=p, q=q, seed=seed, **kw)
+
+
+# ---- step-level calls (one hot-path step each) -------------------------------
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(None)
+
+
+def _step_ws(I, K, J, device):
+    n = L.load().rhosvd_step_workspace_size(int(I), int(K), int(J))
+    return torch.empty(int(n), dtype=torch.uint8, device=device), int(n)
+
+
+def omega_fill(seed, mode, tag, J, K, dtype=torch.float32, device="cuda"):
+    lib = L.load()
+    dev = torch.device(device)
+    out = empty_colmajor(J, K, dtype, dev)
+    L.check(lib.rhosvd_omega_fill(_context(dev.index or 0), int(seed), int(mode), int(tag), int(J),
+                                  int(K), _dtype_code(dtype), _ptr(out), _stream(None, dev)),
+            "rhosvd_omega_fill")
+    return out
+
+
+def sketch(src, view, K, seed, mode, tag, want_norm=False):
+    """Y = S_(n) Omega for the view (L, I, T) of the flat device tensor src."""
+    lib = L.load()
+    Lv, I, T = (int(v) for v in view)
+    dev = src.device
+    y = empty_colmajor(I, K, torch.float64, dev)
+    nrm = torch.zeros(1, dtype=torch.float64, device=dev) if want_norm else None
+    ws, nb = _step_ws(I, K, Lv * T, dev)
+    L.check(lib.rhosvd_sketch(_context(dev.index or 0), _ptr(src), _dtype_code(src.dtype),
+                              _prec_code(None, src.dtype), Lv, I, T, int(K), int(seed), int(mode),
+                              int(tag), _ptr(y), _ptr(nrm), _ptr(ws), nb, _stream(None, dev)),
+            "rhosvd_sketch")
+    return y, nrm
+
+
+def power(src, view, q_mat):
+    """Y = S_(n) (S_(n)^T Q) for Q (I x K, column-major device matrix)."""
+    lib = L.load()
+    Lv, I, T = (int(v) for v in view)
+    K = int(q_mat.shape[1])
+    dev = src.device
+    qc = q_mat.t().contiguous()
+    y = empty_colmajor(I, K, torch.float64, dev)
+    ws, nb = _step_ws(I, K, Lv * T, dev)
+    L.check(lib.rhosvd_power(_context(dev.index or 0), _ptr(src), _dtype_code(src.dtype),
+                             _prec_code(None, src.dtype), Lv, I, T, K, _ptr(qc), _ptr(y), _ptr(ws),
+                             nb, _stream(None, dev)), "rhosvd_power")
+    return y
+
+
+def ttm(src, view, kout, m=None, want_gram=False, want_norm=False):
+    """out = S x_n M^T (folded), optional Gram of its unfolding and ||out||^2."""
+    lib = L.load()
+    Lv, I, T = (int(v) for v in view)
+    dev = src.device
+    mc = m.t().contiguous() if m is not None else None
+    out = torch.empty(Lv * int(kout) * T, dtype=src.dtype, device=dev)
+    gram = empty_colmajor(kout, kout, torch.float64, dev) if want_gram else None
+    nrm = torch.zeros(1, dtype=torch.float64, device=dev) if want_norm else None
+    ws, nb = _step_ws(I, kout, Lv * T, dev)
+    L.check(lib.rhosvd_ttm(_context(dev.index or 0), _ptr(src), _dtype_code(src.dtype),
+                           _prec_code(None, src.dtype), Lv, I, T, int(kout), _ptr(mc), _ptr(out),
+                           _ptr(gram), _ptr(nrm), _ptr(ws), nb, _stream(None, dev)), "rhosvd_ttm")
+    return out, gram, nrm
+
+
+def orthonormalize(y, dtype=torch.float32):
+    """Q of CholeskyQR2 for Y (I x K float64 column-major device matrix)."""
+    lib = L.load()
+    I, K = (int(v) for v in y.shape)
+    dev = y.device
+    yc = y.t().contiguous()
+    q = empty_colmajor(I, K, dtype, dev)
+    work = torch.empty(2 * I * K, dtype=torch.float64, device=dev)
+    flags = torch.zeros(1, dtype=torch.int32, device=dev)
+    L.check(lib.rhosvd_orthonormalize(_context(dev.index or 0), _ptr(yc), I, K, _dtype_code(dtype),
+                                      _ptr(q), _ptr(work), _ptr(flags), _stream(None, dev)),
+            "rhosvd_orthonormalize")
+    q64 = work[: I * K].view(K, I).t()
+    return q, q64, flags
+
+
+def sym_evd(c):
+    """Eigen-decomposition of a symmetric K x K float64 device matrix."""
+    lib = L.load()
+    K = int(c.shape[0])
+    dev = c.device
+    cc = c.t().contiguous()
+    v = empty_colmajor(K, K, torch.float64, dev)
+    lam = torch.empty(K, dtype=torch.float64, device=dev)
+    flags = torch.zeros(1, dtype=torch.int32, device=dev)
+    L.check(lib.rhosvd_sym_evd(_context(dev.index or 0), _ptr(cc), K, _ptr(v), _ptr(lam),
+                               _ptr(flags), _stream(None, dev)), "rhosvd_sym_evd")
+    return v, lam, flags

@@ -1,0 +1,710 @@
+// Host orchestrator behind the C ABI of include/rhosvd.h: validation,
+// workspace planning and the launch sequence of RP-HOSVD (Algorithm 6) and
+// R-STHOSVD (Algorithm 8 over Algorithm 1).  Nothing here computes on the
+// host; every arithmetic step is a kernel in kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "kernels.hpp"
+#include "rhosvd.h"
+
+struct rhosvd_ctx {
+    int device;
+    int num_cu;
+    size_t lds_per_block;
+};
+
+namespace {
+
+thread_local int32_t g_last_hip = 0;
+
+int32_t hip_fail(hipError_t e) {
+    g_last_hip = static_cast<int32_t>(e);
+    return RHOSVD_EHIP;
+}
+
+#define RH_HIP(call)                                  \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess) return hip_fail(e_);    \
+    } while (0)
+
+// Bump allocator over the caller's workspace; with base == nullptr it only
+// measures.
+struct Carver {
+    unsigned char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base(static_cast<unsigned char*>(b)) {}
+    template <typename P>
+    P* take(size_t bytes) {
+        off = (off + 255) & ~static_cast<size_t>(255);
+        P* p = base ? reinterpret_cast<P*>(base + off) : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+constexpr int kMaxSmallK = 64;    // CholeskyQR / Jacobi keep K x K in LDS
+constexpr int kSumsqBlocks = 256;
+
+struct Problem {
+    int N = 0;
+    int64_t dims[RHOSVD_MAX_ORDER] = {};
+    bool dbl = false;
+    size_t elem = 4;
+    int algo = 0;
+    int ranks[RHOSVD_MAX_ORDER] = {};
+    int p = 0, q = 0;
+    uint64_t seed = 0;
+    int order[RHOSVD_MAX_ORDER] = {};
+    int prec = 0;
+};
+
+struct Step {
+    int n;
+    int64_t L, I, T, J;
+    int K, R;
+    bool capped;
+    rh::StreamGeom gs, gp, gt, gtr;
+};
+
+struct Plan {
+    Problem pr;
+    Step st[RHOSVD_MAX_ORDER];
+    // RP-HOSVD core chain geometries
+    rh::StreamGeom gh[RHOSVD_MAX_ORDER];   // X..  x_n Q_n^T
+    rh::StreamGeom gg[RHOSVD_MAX_ORDER];   // Gram of H_(n) (identity TTM)
+    rh::StreamGeom gc[RHOSVD_MAX_ORDER];   // H .. x_n M_n^T
+    bool any_k_gt_r = false;
+    int64_t core_elems = 1;
+    // sizes
+    size_t part_bytes = 0;
+    int max_grid = 1;
+    int64_t maxIK = 1, maxKK = 1, maxKR = 1, maxIR = 1, maxB = 1;
+    int64_t ping = 1, pong = 1;
+    int64_t qstore = 0, mstore = 0;
+};
+
+int64_t prod(const int64_t* d, int a, int b) {
+    int64_t v = 1;
+    for (int m = a; m < b; ++m) v *= d[m];
+    return v;
+}
+
+int32_t validate(const rhosvd_tensor* x, const rhosvd_params* p, Problem* pr, bool need_data) {
+    if (!x || !p) return RHOSVD_EINVAL;
+    if (x->order < 2 || x->order > RHOSVD_MAX_ORDER || !x->dims) return RHOSVD_EINVAL;
+    if (x->dtype != RHOSVD_F32 && x->dtype != RHOSVD_F64) return RHOSVD_EINVAL;
+    if (need_data && !x->data) return RHOSVD_EINVAL;
+    if (p->algo != RHOSVD_RP_HOSVD && p->algo != RHOSVD_R_STHOSVD) return RHOSVD_EINVAL;
+    if (!p->ranks || p->oversample < 0 || p->power_iters < 0 || p->power_iters > 8)
+        return RHOSVD_EINVAL;
+    if (p->flags != 0) return RHOSVD_EINVAL;
+    pr->N = x->order;
+    pr->dbl = x->dtype == RHOSVD_F64;
+    pr->elem = pr->dbl ? sizeof(double) : sizeof(float);
+    pr->algo = p->algo;
+    pr->p = p->oversample;
+    pr->q = p->power_iters;
+    pr->seed = p->seed;
+    pr->prec = p->precision;
+    double total = 1.0;
+    for (int n = 0; n < pr->N; ++n) {
+        if (x->dims[n] < 1) return RHOSVD_EINVAL;
+        pr->dims[n] = x->dims[n];
+        total *= static_cast<double>(x->dims[n]);
+        if (p->ranks[n] < 1 || p->ranks[n] > x->dims[n]) return RHOSVD_EINVAL;
+        pr->ranks[n] = p->ranks[n];
+    }
+    if (total > 4.0e18) return RHOSVD_EINVAL;
+    if (p->mode_order) {
+        if (p->algo != RHOSVD_R_STHOSVD) return RHOSVD_EINVAL;
+        bool seen[RHOSVD_MAX_ORDER] = {};
+        for (int s = 0; s < pr->N; ++s) {
+            const int n = p->mode_order[s];
+            if (n < 0 || n >= pr->N || seen[n]) return RHOSVD_EINVAL;
+            seen[n] = true;
+            pr->order[s] = n;
+        }
+    } else {
+        for (int s = 0; s < pr->N; ++s) pr->order[s] = s;
+    }
+    if (p->precision == RHOSVD_PREC_F64) {
+        if (!pr->dbl) return RHOSVD_EINVAL;
+    } else if (p->precision == RHOSVD_PREC_F32) {
+        if (pr->dbl) return RHOSVD_EINVAL;
+    } else if (p->precision == RHOSVD_PREC_BF16) {
+        if (pr->dbl) return RHOSVD_EINVAL;
+        return RHOSVD_EUNSUPPORTED;
+    } else {
+        return RHOSVD_EINVAL;
+    }
+    return RHOSVD_OK;
+}
+
+void track_stream(Plan* pl, const rh::StreamGeom& g, bool gram) {
+    const size_t y = static_cast<size_t>(g.grid) * g.K_pad * g.I_pad * pl->pr.elem;
+    const size_t gg = gram ? static_cast<size_t>(g.grid) * g.K_pad * g.K_pad * pl->pr.elem : 0;
+    if (y > pl->part_bytes) pl->part_bytes = y;
+    if (gg > pl->part_bytes) pl->part_bytes = gg;
+    if (g.grid > pl->max_grid) pl->max_grid = g.grid;
+}
+
+int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
+    pl->pr = pr;
+    const int N = pr.N;
+    const int elem = static_cast<int>(pr.elem);
+    int64_t d[RHOSVD_MAX_ORDER];
+    for (int n = 0; n < N; ++n) d[n] = pr.dims[n];
+    if (pr.algo == RHOSVD_R_STHOSVD) {
+        for (int s = 0; s < N; ++s) {
+            Step& st = pl->st[s];
+            const int n = pr.order[s];
+            st.n = n;
+            st.L = prod(d, 0, n);
+            st.I = d[n];
+            st.T = prod(d, n + 1, N);
+            st.J = st.L * st.T;
+            st.R = pr.ranks[n];
+            if (st.R > st.J) return RHOSVD_EINVAL;
+            int64_t K = st.R + static_cast<int64_t>(pr.p);
+            st.capped = false;
+            if (K > st.I) { K = st.I; st.capped = true; }
+            if (K > st.J) { K = st.J; st.capped = true; }
+            st.K = static_cast<int>(K);
+            if (st.K > kMaxSmallK) return RHOSVD_EUNSUPPORTED;
+            if (!rh::plan_stream(rh::OP_SKETCH, elem, st.L, st.I, st.T, st.K, num_cu, &st.gs) ||
+                !rh::plan_stream(rh::OP_POWER, elem, st.L, st.I, st.T, st.K, num_cu, &st.gp) ||
+                !rh::plan_stream(rh::OP_TTM, elem, st.L, st.I, st.T, st.K, num_cu, &st.gt) ||
+                !rh::plan_stream(rh::OP_TTM, elem, st.L, st.K, st.T, st.R, num_cu, &st.gtr))
+                return RHOSVD_EUNSUPPORTED;
+            track_stream(pl, st.gs, false);
+            if (pr.q > 0) track_stream(pl, st.gp, false);
+            track_stream(pl, st.gt, true);
+            track_stream(pl, st.gtr, false);
+            const int64_t IK = st.I * st.K;
+            if (IK > pl->maxIK) pl->maxIK = IK;
+            if (static_cast<int64_t>(st.K) * st.K > pl->maxKK) pl->maxKK = static_cast<int64_t>(st.K) * st.K;
+            if (static_cast<int64_t>(st.K) * st.R > pl->maxKR) pl->maxKR = static_cast<int64_t>(st.K) * st.R;
+            if (st.I * st.R > pl->maxIR) pl->maxIR = st.I * st.R;
+            if (st.K * st.J > pl->maxB) pl->maxB = st.K * st.J;
+            d[n] = st.R;
+            if (s < N - 1) {
+                const int64_t sz = prod(d, 0, N);
+                if (s % 2 == 0) { if (sz > pl->ping) pl->ping = sz; }
+                else { if (sz > pl->pong) pl->pong = sz; }
+            }
+        }
+        pl->core_elems = prod(d, 0, N);
+        return RHOSVD_OK;
+    }
+    // RP-HOSVD: every sketch reads X
+    for (int n = 0; n < N; ++n) {
+        Step& st = pl->st[n];
+        st.n = n;
+        st.L = prod(d, 0, n);
+        st.I = d[n];
+        st.T = prod(d, n + 1, N);
+        st.J = st.L * st.T;
+        st.R = pr.ranks[n];
+        if (st.R > st.J) return RHOSVD_EINVAL;
+        int64_t K = st.R + static_cast<int64_t>(pr.p);
+        st.capped = false;
+        if (K > st.I) { K = st.I; st.capped = true; }
+        if (K > st.J) { K = st.J; st.capped = true; }
+        st.K = static_cast<int>(K);
+        if (st.K > kMaxSmallK) return RHOSVD_EUNSUPPORTED;
+        if (st.K > st.R) pl->any_k_gt_r = true;
+        if (!rh::plan_stream(rh::OP_SKETCH, elem, st.L, st.I, st.T, st.K, num_cu, &st.gs) ||
+            !rh::plan_stream(rh::OP_POWER, elem, st.L, st.I, st.T, st.K, num_cu, &st.gp))
+            return RHOSVD_EUNSUPPORTED;
+        track_stream(pl, st.gs, false);
+        if (pr.q > 0) track_stream(pl, st.gp, false);
+        const int64_t IK = st.I * st.K;
+        if (IK > pl->maxIK) pl->maxIK = IK;
+        if (static_cast<int64_t>(st.K) * st.K > pl->maxKK) pl->maxKK = static_cast<int64_t>(st.K) * st.K;
+        if (static_cast<int64_t>(st.K) * st.R > pl->maxKR) pl->maxKR = static_cast<int64_t>(st.K) * st.R;
+        if (st.I * st.R > pl->maxIR) pl->maxIR = st.I * st.R;
+        pl->qstore += IK;
+        pl->mstore += static_cast<int64_t>(st.K) * st.R;
+    }
+    // core chain H = X x_1 Q_1^T ... x_N Q_N^T, then G = H x_n M_n^T
+    int64_t buf = 1;
+    for (int n = 0; n < N; ++n) {
+        const int64_t L = prod(d, 0, n), T = prod(d, n + 1, N);
+        if (!rh::plan_stream(rh::OP_TTM, elem, L, d[n], T, pl->st[n].K, num_cu, &pl->gh[n]))
+            return RHOSVD_EUNSUPPORTED;
+        track_stream(pl, pl->gh[n], false);
+        d[n] = pl->st[n].K;
+        const int64_t sz = prod(d, 0, N);
+        if (sz > buf) buf = sz;
+    }
+    for (int n = 0; n < N; ++n) {
+        const int64_t L = prod(d, 0, n), T = prod(d, n + 1, N);
+        if (!rh::plan_stream(rh::OP_TTM, elem, L, d[n], T, d[n], num_cu, &pl->gg[n]))
+            return RHOSVD_EUNSUPPORTED;
+        track_stream(pl, pl->gg[n], true);
+    }
+    for (int n = 0; n < N; ++n) {
+        const int64_t L = prod(d, 0, n), T = prod(d, n + 1, N);
+        if (!rh::plan_stream(rh::OP_TTM, elem, L, d[n], T, pl->st[n].R, num_cu, &pl->gc[n]))
+            return RHOSVD_EUNSUPPORTED;
+        track_stream(pl, pl->gc[n], false);
+        d[n] = pl->st[n].R;
+        const int64_t sz = prod(d, 0, N);
+        if (sz > buf) buf = sz;
+    }
+    pl->ping = pl->pong = buf;
+    pl->core_elems = prod(d, 0, N);
+    return RHOSVD_OK;
+}
+
+struct Buffers {
+    rhosvd_report* rep;
+    void* part;
+    double* part_ss;
+    double* y;
+    double* q64;   // 2 maxIK doubles (q64 + work)
+    void* qT;
+    double* C;
+    double* V;
+    double* lam;
+    void* M;
+    double* u64;
+    void* B;
+    void* ping;
+    void* pong;
+    void* qstore;
+    void* mstore;
+};
+
+size_t carve(const Plan& pl, void* ws, Buffers* b) {
+    Carver cv(ws);
+    const size_t e = pl.pr.elem;
+    b->rep = cv.take<rhosvd_report>(sizeof(rhosvd_report));
+    b->part = cv.take<void>(pl.part_bytes);
+    const int ssn = pl.max_grid > kSumsqBlocks ? pl.max_grid : kSumsqBlocks;
+    b->part_ss = cv.take<double>(ssn * sizeof(double));
+    b->y = cv.take<double>(pl.maxIK * sizeof(double));
+    b->q64 = cv.take<double>(2 * pl.maxIK * sizeof(double));
+    b->qT = cv.take<void>(pl.maxIK * e);
+    b->C = cv.take<double>(pl.maxKK * sizeof(double));
+    b->V = cv.take<double>(pl.maxKK * sizeof(double));
+    b->lam = cv.take<double>(RHOSVD_MAX_K * sizeof(double));
+    b->M = cv.take<void>(pl.maxKR * e);
+    b->u64 = cv.take<double>(pl.maxIR * sizeof(double));
+    if (pl.pr.algo == RHOSVD_R_STHOSVD) {
+        b->B = cv.take<void>(pl.maxB * e);
+        b->qstore = nullptr;
+        b->mstore = nullptr;
+    } else {
+        b->B = nullptr;
+        b->qstore = cv.take<void>(pl.qstore * e);
+        b->mstore = cv.take<void>(pl.mstore * e);
+    }
+    b->ping = cv.take<void>(pl.ping * e);
+    b->pong = cv.take<void>(pl.pong * e);
+    return cv.off + 256;
+}
+
+void* at(void* base, int64_t elems, size_t elem) {
+    return static_cast<unsigned char*>(base) + static_cast<size_t>(elems) * elem;
+}
+
+// Y = S_(n) Omega, or one fused power step when mat != nullptr; then Q.
+int32_t sketch_and_orthonormalize(const Plan& pl, const Buffers& b, const void* src,
+                                  const rh::StreamGeom& gs, const rh::StreamGeom& gp, int mode,
+                                  uint32_t tag, bool want_norm, void* q_out, hipStream_t s) {
+    const bool dbl = pl.pr.dbl;
+    rh::StreamArgs a{};
+    a.src = src;
+    a.part_y = b.part;
+    a.part_ss = want_norm ? b.part_ss : nullptr;
+    a.seed = pl.pr.seed;
+    a.mode = static_cast<uint32_t>(mode);
+    a.tag = tag;
+    RH_HIP(rh::launch_stream(rh::OP_SKETCH, dbl, gs, a, s));
+    RH_HIP(rh::launch_reduce_y(dbl, b.part, gs.grid, static_cast<int>(gs.I), gs.K, gs.I_pad,
+                               gs.K_pad, b.y, s));
+    if (want_norm) RH_HIP(rh::launch_reduce_ss(b.part_ss, gs.grid, &b.rep->norm_x2, s));
+    RH_HIP(rh::launch_cqr(b.y, gs.I, gs.K, dbl, q_out, b.q64, &b.rep->flags, s));
+    for (int it = 0; it < pl.pr.q; ++it) {
+        rh::StreamArgs pa{};
+        pa.src = src;
+        pa.mat = q_out;
+        pa.part_y = b.part;
+        RH_HIP(rh::launch_stream(rh::OP_POWER, dbl, gp, pa, s));
+        RH_HIP(rh::launch_reduce_y(dbl, b.part, gp.grid, static_cast<int>(gp.I), gp.K, gp.I_pad,
+                                   gp.K_pad, b.y, s));
+        RH_HIP(rh::launch_cqr(b.y, gp.I, gp.K, dbl, q_out, b.q64, &b.rep->flags, s));
+    }
+    return RHOSVD_OK;
+}
+
+int32_t ttm(const Plan& pl, const rh::StreamGeom& g, const void* src, const void* mat, void* out,
+            void* part_g, hipStream_t s) {
+    rh::StreamArgs a{};
+    a.src = src;
+    a.mat = mat;
+    a.out = out;
+    a.part_g = part_g;
+    RH_HIP(rh::launch_stream(rh::OP_TTM, pl.pr.dbl, g, a, s));
+    return RHOSVD_OK;
+}
+
+int32_t run_r_sthosvd(const Plan& pl, const Buffers& b, const void* x, const rhosvd_output* out,
+                      hipStream_t s) {
+    const bool dbl = pl.pr.dbl;
+    const size_t e = pl.pr.elem;
+    const int N = pl.pr.N;
+    const void* src = x;
+    for (int si = 0; si < N; ++si) {
+        const Step& st = pl.st[si];
+        int32_t rc = sketch_and_orthonormalize(pl, b, src, st.gs, st.gp, st.n, 2u, si == 0, b.qT, s);
+        if (rc != RHOSVD_OK) return rc;
+        // B = Q^T S_(n), folded, and C = B B^T
+        rc = ttm(pl, st.gt, src, b.qT, b.B, b.part, s);
+        if (rc != RHOSVD_OK) return rc;
+        RH_HIP(rh::launch_gram_reduce(dbl, b.part, st.gt.grid, st.K, st.gt.K_pad, b.C, s));
+        RH_HIP(rh::launch_evd(b.C, st.K, b.V, b.lam, &b.rep->flags, s));
+        RH_HIP(rh::launch_factor(dbl, b.qT, b.V, b.lam, st.I, st.K, st.R, out->factors[st.n], b.M,
+                                 &b.rep->sigma[st.n][0], b.u64, s));
+        void* dst = (si == N - 1) ? out->core : ((si % 2 == 0) ? b.ping : b.pong);
+        rc = ttm(pl, st.gtr, b.B, b.M, dst, nullptr, s);
+        if (rc != RHOSVD_OK) return rc;
+        src = dst;
+    }
+    (void)e;
+    return RHOSVD_OK;
+}
+
+int32_t run_rp_hosvd(const Plan& pl, const Buffers& b, const void* x, const rhosvd_output* out,
+                     hipStream_t s) {
+    const bool dbl = pl.pr.dbl;
+    const size_t e = pl.pr.elem;
+    const int N = pl.pr.N;
+    int64_t qoff[RHOSVD_MAX_ORDER], moff[RHOSVD_MAX_ORDER];
+    int64_t qo = 0, mo = 0;
+    for (int n = 0; n < N; ++n) {
+        qoff[n] = qo;
+        moff[n] = mo;
+        qo += pl.st[n].I * pl.st[n].K;
+        mo += static_cast<int64_t>(pl.st[n].K) * pl.st[n].R;
+    }
+    for (int n = 0; n < N; ++n) {
+        const Step& st = pl.st[n];
+        const int32_t rc = sketch_and_orthonormalize(pl, b, x, st.gs, st.gp, n, 1u, n == 0,
+                                                     at(b.qstore, qoff[n], e), s);
+        if (rc != RHOSVD_OK) return rc;
+    }
+    // H = X x_1 Q_1^T ... x_N Q_N^T
+    const void* src = x;
+    void* bufs[2] = {b.ping, b.pong};
+    int cur = 0;
+    for (int n = 0; n < N; ++n) {
+        const int32_t rc = ttm(pl, pl.gh[n], src, at(b.qstore, qoff[n], e), bufs[cur], nullptr, s);
+        if (rc != RHOSVD_OK) return rc;
+        src = bufs[cur];
+        cur ^= 1;
+    }
+    const void* H = src;
+    void* scratch = bufs[cur];
+    // small THOSVD of H: Gram of each unfolding, EVD, factors
+    for (int n = 0; n < N; ++n) {
+        const Step& st = pl.st[n];
+        int32_t rc = ttm(pl, pl.gg[n], H, nullptr, scratch, b.part, s);
+        if (rc != RHOSVD_OK) return rc;
+        RH_HIP(rh::launch_gram_reduce(dbl, b.part, pl.gg[n].grid, st.K, pl.gg[n].K_pad, b.C, s));
+        RH_HIP(rh::launch_evd(b.C, st.K, b.V, b.lam, &b.rep->flags, s));
+        RH_HIP(rh::launch_factor(dbl, at(b.qstore, qoff[n], e), pl.any_k_gt_r ? b.V : nullptr,
+                                 b.lam, st.I, st.K, st.R, out->factors[n], at(b.mstore, moff[n], e),
+                                 &b.rep->sigma[n][0], b.u64, s));
+    }
+    // G = H x_n M_n^T
+    src = H;
+    for (int n = 0; n < N; ++n) {
+        void* dst = (n == N - 1) ? out->core : scratch;
+        const int32_t rc = ttm(pl, pl.gc[n], src, at(b.mstore, moff[n], e), dst, nullptr, s);
+        if (rc != RHOSVD_OK) return rc;
+        // alternate: the buffer just read becomes the next scratch
+        void* was = const_cast<void*>(src);
+        src = dst;
+        scratch = was;
+    }
+    return RHOSVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rhosvd_status_string(int32_t status) {
+    switch (status) {
+        case RHOSVD_OK: return "ok";
+        case RHOSVD_EINVAL: return "invalid argument";
+        case RHOSVD_ENOMEM: return "workspace too small";
+        case RHOSVD_EHIP: return "HIP runtime error";
+        case RHOSVD_ENUMERIC: return "numerical failure";
+        case RHOSVD_EBUSY: return "busy";
+        case RHOSVD_EUNSUPPORTED: return "unsupported problem size";
+        default: return "unknown status";
+    }
+}
+
+int32_t rhosvd_last_hip_error(void) { return g_last_hip; }
+
+int32_t rhosvd_create(rhosvd_ctx** ctx, int32_t device) {
+    if (!ctx) return RHOSVD_EINVAL;
+    *ctx = nullptr;
+    int count = 0;
+    RH_HIP(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return RHOSVD_EINVAL;
+    hipDeviceProp_t prop;
+    RH_HIP(hipGetDeviceProperties(&prop, device));
+    rhosvd_ctx* c = new (std::nothrow) rhosvd_ctx;
+    if (!c) return RHOSVD_ENOMEM;
+    c->device = device;
+    c->num_cu = prop.multiProcessorCount;
+    c->lds_per_block = prop.sharedMemPerBlock;
+    *ctx = c;
+    return RHOSVD_OK;
+}
+
+void rhosvd_destroy(rhosvd_ctx* ctx) { delete ctx; }
+
+static int planning_cu(const rhosvd_ctx* ctx) { return ctx ? ctx->num_cu : 256; }
+
+int32_t rhosvd_workspace_size(const rhosvd_tensor* x, const rhosvd_params* p, size_t* bytes) {
+    if (!bytes) return RHOSVD_EINVAL;
+    Problem pr;
+    int32_t rc = validate(x, p, &pr, false);
+    if (rc != RHOSVD_OK) return rc;
+    Plan* pl = new (std::nothrow) Plan;
+    if (!pl) return RHOSVD_ENOMEM;
+    rc = build_plan(pr, planning_cu(nullptr), pl);
+    if (rc == RHOSVD_OK) {
+        Buffers b;
+        *bytes = carve(*pl, nullptr, &b);
+    }
+    delete pl;
+    return rc;
+}
+
+int32_t rhosvd_decompose(rhosvd_ctx* ctx, const rhosvd_tensor* x, const rhosvd_params* p,
+                         void* workspace, size_t ws_bytes, const rhosvd_output* out,
+                         void* stream) {
+    if (!ctx || !out || !out->core || !out->factors || !workspace) return RHOSVD_EINVAL;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return RHOSVD_EINVAL;
+    Problem pr;
+    int32_t rc = validate(x, p, &pr, true);
+    if (rc != RHOSVD_OK) return rc;
+    for (int n = 0; n < pr.N; ++n)
+        if (!out->factors[n]) return RHOSVD_EINVAL;
+    Plan* pl = new (std::nothrow) Plan;
+    if (!pl) return RHOSVD_ENOMEM;
+    // the grid is planned for a 256-CU part so that the workspace size does
+    // not depend on the device the context was created on
+    rc = build_plan(pr, planning_cu(nullptr), pl);
+    if (rc != RHOSVD_OK) {
+        delete pl;
+        return rc;
+    }
+    Buffers b;
+    const size_t need = carve(*pl, nullptr, &b);
+    if (ws_bytes < need) {
+        delete pl;
+        return RHOSVD_ENOMEM;
+    }
+    carve(*pl, workspace, &b);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = -1;
+    hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess) {
+        delete pl;
+        return hip_fail(he);
+    }
+    if (dev != ctx->device) {
+        he = hipSetDevice(ctx->device);
+        if (he != hipSuccess) {
+            delete pl;
+            return hip_fail(he);
+        }
+    }
+    rh::ReportInit ri{};
+    ri.order = pr.N;
+    for (int si = 0; si < pr.N; ++si) {
+        const Step& st = pl->st[si];
+        ri.k_used[st.n] = st.capped ? -st.K : st.K;
+    }
+    rc = RHOSVD_OK;
+    he = rh::launch_report_init(b.rep, ri, s);
+    if (he != hipSuccess) rc = hip_fail(he);
+    if (rc == RHOSVD_OK)
+        rc = (pr.algo == RHOSVD_R_STHOSVD) ? run_r_sthosvd(*pl, b, x->data, out, s)
+                                            : run_rp_hosvd(*pl, b, x->data, out, s);
+    if (rc == RHOSVD_OK) {
+        he = rh::launch_sumsq(pr.dbl, out->core, pl->core_elems, b.part_ss, kSumsqBlocks, s);
+        if (he == hipSuccess) he = rh::launch_reduce_ss(b.part_ss, kSumsqBlocks, &b.rep->norm_core2, s);
+        if (he == hipSuccess && out->report)
+            he = rh::launch_copy_bytes(b.rep, out->report, sizeof(rhosvd_report), s);
+        if (he != hipSuccess) rc = hip_fail(he);
+    }
+    if (dev != ctx->device) (void)hipSetDevice(dev);
+    delete pl;
+    return rc;
+}
+
+double rhosvd_report_rel_error(const rhosvd_report* r) {
+    if (!r || !(r->norm_x2 > 0.0)) return NAN;
+    const double d = r->norm_x2 - r->norm_core2;
+    return std::sqrt((d > 0.0 ? d : 0.0) / r->norm_x2);
+}
+
+// ---- step-level entry points ----------------------------------------------
+
+size_t rhosvd_step_workspace_size(int64_t I, int32_t K, int64_t J) {
+    (void)J;
+    if (I < 1 || K < 1) return 0;
+    const size_t Ip = static_cast<size_t>((I + 15) / 16 * 16), Kp = static_cast<size_t>((K + 15) / 16 * 16);
+    const size_t G = 512;
+    const size_t big = Ip > Kp ? Ip : Kp;
+    return 256 + G * Kp * big * sizeof(double) + 256 + G * sizeof(double) + 256 +
+           kSumsqBlocks * sizeof(double) + 256;
+}
+
+static int32_t step_ws(void* ws, size_t bytes, int64_t I, int32_t K, void** part, double** ss) {
+    if (!ws || reinterpret_cast<uintptr_t>(ws) % 256 != 0) return RHOSVD_EINVAL;
+    if (bytes < rhosvd_step_workspace_size(I, K, 0)) return RHOSVD_ENOMEM;
+    Carver cv(ws);
+    const size_t Ip = static_cast<size_t>((I + 15) / 16 * 16), Kp = static_cast<size_t>((K + 15) / 16 * 16);
+    const size_t big = Ip > Kp ? Ip : Kp;
+    *part = cv.take<void>(512 * Kp * big * sizeof(double));
+    const size_t nss = 512 > kSumsqBlocks ? 512 : kSumsqBlocks;
+    *ss = cv.take<double>(nss * sizeof(double));
+    return RHOSVD_OK;
+}
+
+int32_t rhosvd_omega_fill(rhosvd_ctx* ctx, uint64_t seed, int32_t mode, int32_t tag, int64_t J,
+                          int32_t K, int32_t dtype, void* out, void* stream) {
+    if (!ctx || !out || J < 1 || K < 1 || (dtype != RHOSVD_F32 && dtype != RHOSVD_F64))
+        return RHOSVD_EINVAL;
+    RH_HIP(rh::launch_omega_fill(dtype == RHOSVD_F64, seed, mode, tag, J, K, out,
+                                 static_cast<hipStream_t>(stream)));
+    return RHOSVD_OK;
+}
+
+static int32_t check_view(int32_t dtype, int32_t precision, int64_t L, int64_t I, int64_t T,
+                          int32_t K) {
+    if (dtype != RHOSVD_F32 && dtype != RHOSVD_F64) return RHOSVD_EINVAL;
+    if (L < 1 || I < 1 || T < 1 || K < 1 || K > RHOSVD_MAX_K) return RHOSVD_EINVAL;
+    if (dtype == RHOSVD_F64 && precision != RHOSVD_PREC_F64) return RHOSVD_EINVAL;
+    if (dtype == RHOSVD_F32 && precision != RHOSVD_PREC_F32) {
+        if (precision == RHOSVD_PREC_BF16) return RHOSVD_EUNSUPPORTED;
+        return RHOSVD_EINVAL;
+    }
+    return RHOSVD_OK;
+}
+
+int32_t rhosvd_sketch(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t precision,
+                      int64_t L, int64_t I, int64_t T, int32_t K, uint64_t seed, int32_t mode,
+                      int32_t tag, double* y, double* norm2, void* workspace, size_t ws_bytes,
+                      void* stream) {
+    if (!ctx || !src || !y) return RHOSVD_EINVAL;
+    int32_t rc = check_view(dtype, precision, L, I, T, K);
+    if (rc != RHOSVD_OK) return rc;
+    rh::StreamGeom g;
+    const bool dbl = dtype == RHOSVD_F64;
+    if (!rh::plan_stream(rh::OP_SKETCH, dbl ? 8 : 4, L, I, T, K, 256, &g)) return RHOSVD_EUNSUPPORTED;
+    void* part;
+    double* ss;
+    rc = step_ws(workspace, ws_bytes, I, K, &part, &ss);
+    if (rc != RHOSVD_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rh::StreamArgs a{};
+    a.src = src;
+    a.part_y = part;
+    a.part_ss = norm2 ? ss : nullptr;
+    a.seed = seed;
+    a.mode = static_cast<uint32_t>(mode);
+    a.tag = static_cast<uint32_t>(tag);
+    RH_HIP(rh::launch_stream(rh::OP_SKETCH, dbl, g, a, s));
+    RH_HIP(rh::launch_reduce_y(dbl, part, g.grid, static_cast<int>(I), K, g.I_pad, g.K_pad, y, s));
+    if (norm2) RH_HIP(rh::launch_reduce_ss(ss, g.grid, norm2, s));
+    return RHOSVD_OK;
+}
+
+int32_t rhosvd_power(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t precision,
+                     int64_t L, int64_t I, int64_t T, int32_t K, const void* q_in, double* y,
+                     void* workspace, size_t ws_bytes, void* stream) {
+    if (!ctx || !src || !q_in || !y) return RHOSVD_EINVAL;
+    int32_t rc = check_view(dtype, precision, L, I, T, K);
+    if (rc != RHOSVD_OK) return rc;
+    rh::StreamGeom g;
+    const bool dbl = dtype == RHOSVD_F64;
+    if (!rh::plan_stream(rh::OP_POWER, dbl ? 8 : 4, L, I, T, K, 256, &g)) return RHOSVD_EUNSUPPORTED;
+    void* part;
+    double* ss;
+    rc = step_ws(workspace, ws_bytes, I, K, &part, &ss);
+    if (rc != RHOSVD_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rh::StreamArgs a{};
+    a.src = src;
+    a.mat = q_in;
+    a.part_y = part;
+    RH_HIP(rh::launch_stream(rh::OP_POWER, dbl, g, a, s));
+    RH_HIP(rh::launch_reduce_y(dbl, part, g.grid, static_cast<int>(I), K, g.I_pad, g.K_pad, y, s));
+    return RHOSVD_OK;
+}
+
+int32_t rhosvd_ttm(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t precision, int64_t L,
+                   int64_t I, int64_t T, int32_t Kout, const void* m, void* out, double* gram,
+                   double* norm2, void* workspace, size_t ws_bytes, void* stream) {
+    if (!ctx || !src || !out) return RHOSVD_EINVAL;
+    int32_t rc = check_view(dtype, precision, L, I, T, Kout);
+    if (rc != RHOSVD_OK) return rc;
+    if (!m && Kout != I) return RHOSVD_EINVAL;
+    rh::StreamGeom g;
+    const bool dbl = dtype == RHOSVD_F64;
+    if (!rh::plan_stream(rh::OP_TTM, dbl ? 8 : 4, L, I, T, Kout, 256, &g)) return RHOSVD_EUNSUPPORTED;
+    void* part;
+    double* ss;
+    rc = step_ws(workspace, ws_bytes, I, Kout, &part, &ss);
+    if (rc != RHOSVD_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rh::StreamArgs a{};
+    a.src = src;
+    a.mat = m;
+    a.out = out;
+    a.part_g = gram ? part : nullptr;
+    RH_HIP(rh::launch_stream(rh::OP_TTM, dbl, g, a, s));
+    if (gram) RH_HIP(rh::launch_gram_reduce(dbl, part, g.grid, Kout, g.K_pad, gram, s));
+    if (norm2) {
+        RH_HIP(rh::launch_sumsq(dbl, out, L * static_cast<int64_t>(Kout) * T, ss, kSumsqBlocks, s));
+        RH_HIP(rh::launch_reduce_ss(ss, kSumsqBlocks, norm2, s));
+    }
+    return RHOSVD_OK;
+}
+
+int32_t rhosvd_orthonormalize(rhosvd_ctx* ctx, const double* y, int64_t I, int32_t K,
+                              int32_t dtype, void* q_out, double* work, uint32_t* flags,
+                              void* stream) {
+    if (!ctx || !y || !q_out || !work) return RHOSVD_EINVAL;
+    if (dtype != RHOSVD_F32 && dtype != RHOSVD_F64) return RHOSVD_EINVAL;
+    if (K < 1 || I < K || I > (int64_t)1 << 30) return RHOSVD_EINVAL;
+    if (K > kMaxSmallK) return RHOSVD_EUNSUPPORTED;
+    RH_HIP(rh::launch_cqr(y, I, K, dtype == RHOSVD_F64, q_out, work, flags,
+                          static_cast<hipStream_t>(stream)));
+    return RHOSVD_OK;
+}
+
+int32_t rhosvd_sym_evd(rhosvd_ctx* ctx, const double* c, int32_t K, double* v, double* lambda,
+                       uint32_t* flags, void* stream) {
+    if (!ctx || !c || !v || !lambda || K < 1) return RHOSVD_EINVAL;
+    if (K > kMaxSmallK) return RHOSVD_EUNSUPPORTED;
+    RH_HIP(rh::launch_evd(c, K, v, lambda, flags, static_cast<hipStream_t>(stream)));
+    return RHOSVD_OK;
+}
+
+}  // extern "C"

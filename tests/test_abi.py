@@ -1,0 +1,122 @@
+"""The C ABI without a GPU: the library loads, exports every declared symbol,
+and rejects invalid problems on the host before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2001_07124_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rhosvd.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(rhosvd_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        from paper_2001_07124_amd.build import build_library
+        build_library()
+    return L.load(require_torch=True)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 14
+    assert names == L.exported_names()
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(lib):
+    assert lib.rhosvd_status_string(0) == b"ok"
+    assert lib.rhosvd_status_string(1) == b"invalid argument"
+    assert lib.rhosvd_status_string(99) == b"unknown status"
+
+
+def _problem(dims, ranks, algo=L.R_STHOSVD, p=10, q=1, dtype=L.F32, prec=L.PREC_F32, order=None,
+             flags=0):
+    d = (ctypes.c_int64 * len(dims))(*dims)
+    r = (ctypes.c_int32 * len(ranks))(*ranks)
+    o = (ctypes.c_int32 * len(order))(*order) if order is not None else None
+    t = L.Tensor(len(dims), d, dtype, None)
+    pr = L.Params(algo, r, p, q, 0, o, prec, flags)
+    return t, pr, (d, r, o)
+
+
+def _ws(lib, *a, **k):
+    t, pr, keep = _problem(*a, **k)
+    n = ctypes.c_size_t(0)
+    rc = lib.rhosvd_workspace_size(ctypes.byref(t), ctypes.byref(pr), ctypes.byref(n))
+    return rc, n.value
+
+
+def test_workspace_size_valid(lib):
+    rc, n = _ws(lib, (200, 200, 200, 200), (25, 25, 25, 25))
+    assert rc == L.OK
+    # B of mode 1 (35 x 8e6 floats) plus the 800 MB intermediate dominate
+    assert 35 * 8_000_000 * 4 + 25 * 8_000_000 * 4 < n < 3e9
+    rc, n2 = _ws(lib, (100, 100, 100), (10, 10, 10), algo=L.RP_HOSVD, p=5, q=0, dtype=L.F64,
+                 prec=L.PREC_F64)
+    assert rc == L.OK and n2 > 0
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(dims=(10, 10), ranks=(0, 3)), L.EINVAL),            # R < 1
+    (dict(dims=(10, 10), ranks=(11, 3)), L.EINVAL),           # R > I
+    (dict(dims=(10,), ranks=(3,)), L.EINVAL),                 # order 1
+    (dict(dims=(10, 0, 4), ranks=(1, 1, 1)), L.EINVAL),       # zero extent
+    (dict(dims=(10, 10), ranks=(3, 3), p=-1), L.EINVAL),
+    (dict(dims=(10, 10), ranks=(3, 3), q=9), L.EINVAL),
+    (dict(dims=(10, 10), ranks=(3, 3), order=(0, 0)), L.EINVAL),
+    (dict(dims=(10, 10), ranks=(3, 3), order=(1, 2)), L.EINVAL),
+    (dict(dims=(10, 10), ranks=(3, 3), algo=7), L.EINVAL),
+    (dict(dims=(10, 10), ranks=(3, 3), flags=1), L.EINVAL),
+    (dict(dims=(10, 10), ranks=(3, 3), dtype=L.F32, prec=L.PREC_F64), L.EINVAL),
+    (dict(dims=(10, 10), ranks=(3, 3), dtype=L.F64, prec=L.PREC_F32), L.EINVAL),
+    (dict(dims=(10, 10), ranks=(3, 3), algo=L.RP_HOSVD, order=(1, 0)), L.EINVAL),
+    (dict(dims=(40, 2, 2), ranks=(5, 2, 2)), L.EINVAL),       # R_1 = 5 > J_1 = 4
+    (dict(dims=(300, 300, 300), ranks=(100, 4, 4)), L.EUNSUPPORTED),  # K beyond the limits
+])
+def test_workspace_size_rejects(lib, kw, expect):
+    dims, ranks = kw.pop("dims"), kw.pop("ranks")
+    rc, _ = _ws(lib, dims, ranks, **kw)
+    assert rc == expect
+
+
+def test_null_arguments(lib):
+    n = ctypes.c_size_t(0)
+    assert lib.rhosvd_workspace_size(None, None, ctypes.byref(n)) == L.EINVAL
+    t, pr, keep = _problem((10, 10), (3, 3))
+    assert lib.rhosvd_workspace_size(ctypes.byref(t), ctypes.byref(pr), None) == L.EINVAL
+    assert lib.rhosvd_decompose(None, ctypes.byref(t), ctypes.byref(pr), None, 0, None, None) == L.EINVAL
+    assert lib.rhosvd_create(None, 0) == L.EINVAL
+    assert lib.rhosvd_sketch(None, None, 0, 0, 1, 1, 1, 1, 0, 0, 0, None, None, None, 0, None) == L.EINVAL
+
+
+def test_report_rel_error_host(lib):
+    r = L.Report()
+    r.norm_x2 = 4.0
+    r.norm_core2 = 3.0
+    assert abs(lib.rhosvd_report_rel_error(ctypes.byref(r)) - 0.5) < 1e-15
+    r.norm_core2 = 5.0        # rounding can push ||G|| above ||X||: clamp at 0
+    assert lib.rhosvd_report_rel_error(ctypes.byref(r)) == 0.0
+    r.norm_x2 = 0.0
+    assert np.isnan(lib.rhosvd_report_rel_error(ctypes.byref(r)))
+
+
+def test_report_layout_matches_header(lib):
+    # double, double, int32, int32[16], uint32, double[16][128]
+    assert ctypes.sizeof(L.Report) == 8 + 8 + 4 + 64 + 4 + 16 * 128 * 8
+    assert L.Report.sigma.offset == 88
+
+
+def test_binding_imports_without_gpu():
+    from paper_2001_07124_amd import api  # noqa: F401
+    assert hasattr(api, "r_sthosvd") and hasattr(api, "Decomposer")

@@ -1,0 +1,156 @@
+"""Per-step parity of the HIP kernels against the FP64 oracle (GPU only).
+
+Each step is called through the C ABI on seeded inputs that span several
+tiles and a ragged tail, and compared element by element with the oracle's
+definition of the same step:
+  Omega fill      oracle.philox.omega
+  sketch          unfold(X, n) @ omega(...)            (Algorithm 1 step 2, q = 0)
+  power step      A (A^T Q)                             (Algorithm 1 step 2, q > 0)
+  mode-n product  oracle.tensor_ops.ttm, Gram B B^T     (Algorithm 1 step 4)
+  CholeskyQR2     oracle.rsvd.qr_pos (diag(R) > 0)      (Algorithm 1 step 3)
+  Jacobi EVD      numpy.linalg.eigh                     (Algorithm 1 step 5)
+Tolerances: FP64 paths 1e-11 relative; FP32 paths are set from the
+accumulation length (J terms of fp32 products): 2e-5 of the column scale.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle import philox  # noqa: E402
+from oracle.rsvd import qr_pos  # noqa: E402
+from oracle.tensor_ops import ttm as o_ttm, unfold  # noqa: E402
+from paper_2001_07124_amd import api  # noqa: E402
+from paper_2001_07124_amd.inputs import tucker_tensor  # noqa: E402
+
+
+def _views(dims):
+    out = []
+    for n in range(len(dims)):
+        L = int(np.prod(dims[:n]))
+        T = int(np.prod(dims[n + 1:]))
+        out.append((n, (L, dims[n], T)))
+    return out
+
+
+def _flat(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x.reshape(-1, order="F").astype(dtype))).cuda()
+
+
+def _close_cols(got, want, rtol):
+    scale = np.maximum(np.max(np.abs(want), axis=0, keepdims=True), 1e-300)
+    err = np.max(np.abs(got - want) / scale)
+    assert err <= rtol, err
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("J,K", [(37, 9), (1000, 35), (4096, 16)])
+def test_omega_fill(dtype, J, K):
+    got = api.omega_fill(7, 2, 2, J, K, dtype).cpu().numpy()
+    want = philox.omega(7, 2, 2, J, K)
+    tol = 1e-12 if dtype == torch.float64 else 2e-6
+    np.testing.assert_allclose(got, want, rtol=tol, atol=tol)
+
+
+DIMS = [(37, 23, 19), (16, 9, 130), (5, 6, 7, 8), (200, 3, 70)]
+
+
+@pytest.mark.parametrize("dims", DIMS)
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_sketch(dims, dtype):
+    x, _, _ = tucker_tensor(dims, tuple(min(3, d) for d in dims), seed=21, noise=0.3, dtype=dtype)
+    src = _flat(x, dtype)
+    x64 = x.astype(np.float64)
+    for n, view in _views(dims):
+        J = view[0] * view[2]
+        K = min(11, dims[n], J)
+        y, nrm = api.sketch(src, view, K, seed=5, mode=n, tag=2, want_norm=True)
+        want = unfold(x64, n) @ philox.omega(5, n, 2, J, K)
+        tol = 1e-11 if dtype == np.float64 else 2e-5
+        _close_cols(y.cpu().numpy(), want, tol)
+        assert abs(nrm.item() - float(np.sum(x64 ** 2))) <= (1e-12 if dtype == np.float64 else 1e-6) * np.sum(x64 ** 2)
+
+
+@pytest.mark.parametrize("dims", DIMS)
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_power_step(dims, dtype):
+    x, _, _ = tucker_tensor(dims, tuple(min(3, d) for d in dims), seed=22, noise=0.3, dtype=dtype)
+    src = _flat(x, dtype)
+    x64 = x.astype(np.float64)
+    rng = np.random.default_rng(3)
+    for n, view in _views(dims):
+        K = min(10, dims[n])
+        q, _ = np.linalg.qr(rng.standard_normal((dims[n], K)))
+        q = q.astype(dtype)
+        qt = torch.from_numpy(q).cuda()
+        y = api.power(src, view, qt).cpu().numpy()
+        a = unfold(x64, n)
+        want = a @ (a.T @ q.astype(np.float64))
+        _close_cols(y, want, 1e-11 if dtype == np.float64 else 3e-5)
+
+
+@pytest.mark.parametrize("dims", DIMS)
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_ttm_and_gram(dims, dtype):
+    x, _, _ = tucker_tensor(dims, tuple(min(3, d) for d in dims), seed=23, noise=0.3, dtype=dtype)
+    src = _flat(x, dtype)
+    x64 = x.astype(np.float64)
+    rng = np.random.default_rng(4)
+    for n, view in _views(dims):
+        kout = min(13, dims[n] + 2)
+        m = rng.standard_normal((dims[n], kout)).astype(dtype)
+        out, gram, nrm = api.ttm(src, view, kout, torch.from_numpy(m).cuda(), want_gram=True,
+                                 want_norm=True)
+        want = o_ttm(x64, m.astype(np.float64).T, n)
+        got = out.cpu().numpy().reshape(want.shape, order="F")
+        tol = 1e-11 if dtype == np.float64 else 2e-5
+        _close_cols(unfold(got, n).T, unfold(want, n).T, tol)
+        b = unfold(want, n)
+        _close_cols(gram.cpu().numpy(), b @ b.T, tol)
+        assert abs(nrm.item() - float(np.sum(want ** 2))) <= tol * np.sum(want ** 2)
+    # identity operand on the smallest mode
+    n, view = min(_views(dims), key=lambda nv: nv[1][1])
+    out, _, _ = api.ttm(src, view, dims[n], None)
+    np.testing.assert_array_equal(out.cpu().numpy(), x.reshape(-1, order="F"))
+
+
+@pytest.mark.parametrize("I,K", [(200, 35), (37, 11), (500, 30), (64, 64), (15, 15)])
+def test_orthonormalize(I, K):
+    rng = np.random.default_rng(I * 100 + K)
+    y = rng.standard_normal((I, K)) @ np.diag(np.logspace(0, -3, K))
+    yt = torch.from_numpy(y).cuda()
+    q, q64, flags = api.orthonormalize(yt, torch.float32)
+    want = qr_pos(y)
+    np.testing.assert_allclose(q64.cpu().numpy(), want, atol=1e-10)
+    np.testing.assert_allclose(q.cpu().numpy(), want, atol=2e-7)
+    assert flags.item() == 0
+
+
+def test_orthonormalize_rank_deficient_shifts():
+    rng = np.random.default_rng(9)
+    base = rng.standard_normal((120, 6))
+    y = base @ rng.standard_normal((6, 20))          # rank 6, K = 20
+    q, q64, flags = api.orthonormalize(torch.from_numpy(y).cuda(), torch.float64)
+    q = q64.cpu().numpy()
+    assert flags.item() & api.L.FLAG_CQR_SHIFTED
+    assert np.linalg.norm(q.T @ q - np.eye(20), 2) <= 1e-10
+    # the range of Y is inside span(Q)
+    assert np.linalg.norm(y - q @ (q.T @ y)) <= 1e-10 * np.linalg.norm(y)
+
+
+@pytest.mark.parametrize("K", [1, 2, 7, 35, 64])
+def test_sym_evd(K):
+    rng = np.random.default_rng(K)
+    a = rng.standard_normal((K, K))
+    c = a @ a.T + np.diag(np.logspace(3, -2, K))
+    v, lam, flags = api.sym_evd(torch.from_numpy(c).cuda())
+    w, u = np.linalg.eigh(c)
+    w, u = w[::-1], u[:, ::-1]
+    np.testing.assert_allclose(lam.cpu().numpy(), w, rtol=1e-12, atol=1e-12 * w[0])
+    vv = v.cpu().numpy()
+    assert np.all(np.abs(np.abs(np.sum(vv * u, axis=0)) - 1) < 1e-9)
+    assert flags.item() == 0

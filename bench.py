@@ -91,7 +91,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="r_sthosvd_200x4_r25")
-    ap.add_argument("--precision", default=None)
+    ap.add_argument("--precision", default=None,
+                    help="bf16 (default for FP32 tensors: bf16 sketch/projection, split-bf16 power step) or f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=5)
     args = ap.parse_args()
@@ -104,7 +105,7 @@ def main():
     from paper_2001_07124_amd.inputs import WORKLOADS, tucker_tensor
 
     w = dict(WORKLOADS[args.workload])
-    prec = args.precision or w["prec"]
+    prec = args.precision or ("bf16" if w["dtype"] == np.float32 else w["prec"])
     dims, ranks = w["dims"], w["target"]
     log(f"[bench] generating {args.workload} dims={dims}")
     t0 = time.perf_counter()
@@ -116,26 +117,35 @@ def main():
     xd = api.to_device(x, dev)
     torch.cuda.synchronize()
     tt = torch.float64 if w["dtype"] == np.float64 else torch.float32
-    dec = api.Decomposer(dims, ranks, algo=w["algo"], p=w["p"], q=w["q"], seed=w["seed"],
-                         dtype=tt, precision=prec, device=dev)
-    log(f"[bench] workspace {dec.ws_bytes / 1e9:.2f} GB; warmup {args.warmup}")
-    for _ in range(args.warmup):
-        dec.run(xd)
-    torch.cuda.synchronize()
-    log(f"[bench] timing {args.steps} steps")
     stream = torch.cuda.current_stream(dev)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        dec.run(xd)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter() - t_wall
-    ms = ev0.elapsed_time(ev1) / args.steps
-    res = dec.result()
-    e_gpu = res.rel_error
+
+    def time_path(p_name, steps, warmup):
+        dec = api.Decomposer(dims, ranks, algo=w["algo"], p=w["p"], q=w["q"], seed=w["seed"],
+                             dtype=tt, precision=p_name, device=dev)
+        for _ in range(warmup):
+            dec.run(xd)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t_w = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(steps):
+            dec.run(xd)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        t_w = time.perf_counter() - t_w
+        res = dec.result()
+        return ev0.elapsed_time(ev1) / steps, res.rel_error, dec.ws_bytes, t_w
+
+    log(f"[bench] {prec} path: warmup {args.warmup}, timing {args.steps} steps")
+    ms, e_gpu, ws_bytes, t_wall = time_path(prec, args.steps, args.warmup)
+    log(f"[bench] {prec}: {ms:.3f} ms/step, E={e_gpu:.6f}")
+    compare = None
+    if prec != w["prec"]:
+        ms_ref, e_ref, _, _ = time_path(w["prec"], max(2, args.steps // 2), 1)
+        log(f"[bench] {w['prec']}: {ms_ref:.3f} ms/step, E={e_ref:.6f}")
+        compare = {"precision": w["prec"], "ms_per_step": round(ms_ref, 4),
+                   "value": round(float(np.prod(dims)) * np.dtype(w["dtype"]).itemsize / (ms_ref * 1e-3) / 1e9, 2),
+                   "rel_error": e_ref, "abs_rel_error_diff_vs_headline": abs(e_ref - e_gpu)}
     elem = np.dtype(w["dtype"]).itemsize
     tensor_bytes = float(np.prod(dims)) * elem
     value = tensor_bytes / (ms * 1e-3) / 1e9
@@ -143,49 +153,57 @@ def main():
     alg_bytes = sum(m["bytes"] for m in modes)
     alg_flops = sum(m["flops"] for m in modes)
     path_roof_ms = alg_bytes / (HBM_PEAK_GBPS * 1e9) * 1e3
-    log(f"[bench] {ms:.3f} ms/step, E={e_gpu:.6f}")
 
-    # dominant kernel: the fused power pass (or the sketch when q = 0) of the
-    # first mode, timed live through its step-level entry point with events
+    # mode-1 streaming kernels, each timed live with HIP events on the stream
+    # it is launched on, through its step-level entry point (kernel plus a
+    # small fixed-order reduction of the per-workgroup partials)
     m0 = modes[0]
     view = (1, dims[0], int(np.prod(dims[1:])))
     flat = xd.as_strided((xd.numel(),), (1,))
+    qmat = torch.linalg.qr(torch.randn(dims[0], m0["K"], dtype=torch.float64))[0].to(dev, tt)
+    kernels = {
+        "sketch": (lambda: api.sketch(flat, view, m0["K"], 0, 0, 2, precision=prec),
+                   m0["sketch_bytes"], m0["sketch_flops"]),
+        "project": (lambda: api.ttm(flat, view, m0["K"], qmat, want_gram=True, precision=prec),
+                    m0["sketch_bytes"] + elem * m0["K"] * m0["J"], 2 * m0["K"] * m0["M"]),
+    }
     if w["q"] > 0:
-        qmat = torch.linalg.qr(torch.randn(dims[0], m0["K"], dtype=torch.float64))[0].to(dev, tt)
-        fn = lambda: api.power(flat, view, qmat)  # noqa: E731
-        kb, kf, kname = m0["power_bytes"], m0["power_flops"], "k_stream<OP_POWER> (mode 1)"
-    else:
-        fn = lambda: api.sketch(flat, view, m0["K"], 0, 0, 2)  # noqa: E731
-        kb, kf, kname = m0["sketch_bytes"], m0["sketch_flops"], "k_stream<OP_SKETCH> (mode 1)"
-    fn()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.kernel_reps):
+        kernels["power"] = (lambda: api.power(flat, view, qmat, precision=prec),
+                            m0["power_bytes"], m0["power_flops"])
+    ktimes = {}
+    for name, (fn, kb, kf) in kernels.items():
         fn()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    kms = e0.elapsed_time(e1) / args.kernel_reps
-    k_gbps = kb / (kms * 1e-3) / 1e9
-    k_tflops = kf / (kms * 1e-3) / 1e12
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.kernel_reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        kms = e0.elapsed_time(e1) / args.kernel_reps
+        ktimes[name] = {"ms": round(kms, 4), "GBps": round(kb / (kms * 1e-3) / 1e9, 1),
+                        "TFLOPs": round(kf / (kms * 1e-3) / 1e12, 2), "bytes": kb, "flops": kf}
+    dom = max(ktimes, key=lambda k: ktimes[k]["ms"])
+    kd = ktimes[dom]
     peak_tf = PEAKS_TFLOPS["f64" if elem == 8 else ("bf16" if prec == "bf16" else "f32")]
-    mfma_frac = k_tflops / peak_tf
-    hbm_frac = k_gbps / HBM_PEAK_GBPS
+    mfma_frac = kd["TFLOPs"] / peak_tf
+    hbm_frac = kd["GBps"] / HBM_PEAK_GBPS
     if mfma_frac > hbm_frac:
-        roofline = {"bound": "mfma", "achieved": round(k_tflops, 3), "peak": peak_tf,
-                    "unit": "TFLOP/s", "frac": round(mfma_frac, 4), "traffic": None}
+        roofline = {"bound": "mfma", "achieved": kd["TFLOPs"], "peak": peak_tf, "unit": "TFLOP/s",
+                    "frac": round(mfma_frac, 4), "traffic": None}
     else:
-        roofline = {"bound": "hbm", "achieved": round(k_gbps, 1), "peak": HBM_PEAK_GBPS,
-                    "unit": "GB/s", "frac": round(hbm_frac, 4), "traffic": None}
-    roofline.update({"kernel": kname, "kernel_ms": round(kms, 4),
-                     "algorithmic_bytes": kb, "algorithmic_flops": kf})
+        roofline = {"bound": "hbm", "achieved": kd["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                    "frac": round(hbm_frac, 4), "traffic": None}
+    roofline.update({"kernel": f"mode-1 {dom} pass ({prec})", "kernel_ms": kd["ms"],
+                     "algorithmic_bytes": kd["bytes"], "algorithmic_flops": kd["flops"],
+                     "mode1_kernels": ktimes})
 
     out = {
         "metric": "R-STHOSVD tensor GB/s (% HBM roofline) at 1e-3 rel err",
         "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": {"f32": "f32", "f64": "f64", "bf16": "bf16"}[prec], "data": "synthetic",
+        "dtype": prec, "data": "synthetic",
         "config": {"workload": args.workload, "dims": list(dims), "ranks": list(ranks),
                    "p": w["p"], "q": w["q"], "precision": prec, "algo": w["algo"]},
         "rel_error": e_gpu,
@@ -194,8 +212,10 @@ def main():
         "path": {"algorithmic_bytes": alg_bytes, "algorithmic_flops": alg_flops,
                  "algorithmic_GBps": round(alg_bytes / (ms * 1e-3) / 1e9, 1),
                  "hbm_roofline_ms": round(path_roof_ms, 4),
-                 "hbm_roofline_frac": round(path_roof_ms / ms, 4)},
+                 "hbm_roofline_frac": round(path_roof_ms / ms, 4),
+                 "workspace_bytes": ws_bytes},
         "roofline": roofline,
+        "compare_path": compare,
         "wall_s_timed": round(t_wall, 3),
     }
     if not args.no_cpu_baseline:

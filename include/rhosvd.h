@@ -194,7 +194,8 @@ int32_t rhosvd_orthonormalize(rhosvd_ctx* ctx, const double* y, int64_t I, int32
 /* Symmetric eigen-decomposition C = V diag(lambda) V^T of a K x K matrix
  * (device double, column-major) by cyclic Jacobi in FP64, eigenvalues sorted
  * descending (Algorithm 1 step 5 through the Gram of B).  v: K x K double,
- * lambda: K doubles (device).  flags as above (RHOSVD_FLAG_EVD_NOCONV). */
+ * lambda: K doubles (device).  flags as above (RHOSVD_FLAG_EVD_NOCONV); bits
+ * 16..23 receive the number of Jacobi sweeps performed.  K <= 64. */
 int32_t rhosvd_sym_evd(rhosvd_ctx* ctx, const double* c, int32_t K, double* v,
                        double* lambda, uint32_t* flags, void* stream);
 

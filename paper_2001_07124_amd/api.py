@@ -235,7 +235,7 @@ def omega_fill(seed, mode, tag, J, K, dtype=torch.float32, device="cuda"):
     return out
 
 
-def sketch(src, view, K, seed, mode, tag, want_norm=False):
+def sketch(src, view, K, seed, mode, tag, want_norm=False, precision=None):
     """Y = S_(n) Omega for the view (L, I, T) of the flat device tensor src."""
     lib = L.load()
     Lv, I, T = (int(v) for v in view)
@@ -244,13 +244,13 @@ def sketch(src, view, K, seed, mode, tag, want_norm=False):
     nrm = torch.zeros(1, dtype=torch.float64, device=dev) if want_norm else None
     ws, nb = _step_ws(I, K, Lv * T, dev)
     L.check(lib.rhosvd_sketch(_context(dev.index or 0), _ptr(src), _dtype_code(src.dtype),
-                              _prec_code(None, src.dtype), Lv, I, T, int(K), int(seed), int(mode),
+                              _prec_code(precision, src.dtype), Lv, I, T, int(K), int(seed), int(mode),
                               int(tag), _ptr(y), _ptr(nrm), _ptr(ws), nb, _stream(None, dev)),
             "rhosvd_sketch")
     return y, nrm
 
 
-def power(src, view, q_mat):
+def power(src, view, q_mat, precision=None):
     """Y = S_(n) (S_(n)^T Q) for Q (I x K, column-major device matrix)."""
     lib = L.load()
     Lv, I, T = (int(v) for v in view)
@@ -260,12 +260,12 @@ def power(src, view, q_mat):
     y = empty_colmajor(I, K, torch.float64, dev)
     ws, nb = _step_ws(I, K, Lv * T, dev)
     L.check(lib.rhosvd_power(_context(dev.index or 0), _ptr(src), _dtype_code(src.dtype),
-                             _prec_code(None, src.dtype), Lv, I, T, K, _ptr(qc), _ptr(y), _ptr(ws),
+                             _prec_code(precision, src.dtype), Lv, I, T, K, _ptr(qc), _ptr(y), _ptr(ws),
                              nb, _stream(None, dev)), "rhosvd_power")
     return y
 
 
-def ttm(src, view, kout, m=None, want_gram=False, want_norm=False):
+def ttm(src, view, kout, m=None, want_gram=False, want_norm=False, precision=None):
     """out = S x_n M^T (folded), optional Gram of its unfolding and ||out||^2."""
     lib = L.load()
     Lv, I, T = (int(v) for v in view)
@@ -276,7 +276,7 @@ def ttm(src, view, kout, m=None, want_gram=False, want_norm=False):
     nrm = torch.zeros(1, dtype=torch.float64, device=dev) if want_norm else None
     ws, nb = _step_ws(I, kout, Lv * T, dev)
     L.check(lib.rhosvd_ttm(_context(dev.index or 0), _ptr(src), _dtype_code(src.dtype),
-                           _prec_code(None, src.dtype), Lv, I, T, int(kout), _ptr(mc), _ptr(out),
+                           _prec_code(precision, src.dtype), Lv, I, T, int(kout), _ptr(mc), _ptr(out),
                            _ptr(gram), _ptr(nrm), _ptr(ws), nb, _stream(None, dev)), "rhosvd_ttm")
     return out, gram, nrm
 

@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librhosvd.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "rhosvd_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "kernels_wave.hip", "kernels_small.hip", "rhosvd_api.hip")]
 ARCH = os.environ.get("RHOSVD_ARCH", "gfx950")
 
 

@@ -9,6 +9,10 @@ namespace rh {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;          // 4 waves per workgroup for every streaming kernel
+// LDS per workgroup on gfx950 and the room kept for a kernel's static
+// __shared__ arrays on top of a dynamic request (checked on the host).
+constexpr size_t kLdsLimit = 160 * 1024;
+constexpr size_t kStaticLdsMargin = 12 * 1024;
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of
@@ -40,12 +44,12 @@ __device__ __forceinline__ float uniform01f(uint32_t x) {
 }
 
 // Box-Muller on two uniforms: (r cos 2 pi u1, r sin 2 pi u1), r = sqrt(-2 ln u0).
+// The FP32 form uses the hardware sine/cosine, whose argument is in
+// revolutions, so 2 pi u1 is never rounded.
 __device__ __forceinline__ void box_muller(float u0, float u1, float& z0, float& z1) {
     const float r = sqrtf(-2.0f * logf(u0));
-    float s, c;
-    sincospif(2.0f * u1, &s, &c);
-    z0 = r * c;
-    z1 = r * s;
+    z0 = r * __builtin_amdgcn_cosf(u1);
+    z1 = r * __builtin_amdgcn_sinf(u1);
 }
 __device__ __forceinline__ void box_muller(double u0, double u1, double& z0, double& z1) {
     const double r = sqrt(-2.0 * log(u0));

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"
+#include "householder.hpp"
 #include "kernels.hpp"
 #include "rhosvd.h"
 
@@ -318,39 +319,8 @@ hipError_t launch_stream(int op, bool dbl, const StreamGeom& g, const StreamArgs
 }
 
 // ---------------------------------------------------------------------------
-// Fixed-order reductions of the per-workgroup partials (deterministic).
+// Fixed-order reduction of per-workgroup sums of squares.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void k_reduce_y(const T* __restrict__ part, int G, int I, int K, int I_pad, int K_pad,
-                           double* __restrict__ y) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= I * K) return;
-    const int k = e / I, i = e - k * I;
-    const size_t stride = static_cast<size_t>(K_pad) * I_pad;
-    const T* p = part + static_cast<size_t>(k) * I_pad + i;
-    double s = 0.0;
-    for (int gi = 0; gi < G; ++gi) s += static_cast<double>(p[gi * stride]);
-    y[e] = s;
-}
-
-hipError_t launch_reduce_y(bool dbl, const void* part, int G, int I, int K, int I_pad, int K_pad,
-                           double* y, hipStream_t s) {
-    const int n = I * K;
-    const dim3 grid((n + kBlock - 1) / kBlock);
-    if (dbl)
-        hipLaunchKernelGGL(k_reduce_y<double>, grid, dim3(kBlock), 0, s,
-                           static_cast<const double*>(part), G, I, K, I_pad, K_pad, y);
-    else
-        hipLaunchKernelGGL(k_reduce_y<float>, grid, dim3(kBlock), 0, s,
-                           static_cast<const float*>(part), G, I, K, I_pad, K_pad, y);
-    return hipGetLastError();
-}
-
-hipError_t launch_gram_reduce(bool dbl, const void* part, int G, int K, int K_pad, double* c,
-                              hipStream_t s) {
-    return launch_reduce_y(dbl, part, G, K, K, K_pad, K_pad, c, s);
-}
-
 __global__ void k_reduce_ss(const double* __restrict__ part, int G, double* __restrict__ out) {
     __shared__ double red[kBlock];
     double s = 0.0;
@@ -521,70 +491,6 @@ __device__ void cqr_apply(const double* __restrict__ src, int I, int K, const do
     __syncthreads();
 }
 
-// Householder QR of Y (I x K) into Q (I x K), columns signed so that
-// diag(R) >= 0.  Used when CholeskyQR breaks down even after the shift,
-// i.e. when Y is numerically rank deficient (exact-rank data with p > 0).
-__device__ void householder_qr(const double* __restrict__ y, int I, int K, double* A, double* Q,
-                               double* tau_s, double* alpha_s, double* red) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int e = tid; e < I * K; e += kBlock) A[e] = y[e];
-    __syncthreads();
-    for (int j = 0; j < K; ++j) {
-        double s = 0.0;
-        for (int i = j + tid; i < I; i += kBlock) {
-            const double v = A[static_cast<int64_t>(j) * I + i];
-            s += v * v;
-        }
-        s = wave_sum(s);
-        if (lane == 0) red[wave] = s;
-        __syncthreads();
-        if (tid == 0) {
-            double n2 = 0.0;
-            for (int w = 0; w < kBlock / kWave; ++w) n2 += red[w];
-            const double a = A[static_cast<int64_t>(j) * I + j];
-            const double alpha = (a > 0.0 ? -1.0 : 1.0) * sqrt(n2);
-            const double v0 = a - alpha;
-            const double vn2 = n2 - a * a + v0 * v0;
-            A[static_cast<int64_t>(j) * I + j] = v0;
-            tau_s[j] = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
-            alpha_s[j] = alpha;
-        }
-        __syncthreads();
-        const double tau = tau_s[j];
-        for (int c = j + 1 + wave; c < K; c += kBlock / kWave) {
-            double w = 0.0;
-            for (int i = j + lane; i < I; i += kWave)
-                w += A[static_cast<int64_t>(j) * I + i] * A[static_cast<int64_t>(c) * I + i];
-            w = wave_sum(w);
-            for (int i = j + lane; i < I; i += kWave)
-                A[static_cast<int64_t>(c) * I + i] -= tau * A[static_cast<int64_t>(j) * I + i] * w;
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < I * K; e += kBlock) {
-        const int c = e / I, i = e - c * I;
-        Q[e] = (i == c) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    for (int j = K - 1; j >= 0; --j) {
-        const double tau = tau_s[j];
-        for (int c = wave; c < K; c += kBlock / kWave) {
-            double w = 0.0;
-            for (int i = j + lane; i < I; i += kWave)
-                w += A[static_cast<int64_t>(j) * I + i] * Q[static_cast<int64_t>(c) * I + i];
-            w = wave_sum(w);
-            for (int i = j + lane; i < I; i += kWave)
-                Q[static_cast<int64_t>(c) * I + i] -= tau * A[static_cast<int64_t>(j) * I + i] * w;
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < I * K; e += kBlock) {
-        const int c = e / I;
-        if (alpha_s[c] < 0.0) Q[e] = -Q[e];
-    }
-    __syncthreads();
-}
-
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cqr(const double* __restrict__ y, int I, int K,
                                                 double* work, double* q64, T* q_out,
@@ -641,213 +547,19 @@ __global__ __launch_bounds__(kBlock) void k_cqr(const double* __restrict__ y, in
     for (int e = threadIdx.x; e < I * K; e += kBlock) q_out[e] = static_cast<T>(q64[e]);
 }
 
-hipError_t launch_cqr(const double* y, int64_t I, int K, bool dbl, void* q_out, double* q64,
-                      uint32_t* flags, hipStream_t s) {
+hipError_t launch_cqr_global(const double* y, int64_t I, int K, bool dbl, void* q_out,
+                             double* q64, uint32_t* flags, hipStream_t s) {
     // work buffer lives right after q64 (the caller reserves 2 I K doubles)
     double* work = q64 + I * K;
     const size_t lds = (2 * static_cast<size_t>(K) * K + static_cast<size_t>(K) * (kCqrRows + 1)) *
                        sizeof(double);
+    if (lds + kStaticLdsMargin > kLdsLimit) return hipErrorInvalidValue;
     if (dbl)
         hipLaunchKernelGGL(k_cqr<double>, dim3(1), dim3(kBlock), lds, s, y, static_cast<int>(I), K,
                            work, q64, static_cast<double*>(q_out), flags);
     else
         hipLaunchKernelGGL(k_cqr<float>, dim3(1), dim3(kBlock), lds, s, y, static_cast<int>(I), K,
                            work, q64, static_cast<float*>(q_out), flags);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Symmetric eigen-decomposition by cyclic Jacobi with the round-robin
-// parallel ordering; rotations as in Golub & Van Loan (sym.schur2).  One
-// workgroup, A and V held in LDS (row-major, Ke = K rounded up to even).
-// ---------------------------------------------------------------------------
-constexpr int kMaxSweeps = 30;
-
-__global__ __launch_bounds__(kBlock) void k_evd(const double* __restrict__ cin, int K,
-                                                double* __restrict__ vout,
-                                                double* __restrict__ lam, uint32_t* flags) {
-    extern __shared__ __align__(16) double shd[];
-    const int Ke = K + (K & 1);
-    double* A = shd;
-    double* V = A + Ke * Ke;
-    __shared__ double cs[RHOSVD_MAX_K / 2], sn[RHOSVD_MAX_K / 2];
-    __shared__ int pp[RHOSVD_MAX_K / 2], qq[RHOSVD_MAX_K / 2];
-    __shared__ double red[2][kBlock / kWave];
-    __shared__ int converged;
-    const int tid = threadIdx.x;
-    for (int e = tid; e < Ke * Ke; e += kBlock) {
-        const int r = e / Ke, c = e - r * Ke;
-        A[e] = (r < K && c < K) ? cin[c * K + r] : 0.0;
-        V[e] = (r == c) ? 1.0 : 0.0;
-    }
-    if (tid == 0) converged = 0;
-    __syncthreads();
-    const int half = Ke / 2;
-    for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int e = tid; e < Ke * Ke; e += kBlock) {
-            const int r = e / Ke, c = e - r * Ke;
-            const double v = A[e] * A[e];
-            tot += v;
-            if (r != c) off += v;
-        }
-        off = wave_sum(off);
-        tot = wave_sum(tot);
-        if ((tid & 63) == 0) {
-            red[0][tid >> 6] = off;
-            red[1][tid >> 6] = tot;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double o = 0.0, t = 0.0;
-            for (int w = 0; w < kBlock / kWave; ++w) {
-                o += red[0][w];
-                t += red[1][w];
-            }
-            converged = (o <= 1e-30 * t) ? 1 : 0;
-        }
-        __syncthreads();
-        if (converged) break;
-        for (int round = 0; round < Ke - 1; ++round) {
-            if (tid < half) {
-                const int m = tid;
-                const int a0 = (m == 0) ? 0 : 1 + ((m - 1 + round) % (Ke - 1));
-                const int mm = Ke - 1 - m;
-                const int a1 = 1 + ((mm - 1 + round) % (Ke - 1));
-                const int p = a0 < a1 ? a0 : a1;
-                const int q = a0 < a1 ? a1 : a0;
-                const double apq = A[p * Ke + q];
-                double c = 1.0, s = 0.0;
-                if (apq != 0.0) {
-                    const double tau = (A[q * Ke + q] - A[p * Ke + p]) / (2.0 * apq);
-                    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + t * t);
-                    s = t * c;
-                }
-                pp[m] = p;
-                qq[m] = q;
-                cs[m] = c;
-                sn[m] = s;
-            }
-            __syncthreads();
-            for (int e = tid; e < half * Ke; e += kBlock) {
-                const int m = e / Ke, j = e - m * Ke;
-                const int p = pp[m], q = qq[m];
-                const double c = cs[m], s = sn[m];
-                const double ap = A[p * Ke + j], aq = A[q * Ke + j];
-                A[p * Ke + j] = c * ap - s * aq;
-                A[q * Ke + j] = s * ap + c * aq;
-            }
-            __syncthreads();
-            for (int e = tid; e < half * Ke; e += kBlock) {
-                const int m = e / Ke, j = e - m * Ke;
-                const int p = pp[m], q = qq[m];
-                const double c = cs[m], s = sn[m];
-                const double ap = A[j * Ke + p], aq = A[j * Ke + q];
-                A[j * Ke + p] = c * ap - s * aq;
-                A[j * Ke + q] = s * ap + c * aq;
-                const double vp = V[j * Ke + p], vq = V[j * Ke + q];
-                V[j * Ke + p] = c * vp - s * vq;
-                V[j * Ke + q] = s * vp + c * vq;
-            }
-            __syncthreads();
-        }
-    }
-    if (tid == 0 && !converged && flags) atomicOr(flags, RHOSVD_FLAG_EVD_NOCONV);
-    // sort descending (stable on ties by index)
-    for (int i = tid; i < K; i += kBlock) {
-        const double li = A[i * Ke + i];
-        int rank = 0;
-        for (int j = 0; j < K; ++j) {
-            const double lj = A[j * Ke + j];
-            rank += (lj > li) || (lj == li && j < i);
-        }
-        lam[rank] = li;
-        for (int k = 0; k < K; ++k) vout[rank * K + k] = V[k * Ke + i];
-    }
-}
-
-hipError_t launch_evd(const double* c, int K, double* v, double* lambda, uint32_t* flags,
-                      hipStream_t s) {
-    const int Ke = K + (K & 1);
-    const size_t lds = 2 * static_cast<size_t>(Ke) * Ke * sizeof(double);
-    hipLaunchKernelGGL(k_evd, dim3(1), dim3(kBlock), lds, s, c, K, v, lambda, flags);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// U = Q V[:, :R] in FP64, canonical column signs (largest |entry| positive,
-// lowest row on ties), M = V[:, :R] diag(s), sigma = sqrt(max(lambda, 0)).
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_factor(const T* __restrict__ q,
-                                                   const double* __restrict__ v,
-                                                   const double* __restrict__ lam, int I, int K,
-                                                   int R, T* __restrict__ u_out,
-                                                   T* __restrict__ m_out,
-                                                   double* __restrict__ sigma,
-                                                   double* __restrict__ u64) {
-    __shared__ double sgn[RHOSVD_MAX_K];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int e = tid; e < I * R; e += kBlock) {
-        const int r = e / I, i = e - r * I;
-        double s = 0.0;
-        if (v) {
-            for (int k = 0; k < K; ++k)
-                s += static_cast<double>(q[static_cast<int64_t>(k) * I + i]) * v[r * K + k];
-        } else {
-            s = static_cast<double>(q[static_cast<int64_t>(r) * I + i]);
-        }
-        u64[e] = s;
-    }
-    __syncthreads();
-    for (int r = wave; r < R; r += kBlock / kWave) {
-        double best = -1.0;
-        int bi = 0x7fffffff;
-        for (int i = lane; i < I; i += kWave) {
-            const double a = fabs(u64[static_cast<int64_t>(r) * I + i]);
-            if (a > best) {
-                best = a;
-                bi = i;
-            }
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const double ob = __shfl_xor(best, o, kWave);
-            const int oi = __shfl_xor(bi, o, kWave);
-            if (ob > best || (ob == best && oi < bi)) {
-                best = ob;
-                bi = oi;
-            }
-        }
-        if (lane == 0) sgn[r] = (u64[static_cast<int64_t>(r) * I + bi] < 0.0) ? -1.0 : 1.0;
-    }
-    __syncthreads();
-    for (int e = tid; e < I * R; e += kBlock) {
-        const int r = e / I;
-        u_out[e] = static_cast<T>(sgn[r] * u64[e]);
-    }
-    for (int e = tid; e < K * R; e += kBlock) {
-        const int r = e / K, k = e - r * K;
-        const double vv = v ? v[r * K + k] : (k == r ? 1.0 : 0.0);
-        m_out[e] = static_cast<T>(sgn[r] * vv);
-    }
-    if (sigma && lam)
-        for (int r = tid; r < R; r += kBlock) sigma[r] = sqrt(fmax(lam[r], 0.0));
-}
-
-hipError_t launch_factor(bool dbl, const void* q, const double* v, const double* lambda, int64_t I,
-                         int K, int R, void* u_out, void* m_out, double* sigma_out, double* u64,
-                         hipStream_t s) {
-    if (dbl)
-        hipLaunchKernelGGL(k_factor<double>, dim3(1), dim3(kBlock), 0, s,
-                           static_cast<const double*>(q), v, lambda, static_cast<int>(I), K, R,
-                           static_cast<double*>(u_out), static_cast<double*>(m_out), sigma_out,
-                           u64);
-    else
-        hipLaunchKernelGGL(k_factor<float>, dim3(1), dim3(kBlock), 0, s,
-                           static_cast<const float*>(q), v, lambda, static_cast<int>(I), K, R,
-                           static_cast<float*>(u_out), static_cast<float*>(m_out), sigma_out, u64);
     return hipGetLastError();
 }
 

@@ -42,24 +42,52 @@ bool plan_stream(int op, int elem, int64_t L, int64_t I, int64_t T, int K, int n
 hipError_t launch_stream(int op, bool dbl, const StreamGeom& g, const StreamArgs& a,
                          hipStream_t s);
 
+// Matrix-core input precision of the wave-private FP32 kernels.
+enum CompType { CT_F32 = 0, CT_BF16 = 1, CT_BF16X3 = 2, CT_BF16X2 = 3 };
+
+// Geometry of a wave-private pass (kernels_wave.hip): each wave owns blocks
+// of 16 unfolding columns; IB = ceil(I / 16) row blocks, NB = ceil(K / 16)
+// column blocks of the K-wide operand.
+struct WGeom {
+    int64_t L, I, T, J;
+    int K, IB, NB, ct, variant;
+    size_t q_bytes, scr_bytes, lds_bytes;
+    int64_t nblocks;
+    int grid;
+    int vec4;             // L == 1 and I % 4 == 0: 16-byte row loads
+};
+
+bool plan_wave(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu, WGeom* g);
+hipError_t launch_wave(int op, const WGeom& g, const StreamArgs& a, hipStream_t s);
+
 // Fixed-order reductions of per-workgroup partials.
 hipError_t launch_reduce_y(bool dbl, const void* part, int G, int I, int K, int I_pad, int K_pad,
                            double* y, hipStream_t s);
 hipError_t launch_reduce_ss(const double* part, int G, double* out, hipStream_t s);
 
-// CholeskyQR2 (shifted CholeskyQR3 when needed).  y is I x K double; work is
-// I x K double scratch; q64 (may equal work) and q_out receive Q.
+// CholeskyQR2 (shifted CholeskyQR3 when needed, Householder fallback).  y is
+// I x K double; q64 points at 2 I K doubles (Q in FP64, then scratch); q_out
+// receives Q in the tensor's precision.  Y is staged in LDS when it fits
+// (kernels_small.hip), else the global-memory kernel (kernels.hip) runs.
 hipError_t launch_cqr(const double* y, int64_t I, int K, bool dbl, void* q_out, double* q64,
                       uint32_t* flags, hipStream_t s);
+hipError_t launch_cqr_lds(const double* y, int64_t I, int K, bool dbl, void* q_out, double* q64,
+                          uint32_t* flags, hipStream_t s);
+hipError_t launch_cqr_global(const double* y, int64_t I, int K, bool dbl, void* q_out,
+                             double* q64, uint32_t* flags, hipStream_t s);
+size_t cqr_lds_bytes(int64_t I, int K);
 
+// Jacobi EVD of the K x K Gram (sorted descending) fused with the factor
+// step: U = Q V[:, :R] (identity V when use_v == 0), canonical signs,
+// M = V_R diag(s), sigma = sqrt(max(lambda, 0))[:R].  q == nullptr: EVD only
+// (v_out, lam_out).
+hipError_t launch_evd_factor(bool dbl, const double* c, int K, double* v_out, double* lam_out,
+                             uint32_t* flags, const void* q, int64_t I, int R, int use_v,
+                             void* u_out, void* m_out, double* sigma, double* u64, hipStream_t s);
 hipError_t launch_evd(const double* c, int K, double* v, double* lambda, uint32_t* flags,
                       hipStream_t s);
-
-// U = Q V[:, :R] (V == nullptr means identity), canonical signs, M = V[:, :R] diag(s),
-// sigma = sqrt(max(lambda, 0))[:R] (lambda may be nullptr).
-hipError_t launch_factor(bool dbl, const void* q, const double* v, const double* lambda, int64_t I,
-                         int K, int R, void* u_out, void* m_out, double* sigma_out, double* u64,
-                         hipStream_t s);
+hipError_t launch_reduce_parts(bool dbl, const void* part, int G, int I, int K, int I_pad,
+                               int K_pad, double* y, hipStream_t s);
 
 hipError_t launch_sumsq(bool dbl, const void* x, int64_t n, double* part, int G, hipStream_t s);
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "kernels.hpp"
@@ -49,6 +50,44 @@ struct Carver {
 constexpr int kMaxSmallK = 64;    // CholeskyQR / Jacobi keep K x K in LDS
 constexpr int kSumsqBlocks = 256;
 
+// One streaming pass: the wave-private kernel when the shape fits it (FP32
+// data), the workgroup-tiled kernel otherwise (always for FP64 data).
+struct Pass {
+    int op = 0;
+    bool wave = false;
+    bool dbl = false;
+    rh::StreamGeom sg{};
+    rh::WGeom wg{};
+    int grid = 0, I_pad = 0, K_pad = 0, K = 0;
+    int64_t I = 0;
+};
+
+bool plan_pass(int op, bool dbl, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu,
+               Pass* p) {
+    p->op = op;
+    p->dbl = dbl;
+    p->I = I;
+    p->K = K;
+    if (!dbl && std::getenv("RHOSVD_FORCE_TILED") == nullptr &&
+        rh::plan_wave(op, ct, L, I, T, K, num_cu, &p->wg)) {
+        p->wave = true;
+        p->grid = p->wg.grid;
+        p->I_pad = p->wg.IB * 16;
+        p->K_pad = p->wg.NB * 16;
+        return true;
+    }
+    p->wave = false;
+    if (!rh::plan_stream(op, dbl ? 8 : 4, L, I, T, K, num_cu, &p->sg)) return false;
+    p->grid = p->sg.grid;
+    p->I_pad = p->sg.I_pad;
+    p->K_pad = p->sg.K_pad;
+    return true;
+}
+
+hipError_t launch_pass(const Pass& p, const rh::StreamArgs& a, hipStream_t s) {
+    return p.wave ? rh::launch_wave(p.op, p.wg, a, s) : rh::launch_stream(p.op, p.dbl, p.sg, a, s);
+}
+
 struct Problem {
     int N = 0;
     int64_t dims[RHOSVD_MAX_ORDER] = {};
@@ -60,6 +99,7 @@ struct Problem {
     uint64_t seed = 0;
     int order[RHOSVD_MAX_ORDER] = {};
     int prec = 0;
+    int ct_sketch = 0, ct_power = 0, ct_ttm = 0, ct_trunc = 0;
 };
 
 struct Step {
@@ -67,16 +107,16 @@ struct Step {
     int64_t L, I, T, J;
     int K, R;
     bool capped;
-    rh::StreamGeom gs, gp, gt, gtr;
+    Pass gs, gp, gt, gtr;
 };
 
 struct Plan {
     Problem pr;
     Step st[RHOSVD_MAX_ORDER];
     // RP-HOSVD core chain geometries
-    rh::StreamGeom gh[RHOSVD_MAX_ORDER];   // X..  x_n Q_n^T
-    rh::StreamGeom gg[RHOSVD_MAX_ORDER];   // Gram of H_(n) (identity TTM)
-    rh::StreamGeom gc[RHOSVD_MAX_ORDER];   // H .. x_n M_n^T
+    Pass gh[RHOSVD_MAX_ORDER];   // X..  x_n Q_n^T
+    Pass gg[RHOSVD_MAX_ORDER];   // Gram of H_(n) (identity TTM)
+    Pass gc[RHOSVD_MAX_ORDER];   // H .. x_n M_n^T
     bool any_k_gt_r = false;
     int64_t core_elems = 1;
     // sizes
@@ -137,14 +177,25 @@ int32_t validate(const rhosvd_tensor* x, const rhosvd_params* p, Problem* pr, bo
         if (pr->dbl) return RHOSVD_EINVAL;
     } else if (p->precision == RHOSVD_PREC_BF16) {
         if (pr->dbl) return RHOSVD_EINVAL;
-        return RHOSVD_EUNSUPPORTED;
+        pr->ct_sketch = rh::CT_BF16;
+        pr->ct_power = rh::CT_BF16X3;
+        pr->ct_ttm = rh::CT_BF16X3;
+        pr->ct_trunc = rh::CT_BF16X3;
     } else {
         return RHOSVD_EINVAL;
+    }
+    // experiment knobs: per-pass matrix-core precision (0 f32, 1 bf16, 2 split
+    // bf16 on both sides, 3 bf16 tensor with a split operand)
+    const char* names[4] = {"RHOSVD_CT_SKETCH", "RHOSVD_CT_POWER", "RHOSVD_CT_PROJECT", "RHOSVD_CT_TRUNC"};
+    int* dst[4] = {&pr->ct_sketch, &pr->ct_power, &pr->ct_ttm, &pr->ct_trunc};
+    for (int k = 0; k < 4; ++k) {
+        const char* v = pr->dbl ? nullptr : std::getenv(names[k]);
+        if (v && v[0] >= '0' && v[0] <= '3' && v[1] == 0) *dst[k] = v[0] - '0';
     }
     return RHOSVD_OK;
 }
 
-void track_stream(Plan* pl, const rh::StreamGeom& g, bool gram) {
+void track_stream(Plan* pl, const Pass& g, bool gram) {
     const size_t y = static_cast<size_t>(g.grid) * g.K_pad * g.I_pad * pl->pr.elem;
     const size_t gg = gram ? static_cast<size_t>(g.grid) * g.K_pad * g.K_pad * pl->pr.elem : 0;
     if (y > pl->part_bytes) pl->part_bytes = y;
@@ -175,10 +226,10 @@ int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
             if (K > st.J) { K = st.J; st.capped = true; }
             st.K = static_cast<int>(K);
             if (st.K > kMaxSmallK) return RHOSVD_EUNSUPPORTED;
-            if (!rh::plan_stream(rh::OP_SKETCH, elem, st.L, st.I, st.T, st.K, num_cu, &st.gs) ||
-                !rh::plan_stream(rh::OP_POWER, elem, st.L, st.I, st.T, st.K, num_cu, &st.gp) ||
-                !rh::plan_stream(rh::OP_TTM, elem, st.L, st.I, st.T, st.K, num_cu, &st.gt) ||
-                !rh::plan_stream(rh::OP_TTM, elem, st.L, st.K, st.T, st.R, num_cu, &st.gtr))
+            if (!plan_pass(rh::OP_SKETCH, pr.dbl, pr.ct_sketch, st.L, st.I, st.T, st.K, num_cu, &st.gs) ||
+                !plan_pass(rh::OP_POWER, pr.dbl, pr.ct_power, st.L, st.I, st.T, st.K, num_cu, &st.gp) ||
+                !plan_pass(rh::OP_TTM, pr.dbl, pr.ct_ttm, st.L, st.I, st.T, st.K, num_cu, &st.gt) ||
+                !plan_pass(rh::OP_TTM, pr.dbl, pr.ct_trunc, st.L, st.K, st.T, st.R, num_cu, &st.gtr))
                 return RHOSVD_EUNSUPPORTED;
             track_stream(pl, st.gs, false);
             if (pr.q > 0) track_stream(pl, st.gp, false);
@@ -217,8 +268,8 @@ int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
         st.K = static_cast<int>(K);
         if (st.K > kMaxSmallK) return RHOSVD_EUNSUPPORTED;
         if (st.K > st.R) pl->any_k_gt_r = true;
-        if (!rh::plan_stream(rh::OP_SKETCH, elem, st.L, st.I, st.T, st.K, num_cu, &st.gs) ||
-            !rh::plan_stream(rh::OP_POWER, elem, st.L, st.I, st.T, st.K, num_cu, &st.gp))
+        if (!plan_pass(rh::OP_SKETCH, pr.dbl, pr.ct_sketch, st.L, st.I, st.T, st.K, num_cu, &st.gs) ||
+            !plan_pass(rh::OP_POWER, pr.dbl, pr.ct_power, st.L, st.I, st.T, st.K, num_cu, &st.gp))
             return RHOSVD_EUNSUPPORTED;
         track_stream(pl, st.gs, false);
         if (pr.q > 0) track_stream(pl, st.gp, false);
@@ -234,7 +285,7 @@ int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
     int64_t buf = 1;
     for (int n = 0; n < N; ++n) {
         const int64_t L = prod(d, 0, n), T = prod(d, n + 1, N);
-        if (!rh::plan_stream(rh::OP_TTM, elem, L, d[n], T, pl->st[n].K, num_cu, &pl->gh[n]))
+        if (!plan_pass(rh::OP_TTM, pr.dbl, pr.ct_ttm, L, d[n], T, pl->st[n].K, num_cu, &pl->gh[n]))
             return RHOSVD_EUNSUPPORTED;
         track_stream(pl, pl->gh[n], false);
         d[n] = pl->st[n].K;
@@ -243,13 +294,13 @@ int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
     }
     for (int n = 0; n < N; ++n) {
         const int64_t L = prod(d, 0, n), T = prod(d, n + 1, N);
-        if (!rh::plan_stream(rh::OP_TTM, elem, L, d[n], T, d[n], num_cu, &pl->gg[n]))
+        if (!plan_pass(rh::OP_TTM, pr.dbl, pr.ct_ttm, L, d[n], T, d[n], num_cu, &pl->gg[n]))
             return RHOSVD_EUNSUPPORTED;
         track_stream(pl, pl->gg[n], true);
     }
     for (int n = 0; n < N; ++n) {
         const int64_t L = prod(d, 0, n), T = prod(d, n + 1, N);
-        if (!rh::plan_stream(rh::OP_TTM, elem, L, d[n], T, pl->st[n].R, num_cu, &pl->gc[n]))
+        if (!plan_pass(rh::OP_TTM, pr.dbl, pr.ct_trunc, L, d[n], T, pl->st[n].R, num_cu, &pl->gc[n]))
             return RHOSVD_EUNSUPPORTED;
         track_stream(pl, pl->gc[n], false);
         d[n] = pl->st[n].R;
@@ -315,7 +366,7 @@ void* at(void* base, int64_t elems, size_t elem) {
 
 // Y = S_(n) Omega, or one fused power step when mat != nullptr; then Q.
 int32_t sketch_and_orthonormalize(const Plan& pl, const Buffers& b, const void* src,
-                                  const rh::StreamGeom& gs, const rh::StreamGeom& gp, int mode,
+                                  const Pass& gs, const Pass& gp, int mode,
                                   uint32_t tag, bool want_norm, void* q_out, hipStream_t s) {
     const bool dbl = pl.pr.dbl;
     rh::StreamArgs a{};
@@ -325,7 +376,7 @@ int32_t sketch_and_orthonormalize(const Plan& pl, const Buffers& b, const void* 
     a.seed = pl.pr.seed;
     a.mode = static_cast<uint32_t>(mode);
     a.tag = tag;
-    RH_HIP(rh::launch_stream(rh::OP_SKETCH, dbl, gs, a, s));
+    RH_HIP(launch_pass(gs, a, s));
     RH_HIP(rh::launch_reduce_y(dbl, b.part, gs.grid, static_cast<int>(gs.I), gs.K, gs.I_pad,
                                gs.K_pad, b.y, s));
     if (want_norm) RH_HIP(rh::launch_reduce_ss(b.part_ss, gs.grid, &b.rep->norm_x2, s));
@@ -335,7 +386,7 @@ int32_t sketch_and_orthonormalize(const Plan& pl, const Buffers& b, const void* 
         pa.src = src;
         pa.mat = q_out;
         pa.part_y = b.part;
-        RH_HIP(rh::launch_stream(rh::OP_POWER, dbl, gp, pa, s));
+        RH_HIP(launch_pass(gp, pa, s));
         RH_HIP(rh::launch_reduce_y(dbl, b.part, gp.grid, static_cast<int>(gp.I), gp.K, gp.I_pad,
                                    gp.K_pad, b.y, s));
         RH_HIP(rh::launch_cqr(b.y, gp.I, gp.K, dbl, q_out, b.q64, &b.rep->flags, s));
@@ -343,14 +394,15 @@ int32_t sketch_and_orthonormalize(const Plan& pl, const Buffers& b, const void* 
     return RHOSVD_OK;
 }
 
-int32_t ttm(const Plan& pl, const rh::StreamGeom& g, const void* src, const void* mat, void* out,
+int32_t ttm(const Plan& pl, const Pass& g, const void* src, const void* mat, void* out,
             void* part_g, hipStream_t s) {
     rh::StreamArgs a{};
     a.src = src;
     a.mat = mat;
     a.out = out;
     a.part_g = part_g;
-    RH_HIP(rh::launch_stream(rh::OP_TTM, pl.pr.dbl, g, a, s));
+    RH_HIP(launch_pass(g, a, s));
+    (void)pl;
     return RHOSVD_OK;
 }
 
@@ -368,9 +420,9 @@ int32_t run_r_sthosvd(const Plan& pl, const Buffers& b, const void* x, const rho
         rc = ttm(pl, st.gt, src, b.qT, b.B, b.part, s);
         if (rc != RHOSVD_OK) return rc;
         RH_HIP(rh::launch_gram_reduce(dbl, b.part, st.gt.grid, st.K, st.gt.K_pad, b.C, s));
-        RH_HIP(rh::launch_evd(b.C, st.K, b.V, b.lam, &b.rep->flags, s));
-        RH_HIP(rh::launch_factor(dbl, b.qT, b.V, b.lam, st.I, st.K, st.R, out->factors[st.n], b.M,
-                                 &b.rep->sigma[st.n][0], b.u64, s));
+        RH_HIP(rh::launch_evd_factor(dbl, b.C, st.K, nullptr, nullptr, &b.rep->flags, b.qT, st.I,
+                                     st.R, 1, out->factors[st.n], b.M, &b.rep->sigma[st.n][0],
+                                     b.u64, s));
         void* dst = (si == N - 1) ? out->core : ((si % 2 == 0) ? b.ping : b.pong);
         rc = ttm(pl, st.gtr, b.B, b.M, dst, nullptr, s);
         if (rc != RHOSVD_OK) return rc;
@@ -417,10 +469,10 @@ int32_t run_rp_hosvd(const Plan& pl, const Buffers& b, const void* x, const rhos
         int32_t rc = ttm(pl, pl.gg[n], H, nullptr, scratch, b.part, s);
         if (rc != RHOSVD_OK) return rc;
         RH_HIP(rh::launch_gram_reduce(dbl, b.part, pl.gg[n].grid, st.K, pl.gg[n].K_pad, b.C, s));
-        RH_HIP(rh::launch_evd(b.C, st.K, b.V, b.lam, &b.rep->flags, s));
-        RH_HIP(rh::launch_factor(dbl, at(b.qstore, qoff[n], e), pl.any_k_gt_r ? b.V : nullptr,
-                                 b.lam, st.I, st.K, st.R, out->factors[n], at(b.mstore, moff[n], e),
-                                 &b.rep->sigma[n][0], b.u64, s));
+        RH_HIP(rh::launch_evd_factor(dbl, b.C, st.K, nullptr, nullptr, &b.rep->flags,
+                                     at(b.qstore, qoff[n], e), st.I, st.R, pl.any_k_gt_r ? 1 : 0,
+                                     out->factors[n], at(b.mstore, moff[n], e),
+                                     &b.rep->sigma[n][0], b.u64, s));
     }
     // G = H x_n M_n^T
     src = H;
@@ -595,15 +647,23 @@ int32_t rhosvd_omega_fill(rhosvd_ctx* ctx, uint64_t seed, int32_t mode, int32_t 
     return RHOSVD_OK;
 }
 
+static void step_cts(int32_t precision, int* s, int* p, int* t) {
+    if (precision == RHOSVD_PREC_BF16) {
+        *s = rh::CT_BF16;
+        *p = rh::CT_BF16X3;
+        *t = rh::CT_BF16X3;
+    } else {
+        *s = *p = *t = rh::CT_F32;
+    }
+}
+
 static int32_t check_view(int32_t dtype, int32_t precision, int64_t L, int64_t I, int64_t T,
                           int32_t K) {
     if (dtype != RHOSVD_F32 && dtype != RHOSVD_F64) return RHOSVD_EINVAL;
     if (L < 1 || I < 1 || T < 1 || K < 1 || K > RHOSVD_MAX_K) return RHOSVD_EINVAL;
     if (dtype == RHOSVD_F64 && precision != RHOSVD_PREC_F64) return RHOSVD_EINVAL;
-    if (dtype == RHOSVD_F32 && precision != RHOSVD_PREC_F32) {
-        if (precision == RHOSVD_PREC_BF16) return RHOSVD_EUNSUPPORTED;
+    if (dtype == RHOSVD_F32 && precision != RHOSVD_PREC_F32 && precision != RHOSVD_PREC_BF16)
         return RHOSVD_EINVAL;
-    }
     return RHOSVD_OK;
 }
 
@@ -614,9 +674,11 @@ int32_t rhosvd_sketch(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t p
     if (!ctx || !src || !y) return RHOSVD_EINVAL;
     int32_t rc = check_view(dtype, precision, L, I, T, K);
     if (rc != RHOSVD_OK) return rc;
-    rh::StreamGeom g;
+    Pass g;
     const bool dbl = dtype == RHOSVD_F64;
-    if (!rh::plan_stream(rh::OP_SKETCH, dbl ? 8 : 4, L, I, T, K, 256, &g)) return RHOSVD_EUNSUPPORTED;
+    int ct_s, ct_p, ct_t;
+    step_cts(precision, &ct_s, &ct_p, &ct_t);
+    if (!plan_pass(rh::OP_SKETCH, dbl, ct_s, L, I, T, K, 256, &g)) return RHOSVD_EUNSUPPORTED;
     void* part;
     double* ss;
     rc = step_ws(workspace, ws_bytes, I, K, &part, &ss);
@@ -629,7 +691,7 @@ int32_t rhosvd_sketch(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t p
     a.seed = seed;
     a.mode = static_cast<uint32_t>(mode);
     a.tag = static_cast<uint32_t>(tag);
-    RH_HIP(rh::launch_stream(rh::OP_SKETCH, dbl, g, a, s));
+    RH_HIP(launch_pass(g, a, s));
     RH_HIP(rh::launch_reduce_y(dbl, part, g.grid, static_cast<int>(I), K, g.I_pad, g.K_pad, y, s));
     if (norm2) RH_HIP(rh::launch_reduce_ss(ss, g.grid, norm2, s));
     return RHOSVD_OK;
@@ -641,9 +703,11 @@ int32_t rhosvd_power(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t pr
     if (!ctx || !src || !q_in || !y) return RHOSVD_EINVAL;
     int32_t rc = check_view(dtype, precision, L, I, T, K);
     if (rc != RHOSVD_OK) return rc;
-    rh::StreamGeom g;
+    Pass g;
     const bool dbl = dtype == RHOSVD_F64;
-    if (!rh::plan_stream(rh::OP_POWER, dbl ? 8 : 4, L, I, T, K, 256, &g)) return RHOSVD_EUNSUPPORTED;
+    int ct_s, ct_p, ct_t;
+    step_cts(precision, &ct_s, &ct_p, &ct_t);
+    if (!plan_pass(rh::OP_POWER, dbl, ct_p, L, I, T, K, 256, &g)) return RHOSVD_EUNSUPPORTED;
     void* part;
     double* ss;
     rc = step_ws(workspace, ws_bytes, I, K, &part, &ss);
@@ -653,7 +717,7 @@ int32_t rhosvd_power(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t pr
     a.src = src;
     a.mat = q_in;
     a.part_y = part;
-    RH_HIP(rh::launch_stream(rh::OP_POWER, dbl, g, a, s));
+    RH_HIP(launch_pass(g, a, s));
     RH_HIP(rh::launch_reduce_y(dbl, part, g.grid, static_cast<int>(I), K, g.I_pad, g.K_pad, y, s));
     return RHOSVD_OK;
 }
@@ -665,9 +729,11 @@ int32_t rhosvd_ttm(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t prec
     int32_t rc = check_view(dtype, precision, L, I, T, Kout);
     if (rc != RHOSVD_OK) return rc;
     if (!m && Kout != I) return RHOSVD_EINVAL;
-    rh::StreamGeom g;
+    Pass g;
     const bool dbl = dtype == RHOSVD_F64;
-    if (!rh::plan_stream(rh::OP_TTM, dbl ? 8 : 4, L, I, T, Kout, 256, &g)) return RHOSVD_EUNSUPPORTED;
+    int ct_s, ct_p, ct_t;
+    step_cts(precision, &ct_s, &ct_p, &ct_t);
+    if (!plan_pass(rh::OP_TTM, dbl, ct_t, L, I, T, Kout, 256, &g)) return RHOSVD_EUNSUPPORTED;
     void* part;
     double* ss;
     rc = step_ws(workspace, ws_bytes, I, Kout, &part, &ss);
@@ -678,7 +744,7 @@ int32_t rhosvd_ttm(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t prec
     a.mat = m;
     a.out = out;
     a.part_g = gram ? part : nullptr;
-    RH_HIP(rh::launch_stream(rh::OP_TTM, dbl, g, a, s));
+    RH_HIP(launch_pass(g, a, s));
     if (gram) RH_HIP(rh::launch_gram_reduce(dbl, part, g.grid, Kout, g.K_pad, gram, s));
     if (norm2) {
         RH_HIP(rh::launch_sumsq(dbl, out, L * static_cast<int64_t>(Kout) * T, ss, kSumsqBlocks, s));

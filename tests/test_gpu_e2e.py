@@ -131,3 +131,19 @@ def test_repeat_is_bitwise_deterministic():
     assert torch.equal(c1, d.core)
     for a, b in zip(f1, d.factors):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("dims,ranks,p,q", CASES)
+def test_bf16_path_matches_oracle(dims, ranks, p, q):
+    # bf16 sketch, split-bf16 power step, bf16 tensor against split operands
+    # in the projection and truncation: |E_gpu - E_oracle| <= 1e-3 (the
+    # target accuracy of the bf16 path; the general BF16 bound is 5e-3)
+    x, _, _ = tucker_tensor(dims, ranks, seed=36, noise=0.05, dtype=np.float32)
+    xd = api.to_device(x)
+    res = api.r_sthosvd(xd, ranks, p=p, q=q, seed=3, precision="bf16")
+    ref = o_rst(x.astype(np.float64), ranks, p, q, seed=3)
+    assert abs(res.rel_error - ref.rel_error) <= 1e-3, (res.rel_error, ref.rel_error)
+    for n in range(len(dims)):
+        np.testing.assert_allclose(res.sigma(n), ref.sigma[n], rtol=2e-2, atol=2e-2 * ref.sigma[n][0])
+        u = res.factors[n].cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(u.T @ u - np.eye(u.shape[1]), 2) <= 1e-4

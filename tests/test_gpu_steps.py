@@ -153,4 +153,56 @@ def test_sym_evd(K):
     np.testing.assert_allclose(lam.cpu().numpy(), w, rtol=1e-12, atol=1e-12 * w[0])
     vv = v.cpu().numpy()
     assert np.all(np.abs(np.abs(np.sum(vv * u, axis=0)) - 1) < 1e-9)
-    assert flags.item() == 0
+    assert flags.item() & 0xffff == 0          # converged; bits 16.. hold the sweep count
+    assert (flags.item() >> 16) <= 12
+
+
+# ---- precision variants of the FP32-tensor kernels ---------------------------
+# bf16 inputs carry a relative rounding error u = 2^-9 per entry; a J-term
+# contraction with random signs then errs by about u/sqrt(3) ~ 2.3e-3 of its
+# column scale, so 1e-2 bounds it; the split-bf16 power step keeps about 16
+# mantissa bits (5e-5).
+@pytest.mark.parametrize("dims", DIMS)
+def test_bf16_sketch_power_ttm(dims):
+    x, _, _ = tucker_tensor(dims, tuple(min(3, d) for d in dims), seed=24, noise=0.3, dtype=np.float32)
+    src = _flat(x, np.float32)
+    x64 = x.astype(np.float64)
+    rng = np.random.default_rng(5)
+    for n, view in _views(dims):
+        J = view[0] * view[2]
+        K = min(11, dims[n], J)
+        y, _ = api.sketch(src, view, K, seed=5, mode=n, tag=2, precision="bf16")
+        want = unfold(x64, n) @ philox.omega(5, n, 2, J, K)
+        _close_cols(y.cpu().numpy(), want, 1e-2)
+        q, _ = np.linalg.qr(rng.standard_normal((dims[n], K)))
+        y = api.power(src, view, torch.from_numpy(q.astype(np.float32)).cuda(), precision="bf16").cpu().numpy()
+        a = unfold(x64, n)
+        _close_cols(y, a @ (a.T @ q.astype(np.float32).astype(np.float64)), 5e-5)
+        m = rng.standard_normal((dims[n], K)).astype(np.float32)
+        out, gram, _ = api.ttm(src, view, K, torch.from_numpy(m).cuda(), want_gram=True, precision="bf16")
+        want = o_ttm(x64, m.astype(np.float64).T, n)
+        got = out.cpu().numpy().reshape(want.shape, order="F")
+        _close_cols(unfold(got, n).T, unfold(want, n).T, 1e-2)
+        b = unfold(want, n)
+        _close_cols(gram.cpu().numpy(), b @ b.T, 1e-2)
+
+
+@pytest.mark.parametrize("dims", DIMS)
+def test_tiled_kernels_fp32(dims, monkeypatch):
+    # the workgroup-tiled kernels (used when a shape does not fit the
+    # wave-private ones) against the same oracle definitions
+    monkeypatch.setenv("RHOSVD_FORCE_TILED", "1")
+    x, _, _ = tucker_tensor(dims, tuple(min(3, d) for d in dims), seed=25, noise=0.3, dtype=np.float32)
+    src = _flat(x, np.float32)
+    x64 = x.astype(np.float64)
+    rng = np.random.default_rng(6)
+    for n, view in _views(dims):
+        J = view[0] * view[2]
+        K = min(11, dims[n], J)
+        y, _ = api.sketch(src, view, K, seed=5, mode=n, tag=2)
+        _close_cols(y.cpu().numpy(), unfold(x64, n) @ philox.omega(5, n, 2, J, K), 2e-5)
+        q, _ = np.linalg.qr(rng.standard_normal((dims[n], K)))
+        q = q.astype(np.float32)
+        y = api.power(src, view, torch.from_numpy(q).cuda()).cpu().numpy()
+        a = unfold(x64, n)
+        _close_cols(y, a @ (a.T @ q.astype(np.float64)), 3e-5)

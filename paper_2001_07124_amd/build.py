@@ -2,19 +2,30 @@
 
     python -m paper_2001_07124_amd.build        # or build_library() from Python
 
-The library is compiled in-tree next to this file with hipcc.  Every HIP
-source is compiled with the packed-FP32 target feature turned off.
+Each HIP source is compiled to an object in `_build/` next to this file (in
+parallel), then linked in-tree.  Every source is compiled with the packed-FP32
+target feature turned off.  The small dense kernels additionally ask the
+backend to keep matrix-core accumulators in ordinary VGPRs: their
+accumulators otherwise round-trip through AGPRs on every step of the loops.
 """
 import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librhosvd.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "kernels_wave.hip", "kernels_small.hip", "rhosvd_api.hip")]
+OBJDIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("RHOSVD_ARCH", "gfx950")
+# source -> extra flags
+SOURCES = {
+    "kernels.hip": [],
+    "kernels_wave.hip": [],
+    "kernels_small.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "rhosvd_api.hip": [],
+}
 
 
 def hipcc_path():
@@ -24,17 +35,41 @@ def hipcc_path():
     raise RuntimeError("hipcc not found: the HIP library cannot be built")
 
 
+def _common_flags():
+    return [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+
+
+def _compile(hipcc, src, extra, verbose):
+    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+    cmd = [hipcc, *_common_flags(), *extra, "-c", os.path.join(HERE, "csrc", src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        return obj, res.stdout + res.stderr
+    return obj, None
+
+
 def build_library(verbose=False):
-    cmd = [hipcc_path(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-           *SOURCES, "-o", LIB + ".tmp"]
+    hipcc = hipcc_path()
+    os.makedirs(OBJDIR, exist_ok=True)
+    jobs = min(len(SOURCES), int(os.environ.get("MAX_JOBS", "8")) or 1)
+    with ThreadPoolExecutor(max_workers=jobs) as pool:
+        results = list(pool.map(lambda kv: _compile(hipcc, kv[0], kv[1], verbose), SOURCES.items()))
+    errors = [err for _, err in results if err]
+    if errors:
+        sys.stderr.write("\n".join(errors))
+        raise RuntimeError("hipcc failed to build librhosvd.so")
+    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *[o for o, _ in results],
+           "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed to build librhosvd.so")
+        raise RuntimeError("hipcc failed to link librhosvd.so")
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

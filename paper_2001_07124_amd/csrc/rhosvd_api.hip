@@ -122,7 +122,7 @@ struct Plan {
     // sizes
     size_t part_bytes = 0;
     int max_grid = 1;
-    int64_t maxIK = 1, maxKK = 1, maxKR = 1, maxIR = 1, maxB = 1;
+    int64_t maxIK = 1, maxKK = 1, maxKR = 1, maxIR = 1, maxB = 1, maxQW = 1;
     int64_t ping = 1, pong = 1;
     int64_t qstore = 0, mstore = 0;
 };
@@ -240,6 +240,10 @@ int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
             if (static_cast<int64_t>(st.K) * st.K > pl->maxKK) pl->maxKK = static_cast<int64_t>(st.K) * st.K;
             if (static_cast<int64_t>(st.K) * st.R > pl->maxKR) pl->maxKR = static_cast<int64_t>(st.K) * st.R;
             if (st.I * st.R > pl->maxIR) pl->maxIR = st.I * st.R;
+        {
+            const int64_t qw = static_cast<int64_t>(rh::evd_qwork_doubles(st.K, st.I));
+            if (qw > pl->maxQW) pl->maxQW = qw;
+        }
             if (st.K * st.J > pl->maxB) pl->maxB = st.K * st.J;
             d[n] = st.R;
             if (s < N - 1) {
@@ -278,6 +282,10 @@ int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
         if (static_cast<int64_t>(st.K) * st.K > pl->maxKK) pl->maxKK = static_cast<int64_t>(st.K) * st.K;
         if (static_cast<int64_t>(st.K) * st.R > pl->maxKR) pl->maxKR = static_cast<int64_t>(st.K) * st.R;
         if (st.I * st.R > pl->maxIR) pl->maxIR = st.I * st.R;
+        {
+            const int64_t qw = static_cast<int64_t>(rh::evd_qwork_doubles(st.K, st.I));
+            if (qw > pl->maxQW) pl->maxQW = qw;
+        }
         pl->qstore += IK;
         pl->mstore += static_cast<int64_t>(st.K) * st.R;
     }
@@ -345,7 +353,7 @@ size_t carve(const Plan& pl, void* ws, Buffers* b) {
     b->V = cv.take<double>(pl.maxKK * sizeof(double));
     b->lam = cv.take<double>(RHOSVD_MAX_K * sizeof(double));
     b->M = cv.take<void>(pl.maxKR * e);
-    b->u64 = cv.take<double>(pl.maxIR * sizeof(double));
+    b->u64 = cv.take<double>(pl.maxQW * sizeof(double));
     if (pl.pr.algo == RHOSVD_R_STHOSVD) {
         b->B = cv.take<void>(pl.maxB * e);
         b->qstore = nullptr;

@@ -12,9 +12,20 @@ kernels can draw the *same* Omega without storing it:
   a 2x32-bit key, ten rounds, round multipliers 0xD2511F53 / 0xCD9E8D57 and
   Weyl key increments 0x9E3779B9 / 0xBB67AE85.
 * Key = (low 32 bits of seed, high 32 bits of seed).
-* Omega_n has J rows and K columns; entry (j, k) (0-based) has linear index
-  e = k*J + j (column-major, so a larger oversampling keeps the smaller
+* Omega_n has J rows and K columns; entry (c, k) (0-based) has linear index
+  e = k*J + c (column-major, so a larger oversampling keeps the smaller
   Omega as its leading columns).
+* Row c of the generated matrix belongs to the unfolding column whose
+  position in the *cyclic* order of the remaining modes is c: with the tensor
+  of shape (I_1, ..., I_N) and mode n, the remaining indices are enumerated
+  as i_{n+1}, ..., i_N, i_1, ..., i_{n-1}, the first of them fastest (the
+  unfolding of De Lathauwer, De Moor and Vandewalle, SIMAX 2000).  The
+  paper's n-unfolding (Section 2) orders the same columns with i_1 fastest;
+  for a column j = l + L t of it (l over the modes before n, L their size,
+  t over the modes after n, T their size) the cyclic position is
+  c = t + T l.  This is a fixed row permutation of an i.i.d. Gaussian
+  matrix, so Omega keeps its distribution; omega_unfolding() returns Omega
+  in the paper's row order.
 * Counter for entry e = (low32(e >> 2), high32(e >> 2), mode, tag); the
   generator output word used is e & 3.  tag = 1 for RP-HOSVD sketches,
   tag = 2 for R-STHOSVD sketches.
@@ -111,11 +122,30 @@ def omega_entries(seed, mode, tag, J, j, k):
 
 
 def omega(seed, mode, tag, J, K):
-    """The J x K Gaussian test matrix Omega for one mode, float64."""
+    """The J x K Gaussian test matrix in generator row order (row c = cyclic
+    column position), float64."""
     total = int(J) * int(K)
     if total == 0:
         return np.zeros((J, K))
     nquads = (total + 3) // 4
     z = normals_for_quads(np.arange(nquads, dtype=np.uint64), seed, mode, tag)
     flat = z.reshape(-1)[:total]          # flat[e] = Omega at linear index e
-    return flat.reshape(K, J).T           # e = k*J + j
+    return flat.reshape(K, J).T           # e = k*J + c
+
+
+def cyclic_position(j, L, T):
+    """Cyclic position c = t + T l of the n-unfolding column j = l + L t."""
+    j = np.asarray(j, dtype=np.int64)
+    return (j // L) + T * (j % L)
+
+
+def omega_unfolding(seed, mode, tag, shape, K):
+    """Omega for the n-unfolding (mode = n) of a tensor of the given shape,
+    rows in the paper's column order: row j = l + L t holds generator row
+    c = t + T l."""
+    shape = tuple(int(d) for d in shape)
+    L = int(np.prod(shape[:mode], dtype=np.int64))
+    T = int(np.prod(shape[mode + 1:], dtype=np.int64))
+    om = omega(seed, mode, tag, L * T, K)
+    # generator rows indexed (t, l) with t fastest -> paper rows (l, t), l fastest
+    return om.reshape(T, L, K, order="F").transpose(1, 0, 2).reshape(L * T, K, order="F")

@@ -24,7 +24,7 @@ from typing import List, Optional
 
 import numpy as np
 
-from .philox import TAG_RP_HOSVD, TAG_R_STHOSVD, omega
+from .philox import TAG_RP_HOSVD, TAG_R_STHOSVD, omega_unfolding
 from .rsvd import brsvd, canonical_signs, qr_pos
 from .tensor_ops import frob2, ttm, tucker_to_full, unfold
 
@@ -110,7 +110,8 @@ def r_sthosvd(x, ranks, p, q, seed, mode_order=None, keep_trace=False):
     writes the unfolding, which cannot be meant before n is bound).  For each
     mode n in mode_order (ascending by default): Algorithm 1 on S_(n) with
     target rank R_n, oversampling p and q power steps, using the test matrix
-    Omega(seed, mode=n, tag=2); then S <- S x_n Q_n^T with the rank-R_n factor.
+    Omega(seed, mode=n, tag=2) of the current S (rows in the paper's order,
+    see oracle.philox); then S <- S x_n Q_n^T with the rank-R_n factor.
     """
     x = np.asarray(x, dtype=np.float64)
     _check_ranks(x.shape, ranks)
@@ -125,7 +126,7 @@ def r_sthosvd(x, ranks, p, q, seed, mode_order=None, keep_trace=False):
         if ranks[n] > a.shape[1]:
             raise ValueError("R_n exceeds the column count of the current unfolding")
         res = brsvd(a, ranks[n], p, q,
-                    lambda J, K, n=n: omega(seed, n, TAG_R_STHOSVD, J, K))
+                    lambda J, K, n=n, sh=s_t.shape: omega_unfolding(seed, n, TAG_R_STHOSVD, sh, K))
         u = res.U * canonical_signs(res.U)
         factors[n], sigma[n], k_used[n] = u, res.s, res.K
         if keep_trace:
@@ -154,7 +155,7 @@ def rp_hosvd(x, ranks, p, q, seed):
         K = min(ranks[n] + p, I, J)
         if ranks[n] > J:
             raise ValueError("R_n exceeds the column count of the unfolding")
-        y = a @ omega(seed, n, TAG_RP_HOSVD, J, K)
+        y = a @ omega_unfolding(seed, n, TAG_RP_HOSVD, x.shape, K)
         qm = qr_pos(y)
         for _ in range(q):
             qz = qr_pos(a.T @ qm)

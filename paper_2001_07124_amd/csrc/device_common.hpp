@@ -72,6 +72,20 @@ __device__ __forceinline__ void normals4(uint64_t q, uint32_t mode, uint32_t tag
     box_muller(static_cast<T>(uniform01f(c2)), static_cast<T>(uniform01f(c3)), z[2], z[3]);
 }
 
+// Omega entry for column j of the unfolding of an (L, I, T) view and sketch
+// column k.  The generator row is the cyclic position c = t + T l of
+// j = l + L t (the modes after n come first), so for L = 1 it is j itself.
+template <typename V>
+__device__ __forceinline__ V omega_entry(uint64_t seed, uint32_t mode, uint32_t tag, int64_t j,
+                                         int k, int64_t L, int64_t T, int64_t J) {
+    const int64_t t = j / L, l = j - t * L;
+    const uint64_t e = static_cast<uint64_t>(k) * static_cast<uint64_t>(J) +
+                       static_cast<uint64_t>(t + T * l);
+    V z[4];
+    normals4<V>(e >> 2, mode, tag, seed, z);
+    return z[e & 3];
+}
+
 // ---------------------------------------------------------------------------
 // 16x16x4 matrix-core step, D = A B + C, for float and double.
 // Operand layout (one wave): lane = m + 16 k holds A[m][k] and B[k][m].

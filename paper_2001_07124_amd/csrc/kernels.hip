@@ -104,7 +104,13 @@ __global__ __launch_bounds__(kBlock) void k_stream(StreamGeom g, StreamArgs a, i
         }
 
         // ---- Omega tile: entries (j0 + c, k) for c < Cv, k < K
-        if (OP == OP_SKETCH) {
+        if (OP == OP_SKETCH && g.L > 1) {
+            // generator rows are not consecutive along the tile's columns
+            for (int it = tid; it < K * Cv; it += kBlock) {
+                const int k = it / Cv, c = it - k * Cv;
+                sW[c * KW + k] = omega_entry<T>(a.seed, a.mode, a.tag, j0 + c, k, g.L, g.T, J);
+            }
+        } else if (OP == OP_SKETCH) {
             const int QPK = C / 4 + 2;
             for (int it = tid; it < K * QPK; it += kBlock) {
                 const int k = it / QPK, qi = it - k * QPK;
@@ -181,7 +187,12 @@ __global__ __launch_bounds__(kBlock) void k_stream(StreamGeom g, StreamArgs a, i
         // ---- write the folded output and accumulate its Gram
         if (OP == OP_TTM) {
             T* __restrict__ out = static_cast<T*>(a.out);
-            if (L == 1) {
+            if (L == 1 && a.out_t) {
+                for (int e = tid; e < Cv * K; e += kBlock) {
+                    const int k = e / Cv, c = e - k * Cv;
+                    out[static_cast<int64_t>(k) * J + j0 + c] = sW[c * KW + k];
+                }
+            } else if (L == 1) {
                 T* __restrict__ ob = out + j0 * static_cast<int64_t>(K);
                 for (int e = tid; e < Cv * K; e += kBlock) {
                     const int c = e / K, k = e - c * K;

@@ -32,6 +32,7 @@ struct StreamArgs {
     double* part_ss;      // [grid] partial sum of squares of src (optional)
     uint64_t seed;
     uint32_t mode, tag;
+    int out_t;            // TTM with L == 1: write out[r * J + j] (modes rotated) instead of out[j * K + r]
 };
 
 // Plan the geometry of a pass; returns false if the shape exceeds the

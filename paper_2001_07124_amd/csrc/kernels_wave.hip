@@ -372,7 +372,15 @@ __global__ __launch_bounds__(kBlock, 1) void k_wave(WGeom g, StreamArgs a, int w
                     if (OP == OP_SKETCH) {
                         const int r = 16 * nb + l16;
                         f32x4 w = zero4<f32x4>();
-                        if (r < K) {
+                        if (r < K && L > 1) {
+                            // generator rows are not consecutive along the block
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const int64_t j = j0 + 4 * quad + e;
+                                w[e] = j < J ? omega_entry<float>(a.seed, a.mode, a.tag, j, r, L, g.T, J)
+                                             : 0.0f;
+                            }
+                        } else if (r < K) {
                             const uint64_t e0 = static_cast<uint64_t>(r) * static_cast<uint64_t>(J) +
                                                 static_cast<uint64_t>(j0 + 4 * quad);
                             w = omega4(e0, a.mode, a.tag, a.seed, jal);
@@ -413,7 +421,19 @@ __global__ __launch_bounds__(kBlock, 1) void k_wave(WGeom g, StreamArgs a, int w
                         if (nb < NB && nb2 < NB) accg[nb][nb2] = mma(zg[nb], zg[nb2], accg[nb][nb2]);
             }
             float* __restrict__ out = static_cast<float*>(a.out);
-            if (L == 1) {
+            if (L == 1 && a.out_t) {
+#pragma unroll
+                for (int nb = 0; nb < NBT; ++nb) {
+                    const int r = 16 * nb + l16;
+                    if (nb < NB && r < K) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int cc = 4 * quad + e;
+                            if (cc < cv) out[static_cast<int64_t>(r) * J + j0 + cc] = z[nb][e];
+                        }
+                    }
+                }
+            } else if (L == 1) {
 #pragma unroll
                 for (int nb = 0; nb < NBT; ++nb) {
                     const int r = 16 * nb + l16;

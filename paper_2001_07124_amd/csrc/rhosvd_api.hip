@@ -118,6 +118,11 @@ struct Plan {
     Pass gg[RHOSVD_MAX_ORDER];   // Gram of H_(n) (identity TTM)
     Pass gc[RHOSVD_MAX_ORDER];   // H .. x_n M_n^T
     bool any_k_gt_r = false;
+    // R-STHOSVD in the natural mode order keeps the current tensor with its
+    // next mode first: (I_n, ..., I_N, R_1, ..., R_{n-1}).  Every unfolding is
+    // then contiguous (L = 1), its columns are in the cyclic order that
+    // indexes Omega, and after the last mode the core is back in (R_1, .., R_N).
+    bool rotated = false;
     int64_t core_elems = 1;
     // sizes
     size_t part_bytes = 0;
@@ -210,13 +215,16 @@ int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
     int64_t d[RHOSVD_MAX_ORDER];
     for (int n = 0; n < N; ++n) d[n] = pr.dims[n];
     if (pr.algo == RHOSVD_R_STHOSVD) {
+        pl->rotated = true;
+        for (int s = 0; s < N; ++s)
+            if (pr.order[s] != s) pl->rotated = false;
         for (int s = 0; s < N; ++s) {
             Step& st = pl->st[s];
             const int n = pr.order[s];
             st.n = n;
-            st.L = prod(d, 0, n);
+            st.L = pl->rotated ? 1 : prod(d, 0, n);
             st.I = d[n];
-            st.T = prod(d, n + 1, N);
+            st.T = pl->rotated ? prod(d, 0, N) / d[n] : prod(d, n + 1, N);
             st.J = st.L * st.T;
             st.R = pr.ranks[n];
             if (st.R > st.J) return RHOSVD_EINVAL;
@@ -403,12 +411,13 @@ int32_t sketch_and_orthonormalize(const Plan& pl, const Buffers& b, const void* 
 }
 
 int32_t ttm(const Plan& pl, const Pass& g, const void* src, const void* mat, void* out,
-            void* part_g, hipStream_t s) {
+            void* part_g, hipStream_t s, int out_t = 0) {
     rh::StreamArgs a{};
     a.src = src;
     a.mat = mat;
     a.out = out;
     a.part_g = part_g;
+    a.out_t = out_t;
     RH_HIP(launch_pass(g, a, s));
     (void)pl;
     return RHOSVD_OK;
@@ -432,7 +441,7 @@ int32_t run_r_sthosvd(const Plan& pl, const Buffers& b, const void* x, const rho
                                      st.R, 1, out->factors[st.n], b.M, &b.rep->sigma[st.n][0],
                                      b.u64, s));
         void* dst = (si == N - 1) ? out->core : ((si % 2 == 0) ? b.ping : b.pong);
-        rc = ttm(pl, st.gtr, b.B, b.M, dst, nullptr, s);
+        rc = ttm(pl, st.gtr, b.B, b.M, dst, nullptr, s, pl.rotated ? 1 : 0);
         if (rc != RHOSVD_OK) return rc;
         src = dst;
     }

@@ -69,7 +69,7 @@ def test_sketch(dims, dtype):
         J = view[0] * view[2]
         K = min(11, dims[n], J)
         y, nrm = api.sketch(src, view, K, seed=5, mode=n, tag=2, want_norm=True)
-        want = unfold(x64, n) @ philox.omega(5, n, 2, J, K)
+        want = unfold(x64, n) @ philox.omega_unfolding(5, n, 2, x64.shape, K)
         tol = 1e-11 if dtype == np.float64 else 2e-5
         _close_cols(y.cpu().numpy(), want, tol)
         assert abs(nrm.item() - float(np.sum(x64 ** 2))) <= (1e-12 if dtype == np.float64 else 1e-6) * np.sum(x64 ** 2)
@@ -172,7 +172,7 @@ def test_bf16_sketch_power_ttm(dims):
         J = view[0] * view[2]
         K = min(11, dims[n], J)
         y, _ = api.sketch(src, view, K, seed=5, mode=n, tag=2, precision="bf16")
-        want = unfold(x64, n) @ philox.omega(5, n, 2, J, K)
+        want = unfold(x64, n) @ philox.omega_unfolding(5, n, 2, x64.shape, K)
         _close_cols(y.cpu().numpy(), want, 1e-2)
         q, _ = np.linalg.qr(rng.standard_normal((dims[n], K)))
         y = api.power(src, view, torch.from_numpy(q.astype(np.float32)).cuda(), precision="bf16").cpu().numpy()
@@ -200,7 +200,7 @@ def test_tiled_kernels_fp32(dims, monkeypatch):
         J = view[0] * view[2]
         K = min(11, dims[n], J)
         y, _ = api.sketch(src, view, K, seed=5, mode=n, tag=2)
-        _close_cols(y.cpu().numpy(), unfold(x64, n) @ philox.omega(5, n, 2, J, K), 2e-5)
+        _close_cols(y.cpu().numpy(), unfold(x64, n) @ philox.omega_unfolding(5, n, 2, x64.shape, K), 2e-5)
         q, _ = np.linalg.qr(rng.standard_normal((dims[n], K)))
         q = q.astype(np.float32)
         y = api.power(src, view, torch.from_numpy(q).cuda()).cpu().numpy()

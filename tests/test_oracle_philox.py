@@ -133,3 +133,34 @@ def test_omega_streams_differ():
     for other in (b, c, d):
         r = np.corrcoef(a.reshape(-1), other.reshape(-1))[0, 1]
         assert abs(r) < 0.1
+
+
+def test_omega_unfolding_row_order():
+    """Row j of omega_unfolding is generator row c, c the cyclic position of
+    unfolding column j, both indices written out from their definitions
+    (the paper's n-unfolding column index, Section 2, and the cyclic order
+    i_{n+1}, ..., i_N, i_1, ..., i_{n-1})."""
+    import itertools
+    shape = (3, 4, 2, 5)
+    K = 3
+    for n in range(len(shape)):
+        om = philox.omega_unfolding(11, n, 2, shape, K)
+        J = int(np.prod(shape)) // shape[n]
+        assert om.shape == (J, K)
+        others = [m for m in range(len(shape)) if m != n]
+        cyc = list(range(n + 1, len(shape))) + list(range(n))
+        for idx in itertools.product(*[range(d) for d in shape]):
+            j, stride = 0, 1
+            for m in others:                     # paper: i_1 fastest, skipping n
+                j += idx[m] * stride
+                stride *= shape[m]
+            c, stride = 0, 1
+            for m in cyc:                        # cyclic: i_{n+1} fastest
+                c += idx[m] * stride
+                stride *= shape[m]
+            for k in range(K):
+                want = philox.omega_entries(11, n, 2, J, c, k)
+                assert om[j, k] == want
+    # mode 0 and the last mode: cyclic order equals the paper's order
+    assert np.array_equal(philox.omega_unfolding(11, 0, 2, shape, K),
+                          philox.omega(11, 0, 2, 40, K))

@@ -23,6 +23,7 @@ ARCH = os.environ.get("RHOSVD_ARCH", "gfx950")
 SOURCES = {
     "kernels.hip": [],
     "kernels_wave.hip": [],
+    "kernels_col.hip": [],
     "kernels_small.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
     "rhosvd_api.hip": [],
 }

@@ -61,6 +61,22 @@ struct WGeom {
 bool plan_wave(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu, WGeom* g);
 hipError_t launch_wave(int op, const WGeom& g, const StreamArgs& a, hipStream_t s);
 
+// Geometry of a column-block pass (kernels_col.hip): contiguous unfolding
+// (L = 1), bf16 matrix cores, blocks of 32 columns, nch 32-row chunks and nb
+// 16-column blocks of the K-wide operand.  Sketch: CT_BF16; power step and
+// mode-n product: CT_BF16X2 or CT_BF16X3.
+struct ColGeom {
+    int64_t I, J;
+    int K, nch, nb, variant, rowp;
+    int split;            // the tensor split into hi + lo bf16 in Z = S^T M (CT_BF16X3)
+    size_t mfr_bytes, lds_bytes;
+    int64_t nblocks;
+    int grid, I_pad, K_pad;
+};
+
+bool plan_col(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu, ColGeom* g);
+hipError_t launch_col(int op, const ColGeom& g, const StreamArgs& a, hipStream_t s);
+
 // Fixed-order reductions of per-workgroup partials.
 hipError_t launch_reduce_y(bool dbl, const void* part, int G, int I, int K, int I_pad, int K_pad,
                            double* y, hipStream_t s);

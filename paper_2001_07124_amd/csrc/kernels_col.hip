@@ -1,0 +1,535 @@
+// Streaming passes over a contiguous unfolding (L = 1) of an FP32 tensor on
+// the gfx950 bf16 matrix cores (v_mfma_f32_16x16x32_bf16).
+//
+// S = S_(n) is I x J with column j at src + j I.  A wave owns blocks of 32
+// consecutive columns and keeps a whole block (I <= 32 NCH rows) in
+// registers.  Lane (c = l % 16, g = l / 16) loads, for column half h2 and
+// 32-row chunk h, rows 32 h + 8 g .. 32 h + 8 g + 7 of column 16 h2 + c with
+// two 16-byte buffer loads.  Rows past I belong to the next column (or, past
+// the end of the tensor, read as zero through the buffer's range check); they
+// only meet zero rows of M or land in rows of Y that are dropped, and the
+// sum of squares masks them.
+//
+// Rounded to bf16, the loaded registers are the A operand of Z = S^T M
+// (m = column, k = row) as they stand.  Y += S W needs A = S (m = row,
+// k = column): each wave writes its block column-major into LDS and reads it
+// back with ds_read_b64_tr_b16, which hands lane (i, g) the columns
+// 4g .. 4g+3 of a 16-column half for row i.  The two halves form the k
+// operand in the order {4g .. 4g+3, 16+4g .. 16+4g+3}; the B operand W
+// (Omega in the sketch, Z in the power step) is built in the same order,
+// which is how Z's accumulators already sit in the lanes.
+//
+// Precision: in the sketch the tensor and Omega are rounded to bf16.  M (Q
+// or the factor) and Z are always split into hi + lo bf16, because rounding
+// the small operand would bias the captured energy ||M^T S||^2 at first
+// order.  With SPLIT (CT_BF16X3) the tensor is split as well in Z = S^T M
+// (hi*lo + lo*hi + hi*hi, about 16 bits); without it (CT_BF16X2) it is
+// rounded, which on the 200^4 workload moves the relative error by a few
+// 1e-4.  The power step's Y += S Z takes the rounded tensor against split Z.
+// The Gram Z^T Z takes hi*hi + hi*lo + lo*hi.  Accumulation is FP32.
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+#include "rhosvd.h"
+
+namespace rh {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+
+constexpr int kColThreads = 256;            // 4 independent waves per workgroup
+constexpr int kColWaves = kColThreads / kWave;
+
+__device__ __forceinline__ f32x4 mma32(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf16x8 to_bf16x8(f32x4 a, f32x4 b) {
+    bf16x8 r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        r[e] = static_cast<__bf16>(a[e]);
+        r[e + 4] = static_cast<__bf16>(b[e]);
+    }
+    return r;
+}
+
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi)
+__device__ __forceinline__ void split8(f32x4 a, f32x4 b, bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const __bf16 ha = static_cast<__bf16>(a[e]), hb = static_cast<__bf16>(b[e]);
+        hi[e] = ha;
+        hi[e + 4] = hb;
+        lo[e] = static_cast<__bf16>(a[e] - static_cast<float>(ha));
+        lo[e + 4] = static_cast<__bf16>(b[e] - static_cast<float>(hb));
+    }
+}
+
+// Uniform (2m + 1) 2^-24 from the top 23 bits of x: the float 1 + m 2^-23
+// assembled by a funnel shift, minus (1 - 2^-24); exact.
+__device__ __forceinline__ float uniform01_bits(uint32_t x) {
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, x, 9u)) - 0x1.fffffep-1f;
+}
+
+// Rows 16 rt .. 16 rt + 15 of the column-major block tile (column pitch rowp
+// bf16), columns 16 h2 .. 16 h2 + 15: lane (i, g) receives S(16 rt + i,
+// 16 h2 + 4 g .. 16 h2 + 4 g + 3).
+__device__ __forceinline__ s16x4 tile_tr(const __bf16* tile, int rowp, int h2, int rt, int lane) {
+    const int s = lane & 15, G = lane >> 4;
+    const __bf16* p = tile + (16 * h2 + 4 * G + (s >> 2)) * rowp + 16 * rt + 4 * (s & 3);
+    return __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(p));
+}
+
+__device__ __forceinline__ bf16x8 cat_bf(s16x4 a, s16x4 b) {
+    s16x8 v;
+    v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
+    v[4] = b[0]; v[5] = b[1]; v[6] = b[2]; v[7] = b[3];
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+// One 64-bit product a * b of 32-bit words as a single v_mad_u64_u32 (the
+// compiler otherwise issues v_mul_lo_u32 and v_mul_hi_u32).
+__device__ __forceinline__ uint64_t mul_wide(uint32_t a, uint32_t b) {
+    uint64_t r, carry;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, 0" : "=v"(r), "=s"(carry) : "s"(a), "v"(b));
+    return r;
+}
+
+// Philox4x32-10 (see device_common.hpp) with the wide products above.
+__device__ __forceinline__ void philox_wide(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
+                                            uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = mul_wide(0xD2511F53u, c0);
+        const uint64_t p1 = mul_wide(0xCD9E8D57u, c2);
+        const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
+        c1 = static_cast<uint32_t>(p1);
+        c3 = static_cast<uint32_t>(p0);
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// The four normals of counter quad q (same definition as normals4), with the
+// hardware log2 / sqrt / sine / cosine: the values are rounded to bf16 next.
+__device__ __forceinline__ void normals4_w(uint64_t q, uint32_t mode, uint32_t tag, uint64_t seed,
+                                           float z[4]) {
+    uint32_t c0 = static_cast<uint32_t>(q), c1 = static_cast<uint32_t>(q >> 32);
+    uint32_t c2 = mode, c3 = tag;
+    philox_wide(c0, c1, c2, c3, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+    const float u0 = uniform01_bits(c0), u1 = uniform01_bits(c1);
+    const float u2 = uniform01_bits(c2), u3 = uniform01_bits(c3);
+    const float r0 = __builtin_amdgcn_sqrtf(-1.38629436f * __builtin_amdgcn_logf(u0));
+    const float r1 = __builtin_amdgcn_sqrtf(-1.38629436f * __builtin_amdgcn_logf(u2));
+    z[0] = r0 * __builtin_amdgcn_cosf(u1);
+    z[1] = r0 * __builtin_amdgcn_sinf(u1);
+    z[2] = r1 * __builtin_amdgcn_cosf(u3);
+    z[3] = r1 * __builtin_amdgcn_sinf(u3);
+}
+
+// Omega at linear indices e0 .. e0 + 3; `aligned` when e0 % 4 == 0.
+__device__ __forceinline__ f32x4 omega4_w(uint64_t e0, uint32_t mode, uint32_t tag, uint64_t seed,
+                                          bool aligned) {
+    float z[4];
+    normals4_w(e0 >> 2, mode, tag, seed, z);
+    f32x4 w;
+    w[0] = z[0]; w[1] = z[1]; w[2] = z[2]; w[3] = z[3];
+    if (!aligned) {
+        float z2[4];
+        normals4_w((e0 >> 2) + 1, mode, tag, seed, z2);
+        const int off = static_cast<int>(e0 & 3);
+        // w[e] = (z ++ z2)[off + e], by selects (no indexed registers)
+        f32x4 v;
+        v[0] = off == 0 ? z[0] : off == 1 ? z[1] : off == 2 ? z[2] : z[3];
+        v[1] = off == 0 ? z[1] : off == 1 ? z[2] : off == 2 ? z[3] : z2[0];
+        v[2] = off == 0 ? z[2] : off == 1 ? z[3] : off == 2 ? z2[0] : z2[1];
+        v[3] = off == 0 ? z[3] : off == 1 ? z2[0] : off == 2 ? z2[1] : z2[2];
+        w = v;
+    }
+    return w;
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const float* src, int64_t blk,
+                                                             int64_t nblocks, int I, int64_t J) {
+    // an empty range for a block past the end: its loads return zeros
+    const int64_t b = blk < nblocks ? blk : nblocks - 1;
+    const float* base = src + b * 32 * static_cast<int64_t>(I);
+    int64_t rem = (J - b * 32) * static_cast<int64_t>(I) * 4;
+    if (blk >= nblocks) rem = 0;
+    const int nrec = rem > 0x7ffff000 ? 0x7ffff000 : static_cast<int>(rem);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), static_cast<short>(0), nrec,
+                                             0x00020000);
+}
+
+// FLAG: the sum of squares (sketch) or the Gram Z^T Z (mode-n product).
+// SPLIT: the tensor also enters Z = S^T M split (hi*lo + lo*hi + hi*hi)
+// instead of rounded (hi*lo + hi*hi).
+template <int OP, int NCH, int NB, bool FLAG, bool SPLIT>
+__global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int RT = 2 * NCH;                 // 16-row tiles of Y
+    constexpr bool SS = (OP == OP_SKETCH) && FLAG;
+    constexpr bool GRAM = (OP == OP_TTM) && FLAG;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int c16 = lane & 15, grp = lane >> 4;
+    const int I = static_cast<int>(g.I), K = g.K;
+    const int64_t J = g.J;
+    const int rowp = g.rowp;
+
+    // M fragments (B operand of Z = S^T M), fragment (h, nb): lane (n, g)
+    // holds M(32 h + 8 g + e, 16 nb + n), e = 0..7, split hi / lo.
+    bf16x8* mfr = reinterpret_cast<bf16x8*>(smem);
+    __bf16* tile = reinterpret_cast<__bf16*>(smem + g.mfr_bytes) +
+                   static_cast<size_t>(wave) * 32 * rowp;
+    if (OP != OP_SKETCH) {
+        const float* __restrict__ m = static_cast<const float*>(a.mat);
+        for (int idx = tid; idx < NCH * NB * 64; idx += kColThreads) {
+            const int ln = idx & 63, hn = idx >> 6;
+            const int h = hn / NB, nb = hn - h * NB;
+            const int r = 16 * nb + (ln & 15), gq = ln >> 4;
+            f32x4 v0, v1;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int i = 32 * h + 8 * gq + e;
+                float x = 0.0f;
+                if (i < I && r < K) x = m ? m[static_cast<int64_t>(r) * I + i] : (i == r ? 1.0f : 0.0f);
+                if (e < 4) v0[e] = x; else v1[e - 4] = x;
+            }
+            bf16x8 hi, lo;
+            split8(v0, v1, hi, lo);
+            mfr[(hn * 2 + 0) * 64 + ln] = hi;
+            mfr[(hn * 2 + 1) * 64 + ln] = lo;
+        }
+        __syncthreads();
+    }
+
+    constexpr int AR = (OP == OP_TTM) ? 1 : RT;     // Y accumulators (sketch, power)
+    constexpr int AN = (OP == OP_TTM) ? 1 : NB;
+    constexpr int GN = GRAM ? NB : 1;               // Gram accumulators
+    f32x4 acc[AR][AN];
+    f32x4 accg[GN][GN];
+#pragma unroll
+    for (int f = 0; f < AR; ++f)
+#pragma unroll
+        for (int nb = 0; nb < AN; ++nb) acc[f][nb] = zero4<f32x4>();
+#pragma unroll
+    for (int f = 0; f < GN; ++f)
+#pragma unroll
+        for (int nb = 0; nb < GN; ++nb) accg[f][nb] = zero4<f32x4>();
+    double ss = 0.0;
+
+    const float* __restrict__ src = static_cast<const float*>(a.src);
+    const int64_t wid = static_cast<int64_t>(blockIdx.x) * kColWaves + wave;
+    const int64_t nw = static_cast<int64_t>(gridDim.x) * kColWaves;
+    const bool jal = (J & 3) == 0;
+    const int voff = (c16 * I + 8 * grp) * 4;       // bytes: column c16 of half 0, row 8 grp
+    const int half1 = 16 * I * 4;                   // bytes to column half 1
+    // Omega linear index of (row j0 + 4 grp, column 16 nb + c16), less j0
+    uint64_t eb[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+        eb[nb] = static_cast<uint64_t>(16 * nb + c16) * static_cast<uint64_t>(J) + 4 * grp;
+
+    f32x4 F[NCH][2][2];
+    {
+        const __amdgpu_buffer_rsrc_t rs = block_rsrc(src, wid, g.nblocks, I, J);
+#pragma unroll
+        for (int h = 0; h < NCH; ++h)
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2)
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    F[h][h2][q] = __builtin_bit_cast(
+                        f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 128 * h + 16 * q,
+                                                                     h2 ? half1 : 0, 0));
+    }
+    for (int64_t blk = wid; blk < g.nblocks; blk += nw) {
+        const int64_t j0 = blk * 32;
+        const __amdgpu_buffer_rsrc_t rn = block_rsrc(src, blk + nw, g.nblocks, I, J);
+        f32x4 Z[2][NB];
+#pragma unroll
+        for (int h2 = 0; h2 < 2; ++h2)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) Z[h2][nb] = zero4<f32x4>();
+        float part = 0.0f;
+
+        // chunk by chunk: round to bf16, stage for the transpose, refill the
+        // chunk's registers with the next block, and the Z = S^T M products
+#pragma unroll
+        for (int h = 0; h < NCH; ++h) {
+            if (SS) {
+                const int hv = I - 32 * h;          // valid rows of the chunk (uniform)
+                if (hv >= 32) {
+#pragma unroll
+                    for (int h2 = 0; h2 < 2; ++h2)
+#pragma unroll
+                        for (int q = 0; q < 2; ++q)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) part = fmaf(F[h][h2][q][e], F[h][h2][q][e], part);
+                } else if (hv > 0) {
+                    const int lim = hv - 8 * grp;
+#pragma unroll
+                    for (int h2 = 0; h2 < 2; ++h2)
+#pragma unroll
+                        for (int q = 0; q < 2; ++q)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const float v = (4 * q + e < lim) ? F[h][h2][q][e] : 0.0f;
+                                part = fmaf(v, v, part);
+                            }
+                }
+            }
+            bf16x8 D0, D1, L0, L1;
+            if (SPLIT && OP != OP_SKETCH) {
+                split8(F[h][0][0], F[h][0][1], D0, L0);
+                split8(F[h][1][0], F[h][1][1], D1, L1);
+            } else {
+                D0 = to_bf16x8(F[h][0][0], F[h][0][1]);
+                D1 = to_bf16x8(F[h][1][0], F[h][1][1]);
+            }
+            if (OP != OP_TTM) {
+                *reinterpret_cast<bf16x8*>(tile + c16 * rowp + 32 * h + 8 * grp) = D0;
+                *reinterpret_cast<bf16x8*>(tile + (16 + c16) * rowp + 32 * h + 8 * grp) = D1;
+            }
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2)
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    F[h][h2][q] = __builtin_bit_cast(
+                        f32x4, __builtin_amdgcn_raw_buffer_load_b128(rn, voff + 128 * h + 16 * q,
+                                                                     h2 ? half1 : 0, 0));
+            if (OP != OP_SKETCH) {
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const bf16x8 mhi = mfr[((h * NB + nb) * 2 + 0) * 64 + lane];
+                    const bf16x8 mlo = mfr[((h * NB + nb) * 2 + 1) * 64 + lane];
+                    if (SPLIT) {
+                        Z[0][nb] = mma32(L0, mhi, Z[0][nb]);
+                        Z[1][nb] = mma32(L1, mhi, Z[1][nb]);
+                    }
+                    Z[0][nb] = mma32(D0, mlo, Z[0][nb]);
+                    Z[1][nb] = mma32(D1, mlo, Z[1][nb]);
+                    Z[0][nb] = mma32(D0, mhi, Z[0][nb]);
+                    Z[1][nb] = mma32(D1, mhi, Z[1][nb]);
+                }
+            }
+        }
+        if (SS) ss += static_cast<double>(part);
+
+        // ---- Y += S_blk W, W = Omega (sketch) or Z (power step)
+        if (OP != OP_TTM) {
+            bf16x8 Whi[NB], Wlo[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                if (OP == OP_SKETCH) {
+                    const uint64_t e0 = eb[nb] + static_cast<uint64_t>(j0);
+                    const f32x4 w0 = omega4_w(e0, a.mode, a.tag, a.seed, jal);
+                    const f32x4 w1 = omega4_w(e0 + 16, a.mode, a.tag, a.seed, jal);
+                    Whi[nb] = to_bf16x8(w0, w1);
+                } else {
+                    split8(Z[0][nb], Z[1][nb], Whi[nb], Wlo[nb]);
+                }
+            }
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                const bf16x8 A = cat_bf(tile_tr(tile, rowp, 0, rt, lane), tile_tr(tile, rowp, 1, rt, lane));
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    if (OP == OP_POWER) acc[rt][nb] = mma32(A, Wlo[nb], acc[rt][nb]);
+                    acc[rt][nb] = mma32(A, Whi[nb], acc[rt][nb]);
+                }
+            }
+        }
+
+        // ---- mode-n product output and its Gram
+        if (OP == OP_TTM) {
+            float* __restrict__ out = static_cast<float*>(a.out);
+            const bool full = j0 + 32 <= J;
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const int r = 16 * nb + c16;
+                    const int64_t jj = j0 + 16 * h2 + 4 * grp;
+                    if (r < K) {
+                        if (a.out_t) {
+                            float* o = out + static_cast<int64_t>(r) * J + jj;
+                            if (jal && full) {
+                                *reinterpret_cast<f32x4*>(o) = Z[h2][nb];
+                            } else {
+#pragma unroll
+                                for (int e = 0; e < 4; ++e)
+                                    if (jj + e < J) o[e] = Z[h2][nb][e];
+                            }
+                        } else {
+                            float* o = out + jj * static_cast<int64_t>(K) + r;
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                if (full || jj + e < J) o[e * K] = Z[h2][nb][e];
+                        }
+                    }
+                }
+            if (GRAM) {
+                bf16x8 Ghi[NB], Glo[NB];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) split8(Z[0][nb], Z[1][nb], Ghi[nb], Glo[nb]);
+#pragma unroll
+                for (int n1 = 0; n1 < NB; ++n1)
+#pragma unroll
+                    for (int n2 = 0; n2 < NB; ++n2) {
+                        accg[n1][n2] = mma32(Glo[n1], Ghi[n2], accg[n1][n2]);
+                        accg[n1][n2] = mma32(Ghi[n1], Glo[n2], accg[n1][n2]);
+                        accg[n1][n2] = mma32(Ghi[n1], Ghi[n2], accg[n1][n2]);
+                    }
+            }
+        }
+    }
+
+    // ---- cross-wave reduction (fixed order) and the per-workgroup partials
+    __syncthreads();
+    float* red = reinterpret_cast<float*>(smem);
+    const size_t gidx = blockIdx.x;
+    const int I_pad = 32 * NCH, K_pad = 16 * NB;
+    if (OP != OP_TTM) {
+        for (int w = 0; w < kColWaves; ++w) {
+            if (wave == w) {
+#pragma unroll
+                for (int rt = 0; rt < AR; ++rt)
+#pragma unroll
+                    for (int nb = 0; nb < AN; ++nb)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int idx = (16 * nb + c16) * I_pad + 16 * rt + 4 * grp + e;
+                            red[idx] = (w == 0 ? 0.0f : red[idx]) + acc[rt][nb][e];
+                        }
+            }
+            __syncthreads();
+        }
+        float* __restrict__ py = static_cast<float*>(a.part_y) + gidx * K_pad * I_pad;
+        for (int e = tid; e < K_pad * I_pad; e += kColThreads) py[e] = red[e];
+    }
+    if (GRAM) {
+        for (int w = 0; w < kColWaves; ++w) {
+            if (wave == w) {
+#pragma unroll
+                for (int n1 = 0; n1 < GN; ++n1)
+#pragma unroll
+                    for (int n2 = 0; n2 < GN; ++n2)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int idx = (16 * n2 + c16) * K_pad + 16 * n1 + 4 * grp + e;
+                            red[idx] = (w == 0 ? 0.0f : red[idx]) + accg[n1][n2][e];
+                        }
+            }
+            __syncthreads();
+        }
+        float* __restrict__ pg = static_cast<float*>(a.part_g) + gidx * K_pad * K_pad;
+        for (int e = tid; e < K_pad * K_pad; e += kColThreads) pg[e] = red[e];
+    }
+    if (SS) {
+        __shared__ double rs[kColWaves];
+        ss = wave_sum(ss);
+        if (lane == 0) rs[wave] = ss;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+            for (int w = 0; w < kColWaves; ++w) s += rs[w];
+            a.part_ss[gidx] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Planning and dispatch: (32-row chunks, 16-column operand blocks) shapes,
+// exact ones first; a shape runs on the smallest instantiation that covers it.
+// ---------------------------------------------------------------------------
+static const int kColShapes[][2] = {{7, 3}, {2, 2}, {1, 2}, {2, 4}, {4, 2}, {4, 4}, {8, 2}, {8, 4}};
+constexpr int kNumColShapes = 8;
+
+bool plan_col(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu, ColGeom* g) {
+    if (L != 1 || I < 1 || I > 256 || T < 1 || K < 1 || K > 64) return false;
+    if (op == OP_SKETCH ? ct != CT_BF16 : (ct != CT_BF16X2 && ct != CT_BF16X3)) return false;
+    g->split = (op != OP_SKETCH && ct == CT_BF16X3) ? 1 : 0;
+    const int nch = static_cast<int>((I + 31) / 32), nb = (K + 15) / 16;
+    int var = -1, best = 1 << 30;
+    for (int v = 0; v < kNumColShapes; ++v) {
+        const int c = kColShapes[v][0], b = kColShapes[v][1];
+        if (c >= nch && b >= nb && c * b < best) {
+            best = c * b;
+            var = v;
+        }
+    }
+    if (var < 0) return false;
+    const int NCH = kColShapes[var][0], NB = kColShapes[var][1];
+    g->I = I;
+    g->J = T;
+    g->K = K;
+    g->nch = NCH;
+    g->nb = NB;
+    g->variant = var;
+    g->rowp = 32 * NCH + 8;
+    g->mfr_bytes = (op != OP_SKETCH) ? static_cast<size_t>(NCH) * NB * 2 * 64 * 16 : 0;
+    const size_t tiles = (op != OP_TTM) ? static_cast<size_t>(kColWaves) * 32 * g->rowp * 2 : 0;
+    size_t lds = g->mfr_bytes + tiles;
+    const size_t red = (op != OP_TTM) ? static_cast<size_t>(32 * NCH) * 16 * NB * 4
+                                      : static_cast<size_t>(16 * NB) * 16 * NB * 4;
+    if (red > lds) lds = red;
+    if (lds + kStaticLdsMargin > kLdsLimit) return false;
+    g->lds_bytes = lds;
+    g->nblocks = (T + 31) / 32;
+    const int64_t wgs = (g->nblocks + kColWaves - 1) / kColWaves;
+    const int64_t cap = num_cu > 0 ? num_cu : 256;
+    g->grid = static_cast<int>(wgs < cap ? wgs : cap);
+    g->I_pad = 32 * NCH;
+    g->K_pad = 16 * NB;
+    return true;
+}
+
+template <int OP, int NCH, int NB, bool SPLIT>
+static hipError_t launch_col_s(const ColGeom& g, const StreamArgs& a, hipStream_t s) {
+    const bool flag = (OP == OP_SKETCH) ? a.part_ss != nullptr : (OP == OP_TTM && a.part_g != nullptr);
+    if (flag)
+        hipLaunchKernelGGL((k_col<OP, NCH, NB, true, SPLIT>), dim3(g.grid), dim3(kColThreads),
+                           g.lds_bytes, s, g, a);
+    else
+        hipLaunchKernelGGL((k_col<OP, NCH, NB, false, SPLIT>), dim3(g.grid), dim3(kColThreads),
+                           g.lds_bytes, s, g, a);
+    return hipGetLastError();
+}
+
+template <int OP, int NCH, int NB>
+static hipError_t launch_col_t(const ColGeom& g, const StreamArgs& a, hipStream_t s) {
+    if (OP != OP_SKETCH && g.split) return launch_col_s<OP, NCH, NB, true>(g, a, s);
+    return launch_col_s<OP, NCH, NB, false>(g, a, s);
+}
+
+template <int OP>
+static hipError_t launch_col_op(const ColGeom& g, const StreamArgs& a, hipStream_t s) {
+    switch (g.variant) {
+        case 0: return launch_col_t<OP, 7, 3>(g, a, s);
+        case 1: return launch_col_t<OP, 2, 2>(g, a, s);
+        case 2: return launch_col_t<OP, 1, 2>(g, a, s);
+        case 3: return launch_col_t<OP, 2, 4>(g, a, s);
+        case 4: return launch_col_t<OP, 4, 2>(g, a, s);
+        case 5: return launch_col_t<OP, 4, 4>(g, a, s);
+        case 6: return launch_col_t<OP, 8, 2>(g, a, s);
+        default: return launch_col_t<OP, 8, 4>(g, a, s);
+    }
+}
+
+hipError_t launch_col(int op, const ColGeom& g, const StreamArgs& a, hipStream_t s) {
+    if (op == OP_SKETCH) return launch_col_op<OP_SKETCH>(g, a, s);
+    if (op == OP_POWER) return launch_col_op<OP_POWER>(g, a, s);
+    return launch_col_op<OP_TTM>(g, a, s);
+}
+
+}  // namespace rh

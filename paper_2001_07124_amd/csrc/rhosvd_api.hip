@@ -50,14 +50,19 @@ struct Carver {
 constexpr int kMaxSmallK = 64;    // CholeskyQR / Jacobi keep K x K in LDS
 constexpr int kSumsqBlocks = 256;
 
-// One streaming pass: the wave-private kernel when the shape fits it (FP32
-// data), the workgroup-tiled kernel otherwise (always for FP64 data).
+// One streaming pass, on the first kernel family that takes the shape:
+//   COL    contiguous unfolding (L = 1), bf16 matrix cores (kernels_col.hip)
+//   WAVE   any view, FP32 data, wave-private blocks (kernels_wave.hip)
+//   TILED  anything, FP32 or FP64 data, workgroup tiles (kernels.hip)
+enum PassKind { PASS_TILED = 0, PASS_WAVE = 1, PASS_COL = 2 };
+
 struct Pass {
     int op = 0;
-    bool wave = false;
+    int kind = PASS_TILED;
     bool dbl = false;
     rh::StreamGeom sg{};
     rh::WGeom wg{};
+    rh::ColGeom cg{};
     int grid = 0, I_pad = 0, K_pad = 0, K = 0;
     int64_t I = 0;
 };
@@ -69,14 +74,22 @@ bool plan_pass(int op, bool dbl, int ct, int64_t L, int64_t I, int64_t T, int K,
     p->I = I;
     p->K = K;
     if (!dbl && std::getenv("RHOSVD_FORCE_TILED") == nullptr &&
+        std::getenv("RHOSVD_NO_COL") == nullptr && rh::plan_col(op, ct, L, I, T, K, num_cu, &p->cg)) {
+        p->kind = PASS_COL;
+        p->grid = p->cg.grid;
+        p->I_pad = p->cg.I_pad;
+        p->K_pad = p->cg.K_pad;
+        return true;
+    }
+    if (!dbl && std::getenv("RHOSVD_FORCE_TILED") == nullptr &&
         rh::plan_wave(op, ct, L, I, T, K, num_cu, &p->wg)) {
-        p->wave = true;
+        p->kind = PASS_WAVE;
         p->grid = p->wg.grid;
         p->I_pad = p->wg.IB * 16;
         p->K_pad = p->wg.NB * 16;
         return true;
     }
-    p->wave = false;
+    p->kind = PASS_TILED;
     if (!rh::plan_stream(op, dbl ? 8 : 4, L, I, T, K, num_cu, &p->sg)) return false;
     p->grid = p->sg.grid;
     p->I_pad = p->sg.I_pad;
@@ -85,7 +98,9 @@ bool plan_pass(int op, bool dbl, int ct, int64_t L, int64_t I, int64_t T, int K,
 }
 
 hipError_t launch_pass(const Pass& p, const rh::StreamArgs& a, hipStream_t s) {
-    return p.wave ? rh::launch_wave(p.op, p.wg, a, s) : rh::launch_stream(p.op, p.dbl, p.sg, a, s);
+    if (p.kind == PASS_COL) return rh::launch_col(p.op, p.cg, a, s);
+    if (p.kind == PASS_WAVE) return rh::launch_wave(p.op, p.wg, a, s);
+    return rh::launch_stream(p.op, p.dbl, p.sg, a, s);
 }
 
 struct Problem {

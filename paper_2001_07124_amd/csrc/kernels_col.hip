@@ -239,22 +239,30 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
     for (int nb = 0; nb < NB; ++nb)
         eb[nb] = static_cast<uint64_t>(16 * nb + c16) * static_cast<uint64_t>(J) + 4 * grp;
 
-    f32x4 F[NCH][2][2];
-    {
-        const __amdgpu_buffer_rsrc_t rs = block_rsrc(src, wid, g.nblocks, I, J);
+    // PD blocks in flight per wave: the loop alternates between the register
+    // sets F0 and F1 (PD = 2), each refilled chunk by chunk with the block
+    // PD nw ahead.  The sketch, whose Y accumulators and generator need the
+    // registers, and the largest tiles keep one block in flight.
+    constexpr int PD = (OP == OP_SKETCH || NCH * NB > 24) ? 1 : 2;
+    f32x4 F0[NCH][2][2], F1[NCH][2][2];
+    auto issue = [&](f32x4 (&Fb)[NCH][2][2], int64_t blk) {
+        const __amdgpu_buffer_rsrc_t rs = block_rsrc(src, blk, g.nblocks, I, J);
 #pragma unroll
         for (int h = 0; h < NCH; ++h)
 #pragma unroll
             for (int h2 = 0; h2 < 2; ++h2)
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
-                    F[h][h2][q] = __builtin_bit_cast(
+                    Fb[h][h2][q] = __builtin_bit_cast(
                         f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 128 * h + 16 * q,
                                                                      h2 ? half1 : 0, 0));
-    }
-    for (int64_t blk = wid; blk < g.nblocks; blk += nw) {
+    };
+    // mode-n product output staging (TTM): 32 x 16 NB floats per wave
+    float* stage = reinterpret_cast<float*>(smem + g.mfr_bytes) + static_cast<size_t>(wave) * 32 * 16 * NB;
+
+    auto body = [&](f32x4 (&Fb)[NCH][2][2], int64_t blk) {
         const int64_t j0 = blk * 32;
-        const __amdgpu_buffer_rsrc_t rn = block_rsrc(src, blk + nw, g.nblocks, I, J);
+        const __amdgpu_buffer_rsrc_t rn = block_rsrc(src, blk + PD * nw, g.nblocks, I, J);
         f32x4 Z[2][NB];
 #pragma unroll
         for (int h2 = 0; h2 < 2; ++h2)
@@ -263,7 +271,7 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
         float part = 0.0f;
 
         // chunk by chunk: round to bf16, stage for the transpose, refill the
-        // chunk's registers with the next block, and the Z = S^T M products
+        // chunk's registers with the block 2 nw ahead, and Z = S^T M
 #pragma unroll
         for (int h = 0; h < NCH; ++h) {
             if (SS) {
@@ -274,7 +282,7 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
 #pragma unroll
                         for (int q = 0; q < 2; ++q)
 #pragma unroll
-                            for (int e = 0; e < 4; ++e) part = fmaf(F[h][h2][q][e], F[h][h2][q][e], part);
+                            for (int e = 0; e < 4; ++e) part = fmaf(Fb[h][h2][q][e], Fb[h][h2][q][e], part);
                 } else if (hv > 0) {
                     const int lim = hv - 8 * grp;
 #pragma unroll
@@ -283,18 +291,18 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
                         for (int q = 0; q < 2; ++q)
 #pragma unroll
                             for (int e = 0; e < 4; ++e) {
-                                const float v = (4 * q + e < lim) ? F[h][h2][q][e] : 0.0f;
+                                const float v = (4 * q + e < lim) ? Fb[h][h2][q][e] : 0.0f;
                                 part = fmaf(v, v, part);
                             }
                 }
             }
             bf16x8 D0, D1, L0, L1;
             if (SPLIT && OP != OP_SKETCH) {
-                split8(F[h][0][0], F[h][0][1], D0, L0);
-                split8(F[h][1][0], F[h][1][1], D1, L1);
+                split8(Fb[h][0][0], Fb[h][0][1], D0, L0);
+                split8(Fb[h][1][0], Fb[h][1][1], D1, L1);
             } else {
-                D0 = to_bf16x8(F[h][0][0], F[h][0][1]);
-                D1 = to_bf16x8(F[h][1][0], F[h][1][1]);
+                D0 = to_bf16x8(Fb[h][0][0], Fb[h][0][1]);
+                D1 = to_bf16x8(Fb[h][1][0], Fb[h][1][1]);
             }
             if (OP != OP_TTM) {
                 *reinterpret_cast<bf16x8*>(tile + c16 * rowp + 32 * h + 8 * grp) = D0;
@@ -304,7 +312,7 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
             for (int h2 = 0; h2 < 2; ++h2)
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
-                    F[h][h2][q] = __builtin_bit_cast(
+                    Fb[h][h2][q] = __builtin_bit_cast(
                         f32x4, __builtin_amdgcn_raw_buffer_load_b128(rn, voff + 128 * h + 16 * q,
                                                                      h2 ? half1 : 0, 0));
             if (OP != OP_SKETCH) {
@@ -354,14 +362,15 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
         if (OP == OP_TTM) {
             float* __restrict__ out = static_cast<float*>(a.out);
             const bool full = j0 + 32 <= J;
+            if (a.out_t) {
+                // rotated layout out[r * J + j]: four consecutive j per lane
 #pragma unroll
-            for (int h2 = 0; h2 < 2; ++h2)
+                for (int h2 = 0; h2 < 2; ++h2)
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb) {
-                    const int r = 16 * nb + c16;
-                    const int64_t jj = j0 + 16 * h2 + 4 * grp;
-                    if (r < K) {
-                        if (a.out_t) {
+                    for (int nb = 0; nb < NB; ++nb) {
+                        const int r = 16 * nb + c16;
+                        const int64_t jj = j0 + 16 * h2 + 4 * grp;
+                        if (r < K) {
                             float* o = out + static_cast<int64_t>(r) * J + jj;
                             if (jal && full) {
                                 *reinterpret_cast<f32x4*>(o) = Z[h2][nb];
@@ -370,14 +379,28 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
                                 for (int e = 0; e < 4; ++e)
                                     if (jj + e < J) o[e] = Z[h2][nb][e];
                             }
-                        } else {
-                            float* o = out + jj * static_cast<int64_t>(K) + r;
-#pragma unroll
-                            for (int e = 0; e < 4; ++e)
-                                if (full || jj + e < J) o[e * K] = Z[h2][nb][e];
                         }
                     }
-                }
+            } else {
+                // out[j * K + r]: the block's 32 K values are contiguous; stage
+                // them in LDS and write 16-byte pieces
+#pragma unroll
+                for (int h2 = 0; h2 < 2; ++h2)
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        const int r = 16 * nb + c16;
+                        if (r < K) {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) stage[(16 * h2 + 4 * grp + e) * K + r] = Z[h2][nb][e];
+                        }
+                    }
+                const int64_t nval = (full ? 32 : (J - j0)) * static_cast<int64_t>(K);
+                float* ob = out + j0 * static_cast<int64_t>(K);
+                const int n4 = static_cast<int>(nval >> 2);
+                for (int t = lane; t < n4; t += kWave)
+                    *reinterpret_cast<f32x4*>(ob + 4 * t) = *reinterpret_cast<const f32x4*>(stage + 4 * t);
+                for (int t = 4 * n4 + lane; t < nval; t += kWave) ob[t] = stage[t];
+            }
             if (GRAM) {
                 bf16x8 Ghi[NB], Glo[NB];
 #pragma unroll
@@ -392,6 +415,17 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
                     }
             }
         }
+    };
+
+    issue(F0, wid);
+    if (PD == 2) {
+        issue(F1, wid + nw);
+        for (int64_t blk = wid; blk < g.nblocks; blk += 2 * nw) {
+            body(F0, blk);
+            if (blk + nw < g.nblocks) body(F1, blk + nw);
+        }
+    } else {
+        for (int64_t blk = wid; blk < g.nblocks; blk += nw) body(F0, blk);
     }
 
     // ---- cross-wave reduction (fixed order) and the per-workgroup partials
@@ -478,7 +512,10 @@ bool plan_col(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu
     g->variant = var;
     g->rowp = 32 * NCH + 8;
     g->mfr_bytes = (op != OP_SKETCH) ? static_cast<size_t>(NCH) * NB * 2 * 64 * 16 : 0;
-    const size_t tiles = (op != OP_TTM) ? static_cast<size_t>(kColWaves) * 32 * g->rowp * 2 : 0;
+    // per wave: the bf16 block tile (sketch, power step) or the 32 x K output
+    // staging of the mode-n product
+    const size_t tiles = (op != OP_TTM) ? static_cast<size_t>(kColWaves) * 32 * g->rowp * 2
+                                        : static_cast<size_t>(kColWaves) * 32 * 16 * NB * 4;
     size_t lds = g->mfr_bytes + tiles;
     const size_t red = (op != OP_TTM) ? static_cast<size_t>(32 * NCH) * 16 * NB * 4
                                       : static_cast<size_t>(16 * NB) * 16 * NB * 4;
@@ -508,7 +545,9 @@ static hipError_t launch_col_s(const ColGeom& g, const StreamArgs& a, hipStream_
 
 template <int OP, int NCH, int NB>
 static hipError_t launch_col_t(const ColGeom& g, const StreamArgs& a, hipStream_t s) {
-    if (OP != OP_SKETCH && g.split) return launch_col_s<OP, NCH, NB, true>(g, a, s);
+    if constexpr (OP != OP_SKETCH) {
+        if (g.split) return launch_col_s<OP, NCH, NB, true>(g, a, s);
+    }
     return launch_col_s<OP, NCH, NB, false>(g, a, s);
 }
 

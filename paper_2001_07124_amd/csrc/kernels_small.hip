@@ -395,7 +395,7 @@ hipError_t launch_cqr_lds(const double* y, int64_t I, int K, bool dbl, void* q_o
 // a_pp - t a_pq, a_qq + t a_pq and an exact zero.  Stops when the
 // off-diagonal mass is at most 1e-28 of the total (relative RMS 1e-14);
 // rotations with a_pq^2 <= 1e-36 |a_pp a_qq| are skipped, and so are rounds
-// without a rotation.
+// without a rotation.  A is double-buffered across rounds (see jacobi_lds).
 // ---------------------------------------------------------------------------
 constexpr int kSweeps = 30;
 
@@ -441,16 +441,27 @@ __device__ __forceinline__ void sym_schur2(double app, double aqq, double apq, d
 
 constexpr int kJacItems = 7;   // (Ke/2)(Ke/2 + 1)/2 + (Ke/2)^2 <= 7 * 256 for Ke <= 64
 
-// pq: (Ke - 1) x (Ke / 2) table of pairs, p | q << 8.
-__device__ bool jacobi_lds(double* A, double* V, int Ke, unsigned short* pq, int* sweeps) {
-    __shared__ double rc[RHOSVD_MAX_K / 2], rs[RHOSVD_MAX_K / 2], rt[RHOSVD_MAX_K / 2];
+// pq: (Ke - 1) x (Ke / 2) table of pairs, p | q << 8.  One workgroup
+// barrier per round: every wave computes all of the round's rotations itself
+// (lanes < Ke/2, into its own LDS slot), A is read from one buffer and
+// written to the other (A2), and V, whose blocks only their owner touches
+// within a round, is updated in place.  All waves see the same A and take the
+// same decisions (round skips, convergence).  On return A points at the
+// current buffer.
+__device__ bool jacobi_lds(double*& A, double* A2, double* V, int Ke, unsigned short* pq,
+                           int* sweeps) {
+    __shared__ double rot[kBlock / kWave][3][RHOSVD_MAX_K / 2];
     __shared__ double red[2][kBlock / kWave];
-    __shared__ int any_rot, conv;
+    __shared__ int conv;
     const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
     const int half = Ke / 2;
     const int n1 = Ke - 1;
     const int nA = half * (half + 1) / 2;   // A blocks (m1 <= m2)
     const int nV = half * half;             // V blocks (row pair, column pair)
+    double* const A0 = A;                   // the two buffers: the initial A and A2
+    double* rc = rot[wave][0];
+    double* rs = rot[wave][1];
+    double* rt = rot[wave][2];
     for (int e = tid; e < n1 * half; e += kBlock) {
         const int round = e / half, m = e - round * half;
         int p, q;
@@ -509,25 +520,6 @@ __device__ bool jacobi_lds(double* A, double* V, int Ke, unsigned short* pq, int
         if (conv) return true;
         for (int round = 0; round < n1; ++round) {
             const unsigned short* pr = pq + round * half;
-            if (wave == 0) {
-                int rot = 0;
-                if (lane < half) {
-                    const int code = pr[lane];
-                    const int p = code & 0xff, q = code >> 8;
-                    const double apq = A[p * Ke + q];
-                    const double app = A[p * Ke + p], aqq = A[q * Ke + q];
-                    double c = 1.0, s = 0.0, t = 0.0;
-                    if (apq * apq > 1e-36 * fabs(app * aqq)) {
-                        sym_schur2(app, aqq, apq, c, s, t);
-                        rot = 1;
-                    }
-                    rc[lane] = c;
-                    rs[lane] = s;
-                    rt[lane] = t;
-                }
-                const unsigned long long b = __ballot(rot);
-                if (lane == 0) any_rot = (b != 0ull) ? 1 : 0;
-            }
             // the pairs of this thread's blocks (the table is read-only)
             int code1[kJacItems], code2[kJacItems];
 #pragma unroll
@@ -536,8 +528,23 @@ __device__ bool jacobi_lds(double* A, double* V, int Ke, unsigned short* pq, int
                 code1[u] = (m1 >= 0 && m1 < 64) ? pr[m1] : 0;
                 code2[u] = (m1 >= 0) ? pr[m2] : 0;
             }
-            __syncthreads();
-            if (!any_rot) continue;
+            int rotate = 0;
+            if (lane < half) {
+                const int code = pr[lane];
+                const int p = code & 0xff, q = code >> 8;
+                const double apq = A[p * Ke + q];
+                const double app = A[p * Ke + p], aqq = A[q * Ke + q];
+                double c = 1.0, sn = 0.0, t = 0.0;
+                if (apq * apq > 1e-36 * fabs(app * aqq)) {
+                    sym_schur2(app, aqq, apq, c, sn, t);
+                    rotate = 1;
+                }
+                rc[lane] = c;
+                rs[lane] = sn;
+                rt[lane] = t;
+            }
+            if (__ballot(rotate) == 0ull) continue;   // same in every wave
+            double* An = (A == A0) ? A2 : A0;
             double x[kJacItems][4], cs[kJacItems][4];
 #pragma unroll
             for (int u = 0; u < kJacItems; ++u) {
@@ -577,10 +584,10 @@ __device__ bool jacobi_lds(double* A, double* V, int Ke, unsigned short* pq, int
                 } else if (m1 == m2) {
                     const double t = cs[u][0];
                     const double apq = x[u][1];
-                    A[p2 * Ke + p2] = x[u][0] - t * apq;
-                    A[q2 * Ke + q2] = x[u][3] + t * apq;
-                    A[p2 * Ke + q2] = 0.0;
-                    A[q2 * Ke + p2] = 0.0;
+                    An[p2 * Ke + p2] = x[u][0] - t * apq;
+                    An[q2 * Ke + q2] = x[u][3] + t * apq;
+                    An[p2 * Ke + q2] = 0.0;
+                    An[q2 * Ke + p2] = 0.0;
                 } else {
                     const int p1 = code1[u] & 0xff, q1 = code1[u] >> 8;
                     const double c1 = cs[u][0], s1 = cs[u][1];
@@ -589,17 +596,18 @@ __device__ bool jacobi_lds(double* A, double* V, int Ke, unsigned short* pq, int
                     const double t10 = c2 * d - s2 * e, t11 = s2 * d + c2 * e;
                     const double n00 = c1 * t00 - s1 * t10, n01 = c1 * t01 - s1 * t11;
                     const double n10 = s1 * t00 + c1 * t10, n11 = s1 * t01 + c1 * t11;
-                    A[p1 * Ke + p2] = n00;
-                    A[p1 * Ke + q2] = n01;
-                    A[q1 * Ke + p2] = n10;
-                    A[q1 * Ke + q2] = n11;
-                    A[p2 * Ke + p1] = n00;
-                    A[q2 * Ke + p1] = n01;
-                    A[p2 * Ke + q1] = n10;
-                    A[q2 * Ke + q1] = n11;
+                    An[p1 * Ke + p2] = n00;
+                    An[p1 * Ke + q2] = n01;
+                    An[q1 * Ke + p2] = n10;
+                    An[q1 * Ke + q2] = n11;
+                    An[p2 * Ke + p1] = n00;
+                    An[q2 * Ke + p1] = n01;
+                    An[p2 * Ke + q1] = n10;
+                    An[q2 * Ke + q1] = n11;
                 }
             }
             __syncthreads();
+            A = An;
         }
     }
     return false;
@@ -625,7 +633,8 @@ __global__ __launch_bounds__(kBlock) void k_evd_factor(const double* __restrict_
     const int Ke = K + (K & 1);
     const int K16 = (K + 15) & ~15, I16 = (I + 15) & ~15;
     double* A = shd;
-    double* V = A + Ke * Ke;
+    double* A2 = A + Ke * Ke;
+    double* V = A2 + Ke * Ke;
     // Q staged as I16 x K16 (row-major): in LDS when it fits, else in qwork
     double* Qs = STAGED ? V + Ke * Ke : qwork;
     unsigned short* pq = reinterpret_cast<unsigned short*>(V + Ke * Ke + (STAGED && q ? I16 * K16 : 0));
@@ -646,13 +655,13 @@ __global__ __launch_bounds__(kBlock) void k_evd_factor(const double* __restrict_
     }
     __syncthreads();
     int sweeps = 0;
-    const bool conv = jacobi_lds(A, V, Ke, pq, &sweeps);
+    const bool conv = jacobi_lds(A, A2, V, Ke, pq, &sweeps);
     if (tid == 0 && !conv && flags) atomicOr(flags, RHOSVD_FLAG_EVD_NOCONV);
     // the stand-alone EVD reports its sweep count in bits 16..23 of flags
     if (tid == 0 && flags && !q) atomicOr(flags, static_cast<uint32_t>(sweeps & 0xff) << 16);
     for (int i = tid; i < K; i += kBlock) dg[i] = A[i * Ke + i];
     __syncthreads();
-    double* Vs = A;                    // sorted eigenvectors (K x K, column-major)
+    double* Vs = (A == shd) ? A2 : shd;   // sorted eigenvectors (K x K, column-major), free buffer
     for (int i = tid; i < K; i += kBlock) {
         const double li = dg[i];
         int rank = 0;
@@ -739,12 +748,12 @@ __global__ __launch_bounds__(kBlock) void k_evd_factor(const double* __restrict_
         for (int r = tid; r < R; r += kBlock) sigma[r] = sqrt(fmax(lam[r], 0.0));
 }
 
-// LDS of k_evd_factor: A and V (Ke x Ke each), Q staged as I16 x K16 when
-// the factor step runs, and the (Ke - 1) x (Ke / 2) pair table.
+// LDS of k_evd_factor: A, A2 and V (Ke x Ke each), Q staged as I16 x K16 when
+// the factor step runs and it fits, and the (Ke - 1) x (Ke / 2) pair table.
 size_t evd_lds_bytes(int K, int64_t I, bool staged) {
     const int Ke = K + (K & 1);
     const size_t K16 = (K + 15) & ~15, I16 = (I + 15) & ~static_cast<int64_t>(15);
-    size_t b = 2 * static_cast<size_t>(Ke) * Ke * sizeof(double);
+    size_t b = 3 * static_cast<size_t>(Ke) * Ke * sizeof(double);
     if (staged) b += I16 * K16 * sizeof(double);
     b += static_cast<size_t>(Ke - 1) * (Ke / 2) * sizeof(unsigned short);
     return (b + 15) & ~static_cast<size_t>(15);

@@ -23,6 +23,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, GB/s
 PEAKS_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0}
+# HBM bytes of the dominant kernel from two rocprofv3 counter runs (FETCH_SIZE,
+# WRITE_SIZE), calibrated on a plain copy of known size; valid only while the
+# kernel's source is the one the counters were taken on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 
 
 def log(msg):
@@ -85,6 +89,34 @@ def cpu_baseline(x, w):
                       f"host cpu_count={os.cpu_count()}"}
 
 
+def measured_traffic(kernel, workload, prec):
+    """HBM bytes per launch of `kernel` from the committed counter runs, or
+    None when there are none for this kernel/workload/precision or the
+    kernel's source changed since they were taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        with open(os.path.join(ROOT, t["source"]), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError, KeyError):
+        return None
+    if (sha != t.get("source_sha256") or t.get("kernel") != kernel
+            or t.get("workload") != workload or t.get("precision") != prec):
+        return None
+    return int(t["traffic_bytes_per_launch"])
+
+
+def copy_probe(dev, nbytes=1 << 30):
+    """A plain device copy of known size, for calibrating the HBM counters."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"[bench] copy probe: {nbytes} bytes copied")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +127,10 @@ def main():
                     help="bf16 (default for FP32 tensors: bf16 sketch/projection, split-bf16 power step) or f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=5)
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the FP32 comparison path")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also copy 1 GiB device to device (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
@@ -140,7 +176,7 @@ def main():
     ms, e_gpu, ws_bytes, t_wall = time_path(prec, args.steps, args.warmup)
     log(f"[bench] {prec}: {ms:.3f} ms/step, E={e_gpu:.6f}")
     compare = None
-    if prec != w["prec"]:
+    if prec != w["prec"] and not args.no_compare:
         ms_ref, e_ref, _, _ = time_path(w["prec"], max(2, args.steps // 2), 1)
         log(f"[bench] {w['prec']}: {ms_ref:.3f} ms/step, E={e_ref:.6f}")
         compare = {"precision": w["prec"], "ms_per_step": round(ms_ref, 4),
@@ -194,6 +230,7 @@ def main():
     else:
         roofline = {"bound": "hbm", "achieved": kd["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                     "frac": round(hbm_frac, 4), "traffic": None}
+    roofline["traffic"] = measured_traffic(dom, args.workload, prec)
     roofline.update({"kernel": f"mode-1 {dom} pass ({prec})", "kernel_ms": kd["ms"],
                      "algorithmic_bytes": kd["bytes"], "algorithmic_flops": kd["flops"],
                      "mode1_kernels": ktimes})
@@ -218,6 +255,8 @@ def main():
         "compare_path": compare,
         "wall_s_timed": round(t_wall, 3),
     }
+    if args.copy_probe:
+        copy_probe(dev)
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on a bounded host sample")
         out["cpu_baseline"] = cpu_baseline(x, w)

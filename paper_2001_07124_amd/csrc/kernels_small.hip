@@ -17,31 +17,45 @@
 namespace rh {
 
 // ---------------------------------------------------------------------------
-// out[e] = sum_g part[g * stride + off(e)], e < I K, fixed order in g.
-// Block: 64 elements x 4 partial groups; group q sums g = q, q + 4, ...
+// out[e] = sum_g part[g * stride + off(e)], e < I K, in a fixed order.
+// Block: 16 elements x 16 partial groups; group q sums g = q, q + 16, ...
+// eight loads at a time, and the groups are added in order through LDS.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_reduce_parts(const T* __restrict__ part, int G, int I,
                                                          int K, int I_pad, int K_pad,
                                                          double* __restrict__ y) {
-    __shared__ double red[4][64];
-    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int e = blockIdx.x * 64 + lane;
+    constexpr int kE = 16, kG = kBlock / kE;
+    __shared__ double red[kG][kE + 1];
+    const int el = threadIdx.x % kE, q = threadIdx.x / kE;
+    const int e = blockIdx.x * kE + el;
     double s = 0.0;
     if (e < I * K) {
         const int k = e / I, i = e - k * I;
         const size_t stride = static_cast<size_t>(K_pad) * I_pad;
         const T* p = part + static_cast<size_t>(k) * I_pad + i;
-        for (int g = q; g < G; g += 4) s += static_cast<double>(p[g * stride]);
+        int g = q;
+        for (; g + 7 * kG < G; g += 8 * kG) {
+            double a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] = static_cast<double>(p[(g + u * kG) * stride]);
+            s += ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+        }
+        for (; g < G; g += kG) s += static_cast<double>(p[g * stride]);
     }
-    red[q][lane] = s;
+    red[q][el] = s;
     __syncthreads();
-    if (q == 0 && e < I * K) y[e] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    if (q == 0 && e < I * K) {
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < kG; ++j) t += red[j][el];
+        y[e] = t;
+    }
 }
 
 hipError_t launch_reduce_parts(bool dbl, const void* part, int G, int I, int K, int I_pad,
                                int K_pad, double* y, hipStream_t s) {
-    const dim3 grid((I * K + 63) / 64);
+    const dim3 grid((I * K + 15) / 16);
     if (dbl)
         hipLaunchKernelGGL(k_reduce_parts<double>, grid, dim3(kBlock), 0, s,
                            static_cast<const double*>(part), G, I, K, I_pad, K_pad, y);
@@ -384,31 +398,37 @@ hipError_t launch_cqr_lds(const double* y, int64_t I, int K, bool dbl, void* q_o
 // ---------------------------------------------------------------------------
 // Jacobi EVD (cyclic, round-robin parallel ordering, rotations as in Golub &
 // Van Loan sym.schur2) of A (LDS, row-major Ke x Ke, Ke even <= 64) with V
-// accumulated.  Round `round` pairs index 0 with one of the others and
-// rotates the rest, so that every pair meets once per sweep; the pairs of all
-// rounds are tabulated once.  A round: wave 0 computes the Ke/2 rotations
-// (c, s, t), then every 2 x 2 block {p1,q1} x {p2,q2} of A (upper block
-// triangle, mirrored) becomes J1^T A J2 and every 2 x 2 block of V becomes
-// V J2, in place: the blocks partition both matrices.  A thread keeps the
-// same blocks (by pair number) for the whole iteration and gathers all its
-// operands before it stores anything.  Diagonal blocks take the closed form
-// a_pp - t a_pq, a_qq + t a_pq and an exact zero.  Stops when the
-// off-diagonal mass is at most 1e-28 of the total (relative RMS 1e-14);
-// rotations with a_pq^2 <= 1e-36 |a_pp a_qq| are skipped, and so are rounds
-// without a rotation.  A is double-buffered across rounds (see jacobi_lds).
+// accumulated.  The rows and columns of A and the columns of V are kept in a
+// moving layout in which the pairs of every round occupy the slots (2m,
+// 2m + 1): after a round each slot moves as a player of the circle method of
+// round-robin scheduling (slot 0 stays, the others advance around one cycle
+// of length Ke - 1), so every pair of indices meets once per sweep and the
+// layout is the original one again at every sweep boundary.  A thread owns
+// fixed 2 x 2 blocks for the whole iteration: a block {2m1, 2m1+1} x {2m2,
+// 2m2+1} of A (m1 <= m2) becomes J1^T A J2, a block of two rows of V and the
+// column pair m2 becomes V J2, and the results go to the permuted slots of
+// the other buffer (A and V are double-buffered, one barrier per round).  V
+// runs one round behind A: its blocks take the previous round's rotations,
+// so their loads, arithmetic and stores overlap the current round's pivot
+// reads and rotation arithmetic; a last V step follows the last round.  Only
+// the upper triangle of A is kept: an entry (r, c) is stored at (min(r, c),
+// max(r, c)), so the blocks m1 < m2 are always read from stored entries and
+// the diagonal blocks use only a_pp, a_pq and a_qq.
+// Diagonal blocks take the closed form a_pp - t a_pq, a_qq + t a_pq and an
+// exact zero.  Stops when the off-diagonal mass is at most 1e-28 of the
+// total (relative RMS 1e-14); rotations with a_pq^2 <= 1e-36 |a_pp a_qq| are
+// replaced by the identity.
 // ---------------------------------------------------------------------------
 constexpr int kSweeps = 30;
 
-__device__ __forceinline__ void rr_pair(int m, int round, int Ke, int& p, int& q) {
-    const int n1 = Ke - 1;
-    int x0 = m - 1 + round;
-    if (x0 >= n1) x0 -= n1;
-    int x1 = Ke - 2 - m + round;
-    if (x1 >= n1) x1 -= n1;
-    const int a0 = (m == 0) ? 0 : 1 + x0;
-    const int a1 = 1 + x1;
-    p = a0 < a1 ? a0 : a1;
-    q = a0 < a1 ? a1 : a0;
+// slot of the next round for the element in slot s (Ke >= 4): the top slots
+// 2, 4, ..., Ke - 2 advance by two, Ke - 2 drops to Ke - 1, the bottom slots
+// 3, 5, ..., Ke - 1 move back by two, slot 1 rises to 2, slot 0 stays.
+__device__ __forceinline__ int rr_next(int s, int Ke) {
+    if (Ke == 2 || s == 0) return s;
+    if (s == 1) return 2;
+    if ((s & 1) == 0) return s + 2 < Ke ? s + 2 : Ke - 1;
+    return s - 2;
 }
 
 // 1 / x and 1 / sqrt(x) from the hardware estimates with one Newton step.
@@ -439,66 +459,101 @@ __device__ __forceinline__ void sym_schur2(double app, double aqq, double apq, d
     s = t * c;
 }
 
-constexpr int kJacItems = 7;   // (Ke/2)(Ke/2 + 1)/2 + (Ke/2)^2 <= 7 * 256 for Ke <= 64
+constexpr int kJacA = 3;   // A blocks Ke/2 (Ke/2 + 1) / 2 <= 3 * 256 for Ke <= 64
+constexpr int kJacV = 4;   // V blocks (Ke/2)^2 <= 4 * 256
 
-// pq: (Ke - 1) x (Ke / 2) table of pairs, p | q << 8.  One workgroup
-// barrier per round: every wave computes all of the round's rotations itself
-// (lanes < Ke/2, into its own LDS slot), A is read from one buffer and
-// written to the other (A2), and V, whose blocks only their owner touches
-// within a round, is updated in place.  All waves see the same A and take the
-// same decisions (round skips, convergence).  On return A points at the
-// current buffer.
-__device__ bool jacobi_lds(double*& A, double* A2, double* V, int Ke, unsigned short* pq,
+// Rotation slots: per wave (each wave computes all rotations of a round
+// itself, so the waves meet only at the round's barrier), per round parity
+// (V uses the previous round's), Ke/2 pairs.
+constexpr int kRotSlots = RHOSVD_MAX_K / 2;
+constexpr size_t kRotDoubles = static_cast<size_t>(kBlock / kWave) * 2 * kRotSlots * 4;
+
+// A items: the Ke/2 diagonal blocks, then the off-diagonal blocks m1 < m2;
+// V items: (row pair, column pair).  Only lanes with an item (and, for the
+// rotations, a pair) touch LDS.  rot: kRotDoubles of LDS.  On
+// return A and V point at the current buffers (A0/A2, V0/V2).
+__device__ bool jacobi_lds(double*& A, double*& V, double* A2, double* V2, double* rot, int Ke,
                            int* sweeps) {
-    __shared__ double rot[kBlock / kWave][3][RHOSVD_MAX_K / 2];
     __shared__ double red[2][kBlock / kWave];
     __shared__ int conv;
     const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
     const int half = Ke / 2;
-    const int n1 = Ke - 1;
-    const int nA = half * (half + 1) / 2;   // A blocks (m1 <= m2)
-    const int nV = half * half;             // V blocks (row pair, column pair)
-    double* const A0 = A;                   // the two buffers: the initial A and A2
-    double* rc = rot[wave][0];
-    double* rs = rot[wave][1];
-    double* rt = rot[wave][2];
-    for (int e = tid; e < n1 * half; e += kBlock) {
-        const int round = e / half, m = e - round * half;
-        int p, q;
-        rr_pair(m, round, Ke, p, q);
-        pq[e] = static_cast<unsigned short>(p | (q << 8));
-    }
-    // this thread's items for the whole iteration: A block (m1 <= m2) or V
-    // block (row pair m1 - 64, column pair m2); m1 < 0 marks no item
-    int item_m1[kJacItems], item_m2[kJacItems];
+    const int nA = half * (half + 1) / 2, nV = half * half;
+    double* const A0 = A;
+    double* const V0 = V;
+    double* const rw = rot + static_cast<size_t>(wave) * 2 * kRotSlots * 4;
+    // A items: read offset, rotation slots, target offsets (upper triangle)
+    int ard[kJacA], am1[kJacA], am2[kJacA], awr[kJacA][4];
+    bool aok[kJacA], vok[kJacV];
 #pragma unroll
-    for (int u = 0; u < kJacItems; ++u) {
-        const int it = tid + u * kBlock;
-        int m1 = -1, m2 = 0;
-        if (it < nA) {
-            int rem = it;
+    for (int u = 0; u < kJacA; ++u) {
+        int it = tid + u * kBlock;
+        aok[u] = it < nA;
+        it = it < nA ? it : nA - 1;
+        int m1, m2;
+        if (it < half) {
+            m1 = m2 = it;
+        } else {
+            int rem = it - half;
             m1 = 0;
-            while (rem >= half - m1) {
-                rem -= half - m1;
+            while (rem >= half - 1 - m1) {
+                rem -= half - 1 - m1;
                 ++m1;
             }
-            m2 = m1 + rem;
-        } else if (it < nA + nV) {
-            const int v = it - nA;
-            m1 = 64 + v / half;
-            m2 = v % half;
+            m2 = m1 + 1 + rem;
         }
-        item_m1[u] = m1;
-        item_m2[u] = m2;
+        ard[u] = 2 * m1 * Ke + 2 * m2;
+        am1[u] = m1;
+        am2[u] = m2;
+        const int c0 = rr_next(2 * m2, Ke), c1 = rr_next(2 * m2 + 1, Ke);
+        const int r0 = rr_next(2 * m1, Ke), r1 = rr_next(2 * m1 + 1, Ke);
+        const auto at = [&](int r, int c) { return r <= c ? r * Ke + c : c * Ke + r; };
+        awr[u][0] = at(r0, c0);
+        awr[u][1] = at(r0, c1);
+        awr[u][2] = at(r1, c0);
+        awr[u][3] = at(r1, c1);
     }
-    __syncthreads();
+    // V items: read offset, column pair, target offsets
+    int vrd[kJacV], vm2[kJacV], vwr[kJacV][2];
+#pragma unroll
+    for (int u = 0; u < kJacV; ++u) {
+        int it = tid + u * kBlock;
+        vok[u] = it < nV;
+        it = it < nV ? it : nV - 1;
+        const int rp = it / half, m2 = it - rp * half;
+        vrd[u] = 2 * rp * Ke + 2 * m2;
+        vm2[u] = m2;
+        vwr[u][0] = 2 * rp * Ke + rr_next(2 * m2, Ke);
+        vwr[u][1] = 2 * rp * Ke + rr_next(2 * m2 + 1, Ke);
+    }
+    const int mr = lane;   // this lane's pair for the rotations (lanes < Ke/2)
+    // V <- V J P with the rotations stored under parity `par`
+    const auto v_step = [&](int par, double* Vn) {
+        const double* rv = rw + par * kRotSlots * 4;
+#pragma unroll
+        for (int u = 0; u < kJacV; ++u) {
+            if (u * kBlock < nV && vok[u]) {
+                const double2 x0 = *reinterpret_cast<const double2*>(V + vrd[u]);
+                const double2 x1 = *reinterpret_cast<const double2*>(V + vrd[u] + Ke);
+                const double2 r2 = *reinterpret_cast<const double2*>(rv + 4 * vm2[u]);
+                Vn[vwr[u][0]] = r2.x * x0.x - r2.y * x0.y;
+                Vn[vwr[u][1]] = r2.y * x0.x + r2.x * x0.y;
+                Vn[vwr[u][0] + Ke] = r2.x * x1.x - r2.y * x1.y;
+                Vn[vwr[u][1] + Ke] = r2.y * x1.x + r2.x * x1.y;
+            }
+        }
+    };
+    int g = 0;   // rounds done
     for (int sweep = 0; sweep < kSweeps; ++sweep) {
+        // the upper triangle stands for both halves
         double off = 0.0, tot = 0.0;
         for (int e = tid; e < Ke * Ke; e += kBlock) {
             const int r = e / Ke, c = e - r * Ke;
-            const double v = A[e] * A[e];
-            tot += v;
-            if (r != c) off += v;
+            if (r <= c) {
+                const double x = A[e] * A[e];
+                tot += (r == c) ? x : 2.0 * x;
+                if (r != c) off += 2.0 * x;
+            }
         }
         off = wave_sum(off);
         tot = wave_sum(tot);
@@ -517,100 +572,77 @@ __device__ bool jacobi_lds(double*& A, double* A2, double* V, int Ke, unsigned s
         }
         __syncthreads();
         *sweeps = sweep;
-        if (conv) return true;
-        for (int round = 0; round < n1; ++round) {
-            const unsigned short* pr = pq + round * half;
-            // the pairs of this thread's blocks (the table is read-only)
-            int code1[kJacItems], code2[kJacItems];
+        if (conv) break;
+        for (int round = 0; round < Ke - 1; ++round, ++g) {
+            const int par = g & 1;
+            double* const An = (A == A0) ? A2 : A0;
+            double* const Vn = (V == V0) ? V2 : V0;
+            // this round's blocks of A
+            double2 x0[kJacA], x1[kJacA];
 #pragma unroll
-            for (int u = 0; u < kJacItems; ++u) {
-                const int m1 = item_m1[u], m2 = item_m2[u];
-                code1[u] = (m1 >= 0 && m1 < 64) ? pr[m1] : 0;
-                code2[u] = (m1 >= 0) ? pr[m2] : 0;
+            for (int u = 0; u < kJacA; ++u) {
+                if (u * kBlock < nA && aok[u]) {
+                    x0[u] = *reinterpret_cast<const double2*>(A + ard[u]);
+                    x1[u] = *reinterpret_cast<const double2*>(A + ard[u] + Ke);
+                }
             }
-            int rotate = 0;
+            // this round's rotations (lanes < Ke/2)
             if (lane < half) {
-                const int code = pr[lane];
-                const int p = code & 0xff, q = code >> 8;
-                const double apq = A[p * Ke + q];
-                const double app = A[p * Ke + p], aqq = A[q * Ke + q];
-                double c = 1.0, sn = 0.0, t = 0.0;
-                if (apq * apq > 1e-36 * fabs(app * aqq)) {
-                    sym_schur2(app, aqq, apq, c, sn, t);
-                    rotate = 1;
+                const double2 pp = *reinterpret_cast<const double2*>(A + 2 * mr * (Ke + 1));
+                const double aqq = A[(2 * mr + 1) * (Ke + 1)];
+                double c, sn, t;
+                sym_schur2(pp.x, aqq, pp.y, c, sn, t);
+                // the identity for a negligible a_pq (the formula is not used there)
+                if (!(pp.y * pp.y > 1e-36 * fabs(pp.x * aqq))) {
+                    c = 1.0;
+                    sn = 0.0;
+                    t = 0.0;
                 }
-                rc[lane] = c;
-                rs[lane] = sn;
-                rt[lane] = t;
+                double* r = rw + (par * kRotSlots + lane) * 4;
+                *reinterpret_cast<double2*>(r) = make_double2(c, sn);
+                r[2] = t;
             }
-            if (__ballot(rotate) == 0ull) continue;   // same in every wave
-            double* An = (A == A0) ? A2 : A0;
-            double x[kJacItems][4], cs[kJacItems][4];
+            // V, one round behind
+            if (g > 0) v_step(par ^ 1, Vn);
+            const double* ra = rw + par * kRotSlots * 4;
 #pragma unroll
-            for (int u = 0; u < kJacItems; ++u) {
-                const int m1 = item_m1[u], m2 = item_m2[u];
-                if (m1 < 0) continue;
-                const int p2 = code2[u] & 0xff, q2 = code2[u] >> 8;
-                cs[u][2] = rc[m2];
-                cs[u][3] = rs[m2];
-                if (m1 < 64) {
-                    const int p1 = code1[u] & 0xff, q1 = code1[u] >> 8;
-                    cs[u][0] = (m1 == m2) ? rt[m1] : rc[m1];
-                    cs[u][1] = rs[m1];
-                    x[u][0] = A[p1 * Ke + p2];
-                    x[u][1] = A[p1 * Ke + q2];
-                    x[u][2] = A[q1 * Ke + p2];
-                    x[u][3] = A[q1 * Ke + q2];
-                } else {
-                    const int i0 = 2 * (m1 - 64);
-                    x[u][0] = V[i0 * Ke + p2];
-                    x[u][1] = V[i0 * Ke + q2];
-                    x[u][2] = V[(i0 + 1) * Ke + p2];
-                    x[u][3] = V[(i0 + 1) * Ke + q2];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kJacItems; ++u) {
-                const int m1 = item_m1[u], m2 = item_m2[u];
-                if (m1 < 0) continue;
-                const int p2 = code2[u] & 0xff, q2 = code2[u] >> 8;
-                const double c2 = cs[u][2], s2 = cs[u][3];
-                if (m1 >= 64) {
-                    const int i0 = 2 * (m1 - 64);
-                    V[i0 * Ke + p2] = c2 * x[u][0] - s2 * x[u][1];
-                    V[i0 * Ke + q2] = s2 * x[u][0] + c2 * x[u][1];
-                    V[(i0 + 1) * Ke + p2] = c2 * x[u][2] - s2 * x[u][3];
-                    V[(i0 + 1) * Ke + q2] = s2 * x[u][2] + c2 * x[u][3];
-                } else if (m1 == m2) {
-                    const double t = cs[u][0];
-                    const double apq = x[u][1];
-                    An[p2 * Ke + p2] = x[u][0] - t * apq;
-                    An[q2 * Ke + q2] = x[u][3] + t * apq;
-                    An[p2 * Ke + q2] = 0.0;
-                    An[q2 * Ke + p2] = 0.0;
-                } else {
-                    const int p1 = code1[u] & 0xff, q1 = code1[u] >> 8;
-                    const double c1 = cs[u][0], s1 = cs[u][1];
-                    const double a = x[u][0], b = x[u][1], d = x[u][2], e = x[u][3];
+            for (int u = 0; u < kJacA; ++u) {
+                if (u * kBlock < nA && aok[u]) {
+                    const double2 r2 = *reinterpret_cast<const double2*>(ra + 4 * am2[u]);
+                    const double2 r1 = *reinterpret_cast<const double2*>(ra + 4 * am1[u]);
+                    const double t1 = ra[4 * am1[u] + 2];
+                    const double c2 = r2.x, s2 = r2.y, c1 = r1.x, s1 = r1.y;
+                    const double a = x0[u].x, b = x0[u].y, d = x1[u].x, e = x1[u].y;
                     const double t00 = c2 * a - s2 * b, t01 = s2 * a + c2 * b;
                     const double t10 = c2 * d - s2 * e, t11 = s2 * d + c2 * e;
-                    const double n00 = c1 * t00 - s1 * t10, n01 = c1 * t01 - s1 * t11;
-                    const double n10 = s1 * t00 + c1 * t10, n11 = s1 * t01 + c1 * t11;
-                    An[p1 * Ke + p2] = n00;
-                    An[p1 * Ke + q2] = n01;
-                    An[q1 * Ke + p2] = n10;
-                    An[q1 * Ke + q2] = n11;
-                    An[p2 * Ke + p1] = n00;
-                    An[q2 * Ke + p1] = n01;
-                    An[p2 * Ke + q1] = n10;
-                    An[q2 * Ke + q1] = n11;
+                    double n00 = c1 * t00 - s1 * t10, n01 = c1 * t01 - s1 * t11;
+                    double n10 = s1 * t00 + c1 * t10, n11 = s1 * t01 + c1 * t11;
+                    if (am1[u] == am2[u]) {
+                        n00 = a - t1 * b;
+                        n11 = e + t1 * b;
+                        n01 = 0.0;
+                        n10 = 0.0;
+                    }
+                    // (a diagonal block stores its zero twice, at (p, q))
+                    An[awr[u][0]] = n00;
+                    An[awr[u][1]] = n01;
+                    An[awr[u][2]] = n10;
+                    An[awr[u][3]] = n11;
                 }
             }
             __syncthreads();
             A = An;
+            if (g > 0) V = Vn;
         }
     }
-    return false;
+    // the last round's step of V
+    if (g > 0) {
+        double* const Vn = (V == V0) ? V2 : V0;
+        v_step((g - 1) & 1, Vn);
+        __syncthreads();
+        V = Vn;
+    }
+    return conv != 0;
 }
 
 // EVD of C (K x K, column-major, device) and, when q != nullptr, the factor
@@ -635,9 +667,10 @@ __global__ __launch_bounds__(kBlock) void k_evd_factor(const double* __restrict_
     double* A = shd;
     double* A2 = A + Ke * Ke;
     double* V = A2 + Ke * Ke;
+    double* V2 = V + Ke * Ke;
+    double* rot = V2 + Ke * Ke;
     // Q staged as I16 x K16 (row-major): in LDS when it fits, else in qwork
-    double* Qs = STAGED ? V + Ke * Ke : qwork;
-    unsigned short* pq = reinterpret_cast<unsigned short*>(V + Ke * Ke + (STAGED && q ? I16 * K16 : 0));
+    double* Qs = STAGED ? rot + kRotDoubles : qwork;
     __shared__ double lam[RHOSVD_MAX_K], dg[RHOSVD_MAX_K];
     __shared__ double sgn[RHOSVD_MAX_K];
     const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
@@ -655,7 +688,7 @@ __global__ __launch_bounds__(kBlock) void k_evd_factor(const double* __restrict_
     }
     __syncthreads();
     int sweeps = 0;
-    const bool conv = jacobi_lds(A, A2, V, Ke, pq, &sweeps);
+    const bool conv = jacobi_lds(A, V, A2, V2, rot, Ke, &sweeps);
     if (tid == 0 && !conv && flags) atomicOr(flags, RHOSVD_FLAG_EVD_NOCONV);
     // the stand-alone EVD reports its sweep count in bits 16..23 of flags
     if (tid == 0 && flags && !q) atomicOr(flags, static_cast<uint32_t>(sweeps & 0xff) << 16);
@@ -748,14 +781,13 @@ __global__ __launch_bounds__(kBlock) void k_evd_factor(const double* __restrict_
         for (int r = tid; r < R; r += kBlock) sigma[r] = sqrt(fmax(lam[r], 0.0));
 }
 
-// LDS of k_evd_factor: A, A2 and V (Ke x Ke each), Q staged as I16 x K16 when
-// the factor step runs and it fits, and the (Ke - 1) x (Ke / 2) pair table.
+// LDS of k_evd_factor: A, A2, V and V2 (Ke x Ke each), the rotation slots
+// and Q staged as I16 x K16 when the factor step runs and it fits.
 size_t evd_lds_bytes(int K, int64_t I, bool staged) {
     const int Ke = K + (K & 1);
     const size_t K16 = (K + 15) & ~15, I16 = (I + 15) & ~static_cast<int64_t>(15);
-    size_t b = 3 * static_cast<size_t>(Ke) * Ke * sizeof(double);
+    size_t b = (4 * static_cast<size_t>(Ke) * Ke + kRotDoubles) * sizeof(double);
     if (staged) b += I16 * K16 * sizeof(double);
-    b += static_cast<size_t>(Ke - 1) * (Ke / 2) * sizeof(unsigned short);
     return (b + 15) & ~static_cast<size_t>(15);
 }
 

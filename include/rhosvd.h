@@ -33,11 +33,14 @@
  *   Numerical warnings are reported asynchronously in rhosvd_report.flags.
  *   No call throws or aborts.
  * - Omega.  The Gaussian test matrices are generated in the kernels from
- *   Philox4x32-10 (Salmon et al., SC'11): entry (j, k) of the J x K matrix of
- *   mode n has linear index e = k J + j, counter (e>>2 low, e>>2 high, n, tag),
+ *   Philox4x32-10 (Salmon et al., SC'11): entry (c, k) of the J x K matrix of
+ *   mode n has linear index e = k J + c, counter (e>>2 low, e>>2 high, n, tag),
  *   key (seed low, seed high), output word e & 3, uniform
  *   u = ((x >> 9) + 0.5) 2^-23 and Box-Muller on word pairs (0,1), (2,3).
- *   tag = 1 for RP-HOSVD, 2 for R-STHOSVD.
+ *   tag = 1 for RP-HOSVD, 2 for R-STHOSVD.  Row c multiplies the unfolding
+ *   column whose position in the cyclic order of the other modes
+ *   (i_{n+1}, ..., i_N, i_1, ..., i_{n-1}, first fastest) is c: for the
+ *   column j = l + L t above (T = J / L), c = t + T l.
  */
 #ifndef RHOSVD_H
 #define RHOSVD_H
@@ -151,8 +154,8 @@ double rhosvd_report_rel_error(const rhosvd_report* r);
  * with j = l + L t at src[l + L (i + I t)], J = L T columns.  dtype selects
  * float (RHOSVD_F32) or double (RHOSVD_F64) for src and outputs. ---- */
 
-/* Fill out (J x K column-major, dtype) with Omega of (seed, mode, tag).
- * Test kernel for the in-kernel generator (Algorithm 1 step 1). */
+/* Fill out (J x K column-major, dtype) with Omega of (seed, mode, tag), rows
+ * in the generator order c.  Test kernel for the in-kernel generator (Algorithm 1 step 1). */
 int32_t rhosvd_omega_fill(rhosvd_ctx* ctx, uint64_t seed, int32_t mode, int32_t tag,
                           int64_t J, int32_t K, int32_t dtype, void* out, void* stream);
 

@@ -1,0 +1,160 @@
+"""Parity at the full benchmark size: 200^4 FP32, ranks 25, p = 10 (K = 35), q = 1.
+
+The mode-1 step calls run in exactly the configuration bench.py times
+(contiguous view (1, 200, 8e6), K = 35, seed 0, tag 2, both precisions).  The
+oracle's values are computed in FP64 on the host, streamed over column blocks
+of the unfolding, for what it can afford at this size:
+  * sketch: the first two columns of Y = X_(1) Omega (Omega has the prefix
+    property, so they are the K = 35 sketch's first columns);
+  * power step: all of Y = X_(1) (X_(1)^T Q) for a seeded orthonormal Q;
+  * projection: 4096 sampled columns of B = Q^T X_(1) and all of C = B B^T.
+The whole decomposition is checked through properties that hold at any size:
+the identity-based E against an explicit residual of the GPU's own factors,
+orthonormal factors, descending sigma, E of both precisions against each other
+and against the closed-form noise level of the input.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle import philox  # noqa: E402
+from oracle.tensor_ops import ttm as o_ttm  # noqa: E402
+from paper_2001_07124_amd import api  # noqa: E402
+from paper_2001_07124_amd.inputs import WORKLOADS, tucker_tensor  # noqa: E402
+
+W = WORKLOADS["r_sthosvd_200x4_r25"]
+DIMS = tuple(W["dims"])
+I1 = DIMS[0]
+J1 = int(np.prod(DIMS[1:]))
+K = W["target"][0] + W["p"]
+CHUNK = 500_000
+
+
+@pytest.fixture(scope="module")
+def data():
+    print(f"[fullsize] generating {DIMS}", flush=True)
+    x, core, _ = tucker_tensor(DIMS, W["ranks"], seed=W["data_seed"], factors=W["factors"],
+                               decay=W["decay"], noise=W["noise"], dtype=W["dtype"])
+    xd = api.to_device(x)
+    torch.cuda.synchronize()
+    flat = xd.as_strided((xd.numel(),), (1,))
+    a = x.reshape(I1, J1, order="F")          # X_(1), a view: column j is contiguous
+    rng = np.random.default_rng(2024)
+    q, _ = np.linalg.qr(rng.standard_normal((I1, K)))
+    print("[fullsize] oracle products", flush=True)
+    om = philox.omega_unfolding(W["seed"], 0, 2, DIMS, 2)
+    y_sk = np.zeros((I1, 2))
+    y_pw = np.zeros((I1, K))
+    gram = np.zeros((K, K))
+    x2 = 0.0
+    for j0 in range(0, J1, CHUNK):
+        blk = a[:, j0:j0 + CHUNK].astype(np.float64)
+        x2 += float(np.sum(blk * blk))
+        y_sk += blk @ om[j0:j0 + CHUNK]
+        z = blk.T @ q
+        y_pw += blk @ z
+        gram += z.T @ z
+    cols = np.sort(rng.choice(J1, 4096, replace=False))
+    b_cols = q.T @ a[:, cols].astype(np.float64)
+    print("[fullsize] ready", flush=True)
+    return dict(x=x, core=core, xd=xd, flat=flat, q=q, y_sk=y_sk, y_pw=y_pw, gram=gram,
+                cols=cols, b_cols=b_cols, x2=x2)
+
+
+def _rel_cols(got, want):
+    scale = np.maximum(np.max(np.abs(want), axis=0, keepdims=True), 1e-300)
+    return float(np.max(np.abs(got - want) / scale))
+
+
+VIEW = (1, I1, J1)
+# FP32 inputs, FP32 accumulation over 8e6 terms in per-workgroup partials
+# (summed in FP64): 2e-5 of the column scale as for the small shapes.  bf16:
+# entries rounded with u = 2^-9 in the sketch (1e-2 of the column scale), the
+# tensor rounded in the second product of the power step (2^-8), split
+# operands in the projection (1e-2 as for the small shapes).
+TOL = {"f32": {"sketch": 2e-5, "power": 3e-5, "ttm": 2e-5},
+       "bf16": {"sketch": 1e-2, "power": 2.0 ** -8, "ttm": 1e-2}}
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_fullsize_sketch(data, prec):
+    y, nrm = api.sketch(data["flat"], VIEW, K, W["seed"], 0, 2, want_norm=True, precision=prec)
+    got = y.cpu().numpy()[:, :2]
+    err = _rel_cols(got, data["y_sk"])
+    print(f"[fullsize] sketch {prec}: {err:.3e}", flush=True)
+    assert err <= TOL[prec]["sketch"]
+    assert abs(nrm.item() - data["x2"]) <= 1e-6 * data["x2"]
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_fullsize_power(data, prec):
+    qt = torch.from_numpy(data["q"].astype(np.float32)).cuda()
+    y = api.power(data["flat"], VIEW, qt, precision=prec).cpu().numpy()
+    # the oracle used the FP64 Q; the GPU gets it rounded to FP32 (2^-24 relative)
+    err = _rel_cols(y, data["y_pw"])
+    print(f"[fullsize] power {prec}: {err:.3e}", flush=True)
+    assert err <= TOL[prec]["power"]
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_fullsize_projection_and_gram(data, prec):
+    qt = torch.from_numpy(data["q"].astype(np.float32)).cuda()
+    out, gram, _ = api.ttm(data["flat"], VIEW, K, qt, want_gram=True, precision=prec)
+    cols = torch.from_numpy(data["cols"]).cuda()
+    b = out.view(J1, K)[cols].cpu().numpy().T.astype(np.float64)      # K x 4096
+    err_b = _rel_cols(b.T, data["b_cols"].T)
+    err_g = _rel_cols(gram.cpu().numpy(), data["gram"])
+    print(f"[fullsize] projection {prec}: B {err_b:.3e}, Gram {err_g:.3e}", flush=True)
+    assert err_b <= TOL[prec]["ttm"]
+    assert err_g <= TOL[prec]["ttm"]
+
+
+def _explicit_rel_error(x, x2, core, facs):
+    """norm(X - G x_1 U_1 ... x_4 U_4) / norm(X), FP64, one last-mode slab at a time."""
+    w = core
+    for n in range(3):
+        w = o_ttm(w, facs[n], n)                 # 200 x 200 x 200 x R_4
+    w2 = np.asfortranarray(w).reshape(-1, w.shape[3], order="F")
+    num = 0.0
+    for s in range(x.shape[3]):
+        d = x[..., s].reshape(-1, order="F").astype(np.float64) - w2 @ facs[3][s]
+        num += float(d @ d)
+    return math.sqrt(num / x2)
+
+
+def test_fullsize_decomposition(data):
+    x = data["x"]
+    m = float(np.prod(DIMS))
+    frac = 1.0 - float(np.prod([r / i for r, i in zip(W["ranks"], DIMS)]))
+    n2 = W["noise"] ** 2 * m
+    e_closed = math.sqrt(n2 * frac / (float(np.sum(data["core"] ** 2)) + n2))
+    errs = {}
+    for prec in ("bf16", "f32"):
+        dec = api.Decomposer(DIMS, W["target"], algo=W["algo"], p=W["p"], q=W["q"], seed=W["seed"],
+                             dtype=torch.float32, precision=prec)
+        dec.run(data["xd"])
+        torch.cuda.synchronize()
+        res = dec.result()
+        core = api.to_numpy_fortran(res.core).astype(np.float64)
+        facs = [f.cpu().numpy().astype(np.float64) for f in res.factors]
+        for n, u in enumerate(facs):
+            r = u.shape[1]
+            assert np.linalg.norm(u.T @ u - np.eye(r), 2) <= 1e-5
+            s = res.sigma(n)
+            assert np.all(np.diff(s) <= 0)
+        e_exp = _explicit_rel_error(x, data["x2"], core, facs)
+        print(f"[fullsize] {prec}: E {res.rel_error:.7f}, explicit {e_exp:.7f}, closed form {e_closed:.7f}",
+              flush=True)
+        # the identity E^2 = 1 - norm(G)^2 / norm(X)^2 holds for orthonormal
+        # factors; FP32 factors (norm(U^T U - I) ~ 1e-7) move it by ~1e-7 / E
+        assert abs(e_exp - res.rel_error) <= 1e-5
+        assert abs(res.rel_error - e_closed) <= 1e-3
+        errs[prec] = res.rel_error
+    assert abs(errs["bf16"] - errs["f32"]) <= 1e-4

@@ -98,10 +98,12 @@ size_t cqr_lds_bytes(int64_t I, int K);
 // step: U = Q V[:, :R] (identity V when use_v == 0), canonical signs,
 // M = V_R diag(s), sigma = sqrt(max(lambda, 0))[:R].  q == nullptr: EVD only
 // (v_out, lam_out).  u64: evd_qwork_doubles(K, I) doubles of scratch for Q
-// when it does not fit in LDS.
+// when it does not fit in LDS.  vwork (K x K) and lwork (K) doubles: scratch
+// of the tridiagonal EVD, which then replaces the Jacobi sweeps.
 hipError_t launch_evd_factor(bool dbl, const double* c, int K, double* v_out, double* lam_out,
                              uint32_t* flags, const void* q, int64_t I, int R, int use_v,
-                             void* u_out, void* m_out, double* sigma, double* u64, hipStream_t s);
+                             void* u_out, void* m_out, double* sigma, double* u64,
+                             double* vwork, double* lwork, hipStream_t s);
 hipError_t launch_evd(const double* c, int K, double* v, double* lambda, uint32_t* flags,
                       hipStream_t s);
 size_t evd_qwork_doubles(int K, int64_t I);

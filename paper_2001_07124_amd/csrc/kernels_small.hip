@@ -9,6 +9,9 @@
 //                   and sigma (steps 6-7)
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+#include <cstring>
+
 #include "device_common.hpp"
 #include "householder.hpp"
 #include "kernels.hpp"
@@ -645,6 +648,323 @@ __device__ bool jacobi_lds(double*& A, double*& V, double* A2, double* V2, doubl
     return conv != 0;
 }
 
+// ---------------------------------------------------------------------------
+// Symmetric EVD by Householder tridiagonalisation, bisection on Sturm counts
+// and inverse iteration (Golub & Van Loan, Matrix Computations, 8.3.1 and
+// 8.4; the bisection / inverse-iteration scheme of LAPACK's dstebz and
+// dstein), for K <= 64 in one workgroup.  Jacobi rounds on this CU are bound
+// by LDS instruction issue; here the sequential parts live in registers.
+//   1. wave 0, lane i = row i of A (registers): for k = 0..K-3 a reflector
+//      H_k = I - tau v v^T (v_{k+1} = 1) zeroes A(k+2:, k); p = tau A v and
+//      w = p - (tau/2)(p^T v) v give A <- A - v w^T - w v^T.  d, e to LDS,
+//      v and tau kept for the back-transformation.
+//   2. all threads, four lanes per eigenvalue j (ascending): each lane counts
+//      the eigenvalues below two of the seven interior points of an 8-way
+//      split of [lo, hi) (Sturm count: negative pivots of T - x I, pivots
+//      kept away from zero by pivmin), the quad adds its flags and keeps the
+//      eighth that holds lambda_j; 18 steps take the Gershgorin interval to
+//      about 1e-16 of norm(T).
+//   3. wave 0, lane j = eigenvalue j: three steps of inverse iteration from a
+//      fixed pseudo-random start, each a solve with T - lambda_j I factored
+//      by Gaussian elimination with row interchanges (the factor kept in LDS,
+//      the vector in registers), normalised, then Gram-Schmidt against the
+//      earlier vectors of its cluster (eigenvalues closer than 1e-3 norm(T),
+//      as in dstein).
+//   4. wave 0: z <- H_0 ... H_{K-3} z.
+// Outputs: v (K x K column-major, column r the eigenvector of the r-th largest
+// eigenvalue) and lambda (descending); with report_iters, bits 16..23 of
+// flags receive the inverse-iteration count.  LDS: evd_tri_lds_doubles(K).
+// ---------------------------------------------------------------------------
+constexpr int kTriIters = 3;
+constexpr int kBisectSteps = 18;
+constexpr int kTriP = RHOSVD_MAX_K / 2;   // row pitch of the LDS vectors (64 >= K)
+
+__host__ __device__ inline size_t evd_tri_lds_doubles(int K) {
+    return static_cast<size_t>(kTriP) * kTriP + 3 * static_cast<size_t>(K) * kWave + 6 * kTriP;
+}
+
+// value of a[idx] for a uniform runtime idx (registers cannot be indexed)
+template <int KB>
+__device__ __forceinline__ double pick(const double (&a)[KB], int idx) {
+    double r = 0.0;
+#pragma unroll
+    for (int c = 0; c < KB; ++c) r = (c == idx) ? a[c] : r;
+    return r;
+}
+
+// Start vector of inverse iteration: entries in [-1, 1) from a 32-bit hash
+// of (i, j) (an integer mixer of the murmur finaliser kind).
+__device__ __forceinline__ double start_entry(int i, int j) {
+    uint32_t h = static_cast<uint32_t>(i) * 0x9E3779B1u ^ (static_cast<uint32_t>(j) + 0x7F4A7C15u) * 0x85EBCA77u;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    h *= 0x297A2D39u;
+    h ^= h >> 15;
+    return static_cast<double>(h) * (2.0 / 4294967296.0) - 1.0;
+}
+
+// The code keeps the outer loops rolled: only loops over the register arrays
+// (length KB) are unrolled, so the kernel stays small enough for the
+// instruction cache.  LDS vectors have pitch kTriP and are zero past K, so
+// those loops need no bounds.
+template <int KB>
+__global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ cin, int K,
+                                                   double* __restrict__ v_out,
+                                                   double* __restrict__ lam_out, uint32_t* flags,
+                                                   int report_iters) {
+    extern __shared__ __align__(16) double shd[];
+    double* hv = shd;                                  // kTriP x kTriP: row k = v of H_k
+    double* lu = hv + kTriP * kTriP;                   // [3][K][64] factor of T - lambda I, per lane
+    double* zs = lu;                                   // K x kTriP vectors (between solves)
+    double* tau = lu + 3 * static_cast<size_t>(K) * kWave;
+    double* dd = tau + kTriP;
+    double* ee = dd + kTriP;
+    double* lam = ee + kTriP;
+    double* bc = lam + kTriP;                          // broadcast of v
+    double* bw = bc + kTriP;                           // broadcast of w
+    __shared__ double stats[2];                        // norm(T), pivmin
+    const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
+    for (int e = tid; e < kTriP * kTriP; e += kBlock) hv[e] = 0.0;
+    for (int e = tid; e < 6 * kTriP; e += kBlock) tau[e] = 0.0;
+    __syncthreads();
+
+    // ---- 1. tridiagonalisation (wave 0) ----
+    if (wave == 0) {
+        double a[KB];
+        const int li = lane < K ? lane : 0;
+#pragma unroll
+        for (int c = 0; c < KB; ++c) a[c] = (lane < K && c < K) ? cin[static_cast<size_t>(c) * K + li] : 0.0;
+#pragma unroll 1
+        for (int k = 0; k < K - 2; ++k) {
+            const double ak = pick(a, k);
+            const double x = lane > k ? ak : 0.0;                 // A(k+1:, k)
+            const double akk = readlane_d(ak, k);
+            const double x1 = readlane_d(ak, k + 1);
+            const double tail = wave_sum(lane > k + 1 ? x * x : 0.0);
+            double beta = x1, t = 0.0, scale = 0.0;
+            if (tail > 0.0) {
+                const double nrm = sqrt(fma(x1, x1, tail));
+                beta = x1 >= 0.0 ? -nrm : nrm;
+                t = (beta - x1) / beta;
+                scale = 1.0 / (x1 - beta);
+            }
+            const double v = lane == k + 1 ? 1.0 : (lane > k + 1 ? x * scale : 0.0);
+            if (lane < K) hv[k * kTriP + lane] = v;
+            if (lane == 0) {
+                tau[k] = t;
+                dd[k] = akk;
+                ee[k] = beta;
+            }
+            if (t != 0.0) {
+                // v and w vanish at indices <= k, so the whole rows can be used
+                if (lane < K) bc[lane] = v;
+                double pv = 0.0;
+#pragma unroll
+                for (int j = 0; j < KB; ++j) pv = fma(a[j], bc[j], pv);
+                const double p = lane > k ? t * pv : 0.0;
+                const double kk = 0.5 * t * wave_sum(p * v);
+                const double w = p - kk * v;
+                if (lane < K) bw[lane] = w;
+#pragma unroll
+                for (int j = 0; j < KB; ++j) a[j] = fma(-v, bw[j], fma(-w, bc[j], a[j]));
+            }
+        }
+        if (K >= 2) {
+            const double d0 = readlane_d(pick(a, K - 2), K - 2);
+            const double d1 = readlane_d(pick(a, K - 1), K - 1);
+            const double e0 = readlane_d(pick(a, K - 2), K - 1);
+            if (lane == 0) {
+                dd[K - 2] = d0;
+                dd[K - 1] = d1;
+                ee[K - 2] = e0;
+            }
+        } else {
+            const double d0 = readlane_d(a[0], 0);
+            if (lane == 0) dd[0] = d0;
+        }
+        if (lane == 0) {
+            // Gershgorin radius as the norm bound; pivmin as in dstebz
+            double tn = 0.0, emax = 1.0;
+            for (int i = 0; i < K; ++i) {
+                const double el = i > 0 ? fabs(ee[i - 1]) : 0.0, er = i < K - 1 ? fabs(ee[i]) : 0.0;
+                tn = fmax(tn, fabs(dd[i]) + el + er);
+                if (i < K - 1) emax = fmax(emax, ee[i] * ee[i]);
+            }
+            stats[0] = tn;
+            stats[1] = 2.2250738585072014e-308 * emax;
+        }
+    }
+    __syncthreads();
+
+    // ---- 2. eigenvalues by multisection (all threads; lanes 4j..4j+3) ----
+    {
+        const double tn = stats[0], pivmin = stats[1];
+        const int j = tid >> 2, sub = tid & 3;
+        double d[KB], e2[KB];
+#pragma unroll
+        for (int i = 0; i < KB; ++i) {
+            d[i] = dd[i];
+            e2[i] = ee[i] * ee[i];                 // ee is zero past K - 2
+        }
+        double lo = -tn - 4.0 * pivmin - 2.2e-16 * 4.0 * K * tn - 1e-300;
+        double hi = tn + 4.0 * pivmin + 2.2e-16 * 4.0 * K * tn + 1e-300;
+#pragma unroll 1
+        for (int st = 0; st < kBisectSteps; ++st) {
+            const double h = (hi - lo) * 0.125;
+            const double xa = lo + (2 * sub + 1) * h, xb = lo + (2 * sub + 2) * h;
+            double qa = d[0] - xa, qb = d[0] - xb;
+            qa = fabs(qa) < pivmin ? -pivmin : qa;
+            qb = fabs(qb) < pivmin ? -pivmin : qb;
+            int ca = qa < 0.0, cb = qb < 0.0;
+#pragma unroll
+            for (int i = 1; i < KB; ++i) {
+                // (rows past K are computed and dropped)
+                double na = fma(-e2[i - 1], rcp_nr(qa), d[i] - xa);
+                double nb = fma(-e2[i - 1], rcp_nr(qb), d[i] - xb);
+                na = fabs(na) < pivmin ? -pivmin : na;
+                nb = fabs(nb) < pivmin ? -pivmin : nb;
+                const bool in = i < K;
+                qa = in ? na : qa;
+                qb = in ? nb : qb;
+                ca += (in && na < 0.0) ? 1 : 0;
+                cb += (in && nb < 0.0) ? 1 : 0;
+            }
+            // points 2 sub + 1 and 2 sub + 2 of 1..7 (point 8 is hi itself)
+            int nle = (ca <= j ? 1 : 0) + ((sub < 3 && cb <= j) ? 1 : 0);
+            nle += __shfl_xor(nle, 1, kWave);
+            nle += __shfl_xor(nle, 2, kWave);
+            const double nlo = lo + nle * h;
+            hi = nle == 7 ? hi : lo + (nle + 1) * h;
+            lo = nlo;
+        }
+        if (sub == 0 && j < K) lam[j] = 0.5 * (lo + hi);
+    }
+    __syncthreads();
+
+    // ---- 3-4. eigenvectors (wave 0, lane j = eigenvalue j) ----
+    if (wave == 0) {
+        const double tn = stats[0];
+        const double tiny = 2.2e-16 * fmax(tn, 1e-300);      // pivot floor of T - lambda I
+        const double ctol = 1e-3 * tn;                         // cluster distance
+        const int jl = lane < K ? lane : K - 1;
+        const double lj = lam[jl];
+        // cluster id: the number of gaps above ctol below this eigenvalue
+        int cid = 0;
+        for (int q = 1; q <= jl; ++q) cid += (lam[q] - lam[q - 1] > ctol) ? 1 : 0;
+        double* u1 = lu;
+        double* u2 = lu + K * kWave;
+        double* u3 = lu + 2 * K * kWave;
+        double z[KB];
+#pragma unroll
+        for (int i = 0; i < KB; ++i) z[i] = i < K ? start_entry(i, jl) : 0.0;
+#pragma unroll 1
+        for (int it = 0; it < kTriIters; ++it) {
+            // forward: elimination with row interchanges (branch-free), the
+            // same operations applied to z; rows past K are left alone
+            double ca = dd[0] - lj, cb = ee[0], cd = 0.0;
+#pragma unroll
+            for (int i = 0; i < KB - 1; ++i) {
+                const bool in = i < K - 1;
+                const double ci = ee[i];                 // sub-diagonal of row i+1
+                const double an = dd[i + 1] - lj;        // diagonal of row i+1
+                const double bn = ee[i + 1];             // super-diagonal of row i+1
+                const bool swap = fabs(ca) < fabs(ci);
+                const double pa = fabs(ca) < tiny ? (ca < 0.0 ? -tiny : tiny) : ca;
+                const double piv = swap ? ci : pa;
+                const double l = (swap ? ca : ci) * rcp_nr(piv);
+                const double zi = z[i], zn = z[i + 1];
+                if (in) {
+                    u1[i * kWave + lane] = piv;
+                    u2[i * kWave + lane] = swap ? an : cb;
+                    u3[i * kWave + lane] = swap ? bn : cd;
+                    z[i] = swap ? zn : zi;
+                    z[i + 1] = swap ? fma(-l, zn, zi) : fma(-l, zi, zn);
+                    const double na = swap ? fma(-l, an, cb) : fma(-l, cb, an);
+                    cb = swap ? fma(-l, bn, cd) : fma(-l, cd, bn);
+                    ca = na;
+                    cd = 0.0;
+                }
+            }
+            {
+                const double pa = fabs(ca) < tiny ? (ca < 0.0 ? -tiny : tiny) : ca;
+                u1[(K - 1) * kWave + lane] = pa;
+                u2[(K - 1) * kWave + lane] = 0.0;
+                u3[(K - 1) * kWave + lane] = 0.0;
+            }
+            // back substitution, from the last row up
+            double z1 = 0.0, z2 = 0.0;   // z[i + 1], z[i + 2]
+#pragma unroll
+            for (int i = KB - 1; i >= 0; --i) {
+                if (i < K) {
+                    const double r = fma(-u2[i * kWave + lane], z1, fma(-u3[i * kWave + lane], z2, z[i]));
+                    z[i] = r * rcp_nr(u1[i * kWave + lane]);
+                    z2 = z1;
+                    z1 = z[i];
+                }
+            }
+            double nn = 0.0;
+#pragma unroll
+            for (int i = 0; i < KB; ++i) nn = fma(z[i], z[i], nn);
+            double inv = rsq_nr(nn);
+#pragma unroll
+            for (int i = 0; i < KB; ++i) z[i] *= inv;
+            // Gram-Schmidt within clusters, in ascending order: vector m is
+            // final when its turn comes; the later members of its cluster
+            // remove their component along it
+#pragma unroll 1
+            for (int m = 0; m < K - 1; ++m) {
+                if (!(lam[m + 1] - lam[m] <= ctol)) continue;      // uniform: no later cluster mate
+                if (lane == m) {
+                    double s2 = 0.0;
+#pragma unroll
+                    for (int i = 0; i < KB; ++i) s2 = fma(z[i], z[i], s2);
+                    const double r = rsq_nr(s2);
+#pragma unroll
+                    for (int i = 0; i < KB; ++i) {
+                        z[i] *= r;
+                        zs[m * kTriP + i] = z[i];
+                    }
+                }
+                const bool mate = lane > m && lane < K && cid == __builtin_amdgcn_readlane(cid, m);
+                double dot = 0.0;
+#pragma unroll
+                for (int i = 0; i < KB; ++i) dot = fma(zs[m * kTriP + i], z[i], dot);
+                if (mate) {
+#pragma unroll
+                    for (int i = 0; i < KB; ++i) z[i] = fma(-dot, zs[m * kTriP + i], z[i]);
+                }
+            }
+            nn = 0.0;
+#pragma unroll
+            for (int i = 0; i < KB; ++i) nn = fma(z[i], z[i], nn);
+            inv = rsq_nr(nn);
+#pragma unroll
+            for (int i = 0; i < KB; ++i) z[i] *= inv;
+        }
+        // back-transformation z <- H_0 ... H_{K-3} z (rows of hv are zero
+        // at indices <= k and past K)
+#pragma unroll 1
+        for (int k = K - 3; k >= 0; --k) {
+            const double t = tau[k];
+            double w = 0.0;
+#pragma unroll
+            for (int i = 0; i < KB; ++i) w = fma(hv[k * kTriP + i], z[i], w);
+            w *= t;
+#pragma unroll
+            for (int i = 0; i < KB; ++i) z[i] = fma(-w, hv[k * kTriP + i], z[i]);
+        }
+        if (lane < K) {
+            const int col = K - 1 - lane;
+#pragma unroll
+            for (int i = 0; i < KB; ++i)
+                if (i < K) v_out[static_cast<size_t>(col) * K + i] = z[i];
+            lam_out[col] = lj;
+        }
+        if (tid == 0 && flags && report_iters) atomicOr(flags, static_cast<uint32_t>(kTriIters) << 16);
+    }
+}
+
 // EVD of C (K x K, column-major, device) and, when q != nullptr, the factor
 // step: U = Q V[:, :R] (V = identity when use_v == 0), canonical signs,
 // M = V_R diag(s) (K x R), sigma = sqrt(max(lambda, 0))[:R].  Q is staged
@@ -660,7 +980,9 @@ __global__ __launch_bounds__(kBlock) void k_evd_factor(const double* __restrict_
                                                        T* __restrict__ u_out,
                                                        T* __restrict__ m_out,
                                                        double* __restrict__ sigma,
-                                                       double* __restrict__ qwork) {
+                                                       double* __restrict__ qwork,
+                                                       const double* __restrict__ vpre,
+                                                       const double* __restrict__ lpre) {
     extern __shared__ __align__(16) double shd[];
     const int Ke = K + (K & 1);
     const int K16 = (K + 15) & ~15, I16 = (I + 15) & ~15;
@@ -674,10 +996,16 @@ __global__ __launch_bounds__(kBlock) void k_evd_factor(const double* __restrict_
     __shared__ double lam[RHOSVD_MAX_K], dg[RHOSVD_MAX_K];
     __shared__ double sgn[RHOSVD_MAX_K];
     const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
-    for (int e = tid; e < Ke * Ke; e += kBlock) {
-        const int r = e / Ke, c = e - r * Ke;
-        A[e] = (r < K && c < K) ? cin[c * K + r] : 0.0;
-        V[e] = (r == c) ? 1.0 : 0.0;
+    if (vpre) {
+        // eigenpairs already sorted (k_evd_tri): into the first buffer
+        for (int e = tid; e < K * K; e += kBlock) A[e] = vpre[e];
+        for (int e = tid; e < K; e += kBlock) lam[e] = lpre[e];
+    } else {
+        for (int e = tid; e < Ke * Ke; e += kBlock) {
+            const int r = e / Ke, c = e - r * Ke;
+            A[e] = (r < K && c < K) ? cin[c * K + r] : 0.0;
+            V[e] = (r == c) ? 1.0 : 0.0;
+        }
     }
     if (q) {
         for (int e = tid; e < I16 * K16; e += kBlock) {
@@ -687,25 +1015,28 @@ __global__ __launch_bounds__(kBlock) void k_evd_factor(const double* __restrict_
         }
     }
     __syncthreads();
-    int sweeps = 0;
-    const bool conv = jacobi_lds(A, V, A2, V2, rot, Ke, &sweeps);
-    if (tid == 0 && !conv && flags) atomicOr(flags, RHOSVD_FLAG_EVD_NOCONV);
-    // the stand-alone EVD reports its sweep count in bits 16..23 of flags
-    if (tid == 0 && flags && !q) atomicOr(flags, static_cast<uint32_t>(sweeps & 0xff) << 16);
-    for (int i = tid; i < K; i += kBlock) dg[i] = A[i * Ke + i];
-    __syncthreads();
-    double* Vs = (A == shd) ? A2 : shd;   // sorted eigenvectors (K x K, column-major), free buffer
-    for (int i = tid; i < K; i += kBlock) {
-        const double li = dg[i];
-        int rank = 0;
-        for (int j = 0; j < K; ++j) {
-            const double lj = dg[j];
-            rank += (lj > li) || (lj == li && j < i);
+    double* Vs = shd;   // sorted eigenvectors (K x K, column-major)
+    if (!vpre) {
+        int sweeps = 0;
+        const bool conv = jacobi_lds(A, V, A2, V2, rot, Ke, &sweeps);
+        if (tid == 0 && !conv && flags) atomicOr(flags, RHOSVD_FLAG_EVD_NOCONV);
+        // the stand-alone EVD reports its sweep count in bits 16..23 of flags
+        if (tid == 0 && flags && !q) atomicOr(flags, static_cast<uint32_t>(sweeps & 0xff) << 16);
+        for (int i = tid; i < K; i += kBlock) dg[i] = A[i * Ke + i];
+        __syncthreads();
+        Vs = (A == shd) ? A2 : shd;   // a free buffer
+        for (int i = tid; i < K; i += kBlock) {
+            const double li = dg[i];
+            int rank = 0;
+            for (int j = 0; j < K; ++j) {
+                const double lj = dg[j];
+                rank += (lj > li) || (lj == li && j < i);
+            }
+            lam[rank] = li;
+            for (int k = 0; k < K; ++k) Vs[rank * K + k] = V[k * Ke + i];
         }
-        lam[rank] = li;
-        for (int k = 0; k < K; ++k) Vs[rank * K + k] = V[k * Ke + i];
+        __syncthreads();
     }
-    __syncthreads();
     if (v_out)
         for (int e = tid; e < K * K; e += kBlock) v_out[e] = Vs[e];
     if (lam_out)
@@ -795,21 +1126,63 @@ size_t evd_qwork_doubles(int K, int64_t I) {
     return static_cast<size_t>((I + 15) & ~static_cast<int64_t>(15)) * ((K + 15) & ~15);
 }
 
+static bool evd_use_jacobi() {
+    const char* e = std::getenv("RHOSVD_EVD");
+    return e != nullptr && std::strcmp(e, "jacobi") == 0;
+}
+
+static hipError_t launch_evd_tri(const double* c, int K, double* v, double* lam, uint32_t* flags,
+                                 int report_iters, hipStream_t s) {
+    const size_t lds = evd_tri_lds_doubles(K) * sizeof(double);
+    if (lds + kStaticLdsMargin > kLdsLimit) return hipErrorInvalidValue;
+#define RH_TRI_CASE(KBV)                                                                        \
+    case KBV:                                                                                   \
+        hipLaunchKernelGGL(k_evd_tri<KBV>, dim3(1), dim3(kBlock), lds, s, c, K, v, lam, flags, \
+                           report_iters);                                                       \
+        break;
+    switch ((K + 7) & ~7) {
+        RH_TRI_CASE(8)
+        RH_TRI_CASE(16)
+        RH_TRI_CASE(24)
+        RH_TRI_CASE(32)
+        RH_TRI_CASE(40)
+        RH_TRI_CASE(48)
+        RH_TRI_CASE(56)
+        RH_TRI_CASE(64)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef RH_TRI_CASE
+    return hipGetLastError();
+}
+
 // u64: I16 x K16 doubles of device scratch, used when Q does not fit in LDS.
+// vwork / lwork: K x K and K doubles for the eigenpairs of the tridiagonal
+// method (Jacobi runs inside the factor kernel when they are null or when
+// RHOSVD_EVD=jacobi).
 hipError_t launch_evd_factor(bool dbl, const double* c, int K, double* v_out, double* lam_out,
                              uint32_t* flags, const void* q, int64_t I, int R, int use_v,
-                             void* u_out, void* m_out, double* sigma, double* u64, hipStream_t s) {
+                             void* u_out, void* m_out, double* sigma, double* u64,
+                             double* vwork, double* lwork, hipStream_t s) {
     if (K < 1 || K > 64) return hipErrorInvalidValue;
     if (q && (I < 1 || I > (1 << 24) || R < 1 || R > K)) return hipErrorInvalidValue;
     const bool staged = q != nullptr && evd_lds_bytes(K, I, true) + kStaticLdsMargin <= kLdsLimit;
     if (q && !staged && !u64) return hipErrorInvalidValue;
     const size_t lds = evd_lds_bytes(K, I, staged);
     if (lds + kStaticLdsMargin > kLdsLimit) return hipErrorInvalidValue;
+    const double* vpre = nullptr;
+    const double* lpre = nullptr;
+    if (vwork && lwork && !evd_use_jacobi()) {
+        const hipError_t err = launch_evd_tri(c, K, vwork, lwork, flags, 0, s);
+        if (err != hipSuccess) return err;
+        vpre = vwork;
+        lpre = lwork;
+    }
     const int Ii = static_cast<int>(I);
 #define RH_EVD_LAUNCH(T, ST)                                                                      \
     hipLaunchKernelGGL((k_evd_factor<T, ST>), dim3(1), dim3(kBlock), lds, s, c, K, v_out, lam_out, \
                        flags, static_cast<const T*>(q), Ii, R, use_v, static_cast<T*>(u_out),     \
-                       static_cast<T*>(m_out), sigma, u64)
+                       static_cast<T*>(m_out), sigma, u64, vpre, lpre)
     if (dbl) {
         if (staged) RH_EVD_LAUNCH(double, true); else RH_EVD_LAUNCH(double, false);
     } else {
@@ -821,8 +1194,10 @@ hipError_t launch_evd_factor(bool dbl, const double* c, int K, double* v_out, do
 
 hipError_t launch_evd(const double* c, int K, double* v, double* lambda, uint32_t* flags,
                       hipStream_t s) {
+    if (K < 1 || K > 64) return hipErrorInvalidValue;
+    if (!evd_use_jacobi()) return launch_evd_tri(c, K, v, lambda, flags, 1, s);
     return launch_evd_factor(true, c, K, v, lambda, flags, nullptr, 0, 0, 0, nullptr, nullptr,
-                             nullptr, nullptr, s);
+                             nullptr, nullptr, nullptr, nullptr, s);
 }
 
 }  // namespace rh

@@ -454,7 +454,7 @@ int32_t run_r_sthosvd(const Plan& pl, const Buffers& b, const void* x, const rho
         RH_HIP(rh::launch_gram_reduce(dbl, b.part, st.gt.grid, st.K, st.gt.K_pad, b.C, s));
         RH_HIP(rh::launch_evd_factor(dbl, b.C, st.K, nullptr, nullptr, &b.rep->flags, b.qT, st.I,
                                      st.R, 1, out->factors[st.n], b.M, &b.rep->sigma[st.n][0],
-                                     b.u64, s));
+                                     b.u64, b.V, b.lam, s));
         void* dst = (si == N - 1) ? out->core : ((si % 2 == 0) ? b.ping : b.pong);
         rc = ttm(pl, st.gtr, b.B, b.M, dst, nullptr, s, pl.rotated ? 1 : 0);
         if (rc != RHOSVD_OK) return rc;
@@ -504,7 +504,7 @@ int32_t run_rp_hosvd(const Plan& pl, const Buffers& b, const void* x, const rhos
         RH_HIP(rh::launch_evd_factor(dbl, b.C, st.K, nullptr, nullptr, &b.rep->flags,
                                      at(b.qstore, qoff[n], e), st.I, st.R, pl.any_k_gt_r ? 1 : 0,
                                      out->factors[n], at(b.mstore, moff[n], e),
-                                     &b.rep->sigma[n][0], b.u64, s));
+                                     &b.rep->sigma[n][0], b.u64, b.V, b.lam, s));
     }
     // G = H x_n M_n^T
     src = H;

@@ -153,8 +153,12 @@ def test_fullsize_decomposition(data):
         print(f"[fullsize] {prec}: E {res.rel_error:.7f}, explicit {e_exp:.7f}, closed form {e_closed:.7f}",
               flush=True)
         # the identity E^2 = 1 - norm(G)^2 / norm(X)^2 holds for orthonormal
-        # factors; FP32 factors (norm(U^T U - I) ~ 1e-7) move it by ~1e-7 / E
-        assert abs(e_exp - res.rel_error) <= 1e-5
+        # factors; FP32 factors (norm(U^T U - I) ~ 1e-7) move it by ~1e-7 / E.
+        # The bf16 path forms G with split (hi + lo) operands that carry about
+        # 2^-17 relative error per entry and mode, so its norm(G) is off by a
+        # few 1e-6 relative and the identity by ~1e-5 in E (0.7e-5 and 1.2e-5
+        # seen at this size): 1e-4 for bf16
+        assert abs(e_exp - res.rel_error) <= (1e-5 if prec == "f32" else 1e-4)
         assert abs(res.rel_error - e_closed) <= 1e-3
         errs[prec] = res.rel_error
     assert abs(errs["bf16"] - errs["f32"]) <= 1e-4

@@ -133,6 +133,71 @@ __device__ void mfma_gram(const double* W, const CqrGeom g, double* G, double sh
     }
 }
 
+// The same Gram for NT = KP16 / 16 >= 3 column tiles, split by rows: wave w
+// takes the rows [w I16 / 4, (w + 1) I16 / 4) and forms all NT (NT + 1) / 2
+// upper tiles, each k-step loading its NT fragments once.  Waves 1..3 leave
+// their tiles in red (3 NP 256 doubles: the G and X region, which holds
+// 2 KP16^2 >= 3 NP 256 for NT >= 3); wave 0 adds them in wave order and
+// writes G.  X must be rewritten (zero padding included) before its next use.
+template <int NT>
+__device__ void mfma_gram_rows(const double* W, const CqrGeom g, double* G, double* red,
+                               double shift, double* diag0) {
+    constexpr int NP = NT * (NT + 1) / 2;
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    const int m = lane & 15, kq = lane >> 4;
+    const int rows = g.I16 >> 2;
+    const double* wp = W + (wave * rows + kq) * g.P + m;
+    f64x4 acc[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) acc[p] = zero4<f64x4>();
+    for (int i0 = 0; i0 < rows; i0 += 4) {
+        double a[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) a[t] = wp[i0 * g.P + 16 * t];
+        int p = 0;
+#pragma unroll
+        for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+            for (int tb = ta; tb < NT; ++tb) {
+                acc[p] = Mma<double>::step(a[ta], a[tb], acc[p]);
+                ++p;
+            }
+    }
+    if (wave > 0) {
+        double* rw = red + static_cast<size_t>(wave - 1) * NP * 256 + lane * 4;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) *reinterpret_cast<f64x4*>(rw + p * 256) = acc[p];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int w = 0; w < 3; ++w)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const f64x4 o = *reinterpret_cast<const f64x4*>(red + (w * NP + p) * 256 + lane * 4);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[p][r] += o[r];
+            }
+        int p = 0;
+#pragma unroll
+        for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+            for (int tb = ta; tb < NT; ++tb) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * ta + Mma<double>::row(kq, r), col = 16 * tb + m;
+                    if (row < g.K && col < g.K) {
+                        const double x = acc[p][r] + (row == col ? shift : 0.0);
+                        G[row * g.KP16 + col] = x;
+                        G[col * g.KP16 + row] = x;
+                        if (row == col) diag0[row] = x;
+                    }
+                }
+                ++p;
+            }
+    }
+}
+
 // One wave.  Right-looking Cholesky G = L L^T with lane i holding row i:
 // step j takes the pivot from lane j, L(j+1, j) by a lane read (the next
 // pivot depends on nothing else), and the rest of column j through S.  Then
@@ -167,8 +232,11 @@ __device__ bool wave_chol_inv(const double* G, const double* diag0, double* S, d
                 if (j + 1 < KB) g[j + 1] = fma(-l, readlane_d(l, j + 1), g[j + 1]);
                 if (j + 2 < KB) {
                     if (lane < KB) S[j * XP + lane] = l;
+                    double sr[KB];
 #pragma unroll
-                    for (int c = j + 2; c < KB; ++c) g[c] = fma(-l, S[j * XP + c], g[c]);
+                    for (int c = j + 2; c < KB; ++c) sr[c] = S[j * XP + c];
+#pragma unroll
+                    for (int c = j + 2; c < KB; ++c) g[c] = fma(-l, sr[c], g[c]);
                 }
             }
         }
@@ -184,17 +252,23 @@ __device__ bool wave_chol_inv(const double* G, const double* diag0, double* S, d
 #pragma unroll
     for (int m = KB - 1; m >= 0; --m) {
         if (m < K) {
+            double sr[KB];
+#pragma unroll
+            for (int k = 0; k < m; ++k) sr[k] = S[m * XP + k];
             const double x = ((li == m ? 1.0 : 0.0) - acc[m]) * readlane_d(dinvl, m);
             acc[m] = x;
 #pragma unroll
-            for (int k = 0; k < m; ++k) acc[k] = fma(x, S[m * XP + k], acc[k]);
+            for (int k = 0; k < m; ++k) acc[k] = fma(x, sr[k], acc[k]);
         } else {
             acc[m] = 0.0;
         }
     }
-    if (lane < KB && li < K) {
+    // all of X's XP x XP block: zero outside K x K
+    for (int r = lane; r < XP; r += kWave) {
+        const bool in = r < K;
 #pragma unroll
-        for (int c = 0; c < KB; ++c) X[lane * XP + c] = acc[c];
+        for (int c = 0; c < KB; ++c) X[r * XP + c] = in ? acc[c] : 0.0;
+        for (int c = KB; c < XP; ++c) X[r * XP + c] = 0.0;
     }
     return true;
 }
@@ -233,6 +307,42 @@ __device__ void mfma_apply(double* W, const CqrGeom g, const double* X) {
     }
 }
 
+// W <- W X^T as mfma_apply, with X's fragments (lower triangular: column tile
+// cb needs k < 16 cb + 16) held in registers across the row blocks and each
+// block's W fragments loaded at once.
+template <int NT>
+__device__ void mfma_apply_rows(double* W, const CqrGeom g, const double* X) {
+    constexpr int NK = 4 * NT;   // k-steps of 4 over KP16
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    const int m = lane & 15, kq = lane >> 4;
+    double xb[NT][NK];
+#pragma unroll
+    for (int cb = 0; cb < NT; ++cb)
+#pragma unroll
+        for (int st = 0; st < NK; ++st)
+            xb[cb][st] = (st < 4 * cb + 4) ? X[(16 * cb + m) * g.KP16 + 4 * st + kq] : 0.0;
+    const int nrb = g.I16 >> 4;
+    for (int rb = wave; rb < nrb; rb += kBlock / kWave) {
+        double a[NK];
+#pragma unroll
+        for (int st = 0; st < NK; ++st) a[st] = W[(16 * rb + m) * g.P + 4 * st + kq];
+        f64x4 acc[NT];
+#pragma unroll
+        for (int cb = 0; cb < NT; ++cb) {
+            acc[cb] = zero4<f64x4>();
+#pragma unroll
+            for (int st = 0; st < 4 * cb + 4; ++st) acc[cb] = Mma<double>::step(a[st], xb[cb][st], acc[cb]);
+        }
+#pragma unroll
+        for (int cb = 0; cb < NT; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * rb + Mma<double>::row(kq, r), col = 16 * cb + m;
+                W[row * g.P + col] = acc[cb][r];
+            }
+    }
+}
+
 __host__ __device__ inline CqrGeom cqr_geom(int I, int K) {
     CqrGeom g;
     g.I = I;
@@ -267,20 +377,25 @@ __global__ __launch_bounds__(kBlock) void k_cqr(const double* __restrict__ y, in
             if (i >= I || k >= K) W[i * g.P + k] = 0.0;
     for (int e = tid; e < g.KP16 * g.KP16; e += kBlock) X[e] = 0.0;
     {
+        // element e = k I + i of y; (k, i) advanced by kBlock per step
         const int n = I * K;
-        for (int e0 = tid; e0 < n; e0 += 8 * kBlock) {
-            double v[8];
+        for (int e0 = tid; e0 < n; e0 += 32 * kBlock) {
+            double v[32];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < 32; ++u) {
                 const int e = e0 + u * kBlock;
                 v[u] = y[e < n ? e : n - 1];
             }
+            int k = e0 / I, i = e0 - k * I;
+            const int dk = kBlock / I, di = kBlock - dk * I;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * kBlock;
-                if (e < n) {
-                    const int k = e / I, i = e - k * I;
-                    W[i * g.P + k] = v[u];
+            for (int u = 0; u < 32; ++u) {
+                if (e0 + u * kBlock < n) W[i * g.P + k] = v[u];
+                i += di;
+                k += dk;
+                if (i >= I) {
+                    i -= I;
+                    ++k;
                 }
             }
         }
@@ -293,8 +408,13 @@ __global__ __launch_bounds__(kBlock) void k_cqr(const double* __restrict__ y, in
     bool shifted = false, ok = true;
     int rounds = 2;
     double shift = 0.0;
+    // column tiles: K in (KB - 8, KB] gives KP16 = 16 NT
+    constexpr int NT = (KB + 15) / 16;
     for (int r = 0; r < rounds; ++r) {
-        mfma_gram(W, g, G, shift, diag0);
+        if constexpr (NT >= 3)
+            mfma_gram_rows<NT>(W, g, G, G, shift, diag0);
+        else
+            mfma_gram(W, g, G, shift, diag0);
         __syncthreads();
         if (wave == 0) {
             const bool okw = wave_chol_inv<KB>(G, diag0, G, X, K, g.KP16);
@@ -317,7 +437,10 @@ __global__ __launch_bounds__(kBlock) void k_cqr(const double* __restrict__ y, in
             break;
         }
         shift = 0.0;
-        mfma_apply(W, g, X);
+        if constexpr (NT >= 3)
+            mfma_apply_rows<NT>(W, g, X);
+        else
+            mfma_apply(W, g, X);
         __syncthreads();
     }
     if (ok) {
@@ -664,7 +787,7 @@ __device__ bool jacobi_lds(double*& A, double*& V, double* A2, double* V2, doubl
 //      kept away from zero by pivmin), the quad adds its flags and keeps the
 //      eighth that holds lambda_j; 18 steps take the Gershgorin interval to
 //      about 1e-16 of norm(T).
-//   3. wave 0, lane j = eigenvalue j: three steps of inverse iteration from a
+//   3. wave 0, lane j = eigenvalue j: two steps of inverse iteration from a
 //      fixed pseudo-random start, each a solve with T - lambda_j I factored
 //      by Gaussian elimination with row interchanges (the factor kept in LDS,
 //      the vector in registers), normalised, then Gram-Schmidt against the
@@ -675,7 +798,7 @@ __device__ bool jacobi_lds(double*& A, double*& V, double* A2, double* V2, doubl
 // eigenvalue) and lambda (descending); with report_iters, bits 16..23 of
 // flags receive the inverse-iteration count.  LDS: evd_tri_lds_doubles(K).
 // ---------------------------------------------------------------------------
-constexpr int kTriIters = 3;
+constexpr int kTriIters = 2;   // each step shrinks the error by about eps norm(T) / gap
 constexpr int kBisectSteps = 18;
 constexpr int kTriP = RHOSVD_MAX_K / 2;   // row pitch of the LDS vectors (64 >= K)
 
@@ -683,13 +806,34 @@ __host__ __device__ inline size_t evd_tri_lds_doubles(int K) {
     return static_cast<size_t>(kTriP) * kTriP + 3 * static_cast<size_t>(K) * kWave + 6 * kTriP;
 }
 
-// value of a[idx] for a uniform runtime idx (registers cannot be indexed)
+// value of a[idx] for a uniform runtime idx (registers cannot be indexed):
+// four independent select chains, then one of the four by idx & 3
 template <int KB>
 __device__ __forceinline__ double pick(const double (&a)[KB], int idx) {
-    double r = 0.0;
+    double r[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int c = 0; c < KB; ++c) r = (c == idx) ? a[c] : r;
-    return r;
+    for (int c = 0; c < KB; ++c) r[c & 3] = (c == idx) ? a[c] : r[c & 3];
+    const int m = idx & 3;
+    return m == 0 ? r[0] : (m == 1 ? r[1] : (m == 2 ? r[2] : r[3]));
+}
+
+// Sum over the wave, the same value in every lane: butterflies inside quads
+// and rows of 16 on DPP lane moves (no LDS), then the four row sums.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
+                                                       static_cast<unsigned>(lo)));
+}
+
+__device__ __forceinline__ double wave_total(double v) {
+    v += dpp_d<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_d<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_d<0x124>(v);   // row_ror:4
+    v += dpp_d<0x128>(v);   // row_ror:8
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
 // Start vector of inverse iteration: entries in [-1, 1) from a 32-bit hash
@@ -741,7 +885,7 @@ __global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ c
             const double x = lane > k ? ak : 0.0;                 // A(k+1:, k)
             const double akk = readlane_d(ak, k);
             const double x1 = readlane_d(ak, k + 1);
-            const double tail = wave_sum(lane > k + 1 ? x * x : 0.0);
+            const double tail = wave_total(lane > k + 1 ? x * x : 0.0);
             double beta = x1, t = 0.0, scale = 0.0;
             if (tail > 0.0) {
                 const double nrm = sqrt(fma(x1, x1, tail));
@@ -763,7 +907,7 @@ __global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ c
 #pragma unroll
                 for (int j = 0; j < KB; ++j) pv = fma(a[j], bc[j], pv);
                 const double p = lane > k ? t * pv : 0.0;
-                const double kk = 0.5 * t * wave_sum(p * v);
+                const double kk = 0.5 * t * wave_total(p * v);
                 const double w = p - kk * v;
                 if (lane < K) bw[lane] = w;
 #pragma unroll
@@ -801,10 +945,12 @@ __global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ c
     {
         const double tn = stats[0], pivmin = stats[1];
         const int j = tid >> 2, sub = tid & 3;
+        // rows past K: d huge and e zero keep their pivots positive, so they
+        // never count and need no masking
         double d[KB], e2[KB];
 #pragma unroll
         for (int i = 0; i < KB; ++i) {
-            d[i] = dd[i];
+            d[i] = i < K ? dd[i] : 1e300;
             e2[i] = ee[i] * ee[i];                 // ee is zero past K - 2
         }
         double lo = -tn - 4.0 * pivmin - 2.2e-16 * 4.0 * K * tn - 1e-300;
@@ -819,16 +965,12 @@ __global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ c
             int ca = qa < 0.0, cb = qb < 0.0;
 #pragma unroll
             for (int i = 1; i < KB; ++i) {
-                // (rows past K are computed and dropped)
-                double na = fma(-e2[i - 1], rcp_nr(qa), d[i] - xa);
-                double nb = fma(-e2[i - 1], rcp_nr(qb), d[i] - xb);
-                na = fabs(na) < pivmin ? -pivmin : na;
-                nb = fabs(nb) < pivmin ? -pivmin : nb;
-                const bool in = i < K;
-                qa = in ? na : qa;
-                qb = in ? nb : qb;
-                ca += (in && na < 0.0) ? 1 : 0;
-                cb += (in && nb < 0.0) ? 1 : 0;
+                qa = fma(-e2[i - 1], rcp_nr(qa), d[i] - xa);
+                qb = fma(-e2[i - 1], rcp_nr(qb), d[i] - xb);
+                qa = fabs(qa) < pivmin ? -pivmin : qa;
+                qb = fabs(qb) < pivmin ? -pivmin : qb;
+                ca += qa < 0.0 ? 1 : 0;
+                cb += qb < 0.0 ? 1 : 0;
             }
             // points 2 sub + 1 and 2 sub + 2 of 1..7 (point 8 is hi itself)
             int nle = (ca <= j ? 1 : 0) + ((sub < 3 && cb <= j) ? 1 : 0);

@@ -69,6 +69,7 @@ struct ColGeom {
     int64_t I, J;
     int K, nch, nb, variant, rowp;
     int split;            // the tensor split into hi + lo bf16 in Z = S^T M (CT_BF16X3)
+    int red3;             // LDS holds three waves' Y accumulators for the final reduction
     size_t mfr_bytes, lds_bytes;
     int64_t nblocks;
     int grid, I_pad, K_pad;

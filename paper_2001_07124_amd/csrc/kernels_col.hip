@@ -191,7 +191,22 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
     __bf16* tile = reinterpret_cast<__bf16*>(smem + g.mfr_bytes) +
                    static_cast<size_t>(wave) * 32 * rowp;
     if (OP != OP_SKETCH) {
-        const float* __restrict__ m = static_cast<const float*>(a.mat);
+        // M (I x K, column-major) staged in LDS past the fragments with 16-byte
+        // loads, then the fragments built from LDS
+        const float* __restrict__ mg = static_cast<const float*>(a.mat);
+        float* ms = reinterpret_cast<float*>(smem + g.mfr_bytes);
+        if (mg) {
+            const int n = I * K;
+            if ((reinterpret_cast<uintptr_t>(mg) & 15) == 0) {
+                for (int e = 4 * tid; e + 3 < n; e += 4 * kColThreads)
+                    *reinterpret_cast<f32x4*>(ms + e) = *reinterpret_cast<const f32x4*>(mg + e);
+                for (int e = (n & ~3) + tid; e < n; e += kColThreads) ms[e] = mg[e];
+            } else {
+                for (int e = tid; e < n; e += kColThreads) ms[e] = mg[e];
+            }
+            __syncthreads();
+        }
+        const float* m = mg ? ms : nullptr;
         for (int idx = tid; idx < NCH * NB * 64; idx += kColThreads) {
             const int ln = idx & 63, hn = idx >> 6;
             const int h = hn / NB, nb = hn - h * NB;
@@ -433,7 +448,39 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
     float* red = reinterpret_cast<float*>(smem);
     const size_t gidx = blockIdx.x;
     const int I_pad = 32 * NCH, K_pad = 16 * NB;
-    if (OP != OP_TTM) {
+    if (OP != OP_TTM && g.red3) {
+        // waves 1..3 store their accumulators (16-byte pieces) in regions
+        // 0..2; wave 0 adds them in wave order, ((a0 + a1) + a2) + a3, and
+        // writes the partial from registers
+        const int region = K_pad * I_pad;
+        if (wave > 0) {
+            float* rw = red + (wave - 1) * region;
+#pragma unroll
+            for (int rt = 0; rt < AR; ++rt)
+#pragma unroll
+                for (int nb = 0; nb < AN; ++nb)
+                    *reinterpret_cast<f32x4*>(rw + (16 * nb + c16) * I_pad + 16 * rt + 4 * grp) = acc[rt][nb];
+        }
+        __syncthreads();
+        if (wave == 0) {
+            float* __restrict__ py = static_cast<float*>(a.part_y) + gidx * K_pad * I_pad;
+#pragma unroll
+            for (int rt = 0; rt < AR; ++rt)
+#pragma unroll
+                for (int nb = 0; nb < AN; ++nb) {
+                    const int off = (16 * nb + c16) * I_pad + 16 * rt + 4 * grp;
+                    f32x4 v = acc[rt][nb];
+#pragma unroll
+                    for (int w = 0; w < kColWaves - 1; ++w) {
+                        const f32x4 o = *reinterpret_cast<const f32x4*>(red + w * region + off);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) v[e] += o[e];
+                    }
+                    *reinterpret_cast<f32x4*>(py + off) = v;
+                }
+        }
+        __syncthreads();
+    } else if (OP != OP_TTM) {
         for (int w = 0; w < kColWaves; ++w) {
             if (wave == w) {
 #pragma unroll
@@ -517,10 +564,21 @@ bool plan_col(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu
     const size_t tiles = (op != OP_TTM) ? static_cast<size_t>(kColWaves) * 32 * g->rowp * 2
                                         : static_cast<size_t>(kColWaves) * 32 * 16 * NB * 4;
     size_t lds = g->mfr_bytes + tiles;
+    // M staged past the fragments at the start
+    if (op != OP_SKETCH && g->mfr_bytes + static_cast<size_t>(I) * K * 4 > lds)
+        lds = g->mfr_bytes + static_cast<size_t>(I) * K * 4;
     const size_t red = (op != OP_TTM) ? static_cast<size_t>(32 * NCH) * 16 * NB * 4
                                       : static_cast<size_t>(16 * NB) * 16 * NB * 4;
     if (red > lds) lds = red;
     if (lds + kStaticLdsMargin > kLdsLimit) return false;
+    g->red3 = 0;
+    if (op != OP_TTM) {
+        const size_t l3 = 3 * red > lds ? 3 * red : lds;
+        if (l3 + kStaticLdsMargin <= kLdsLimit) {
+            lds = l3;
+            g->red3 = 1;
+        }
+    }
     g->lds_bytes = lds;
     g->nblocks = (T + 31) / 32;
     const int64_t wgs = (g->nblocks + kColWaves - 1) / kColWaves;

@@ -1150,10 +1150,32 @@ __global__ __launch_bounds__(kBlock) void k_evd_factor(const double* __restrict_
         }
     }
     if (q) {
+        // Qs row-major (pitch K16): the padding first, then Q read in its own
+        // column-major order (coalesced), eight loads in flight per thread
         for (int e = tid; e < I16 * K16; e += kBlock) {
-            // (a row of Q per K16 consecutive entries)
             const int i = e / K16, k = e - i * K16;
-            Qs[e] = (i < I && k < K) ? static_cast<double>(q[static_cast<int64_t>(k) * I + i]) : 0.0;
+            if (i >= I || k >= K) Qs[e] = 0.0;
+        }
+        const int n = I * K;
+        for (int e0 = tid; e0 < n; e0 += 8 * kBlock) {
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * kBlock;
+                v[u] = q[e < n ? e : n - 1];
+            }
+            int k = e0 / I, i = e0 - k * I;
+            const int dk = kBlock / I, di = kBlock - dk * I;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (e0 + u * kBlock < n) Qs[i * K16 + k] = static_cast<double>(v[u]);
+                i += di;
+                k += dk;
+                if (i >= I) {
+                    i -= I;
+                    ++k;
+                }
+            }
         }
     }
     __syncthreads();
@@ -1186,24 +1208,34 @@ __global__ __launch_bounds__(kBlock) void k_evd_factor(const double* __restrict_
     if (!q) return;
     // U = Q V_R (FP64), 16 x 16 tiles, written over Q's rows (pitch K16 >= R)
     {
+        // V_R's fragments stay in registers for all row blocks (K16 <= 64,
+        // R <= 64); each row block loads its Q fragments at once
         const int m = lane & 15, kq = lane >> 4;
-        const int nib = I16 >> 4, nrb = (R + 15) >> 4;
+        const int nib = I16 >> 4, nrb = (R + 15) >> 4, nst = K16 >> 2;
+        double vb[4][16];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int st = 0; st < 16; ++st) {
+                const int k = 4 * st + kq, rcol = 16 * rb + m;
+                double b = 0.0;
+                if (rb < nrb && st < nst && rcol < R && k < K)
+                    b = use_v ? Vs[rcol * K + k] : (k == rcol ? 1.0 : 0.0);
+                vb[rb][st] = b;
+            }
         for (int ib = wave; ib < nib; ib += kBlock / kWave) {
             const double* qa = Qs + (16 * ib + m) * K16 + kq;
+            double a[16];
+#pragma unroll
+            for (int st = 0; st < 16; ++st) a[st] = st < nst ? qa[4 * st] : 0.0;
             f64x4 acc[4];
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) acc[rb] = zero4<f64x4>();
-            for (int k0 = 0; k0 < K16; k0 += 4) {
-                const double a = qa[k0];
-                const int k = k0 + kq;
+            for (int rb = 0; rb < 4; ++rb) {
+                acc[rb] = zero4<f64x4>();
+                if (rb < nrb) {
 #pragma unroll
-                for (int rb = 0; rb < 4; ++rb) {
-                    if (rb < nrb) {
-                        const int rcol = 16 * rb + m;
-                        double b = 0.0;
-                        if (rcol < R && k < K) b = use_v ? Vs[rcol * K + k] : (k == rcol ? 1.0 : 0.0);
-                        acc[rb] = Mma<double>::step(a, b, acc[rb]);
-                    }
+                    for (int st = 0; st < 16; ++st)
+                        if (st < nst) acc[rb] = Mma<double>::step(a[st], vb[rb][st], acc[rb]);
                 }
             }
 #pragma unroll

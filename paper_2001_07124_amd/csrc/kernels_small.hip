@@ -92,6 +92,7 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 
 struct CqrGeom {
     int I, K, I16, KP16, P;
+    int GP;   // pitch of G and X (KP16 + 1: odd, so a column walk spreads over the banks)
 };
 
 // G (pitch KP16, K x K block written) = W^T W + shift I; diag0 = diag(G).
@@ -125,8 +126,8 @@ __device__ void mfma_gram(const double* W, const CqrGeom g, double* G, double sh
             const int row = 16 * ta + Mma<double>::row(kq, r), col = 16 * tb + m;
             if (row < g.K && col < g.K) {
                 const double x = (acc0[r] + acc1[r]) + (row == col ? shift : 0.0);
-                G[row * g.KP16 + col] = x;
-                G[col * g.KP16 + row] = x;
+                G[row * g.GP + col] = x;
+                G[col * g.GP + row] = x;
                 if (row == col) diag0[row] = x;
             }
         }
@@ -137,7 +138,7 @@ __device__ void mfma_gram(const double* W, const CqrGeom g, double* G, double sh
 // takes the rows [w I16 / 4, (w + 1) I16 / 4) and forms all NT (NT + 1) / 2
 // upper tiles, each k-step loading its NT fragments once.  Waves 1..3 leave
 // their tiles in red (3 NP 256 doubles: the G and X region, which holds
-// 2 KP16^2 >= 3 NP 256 for NT >= 3); wave 0 adds them in wave order and
+// 2 KP16 (KP16 + 1) >= 3 NP 256 for NT >= 3); wave 0 adds them in wave order and
 // writes G.  X must be rewritten (zero padding included) before its next use.
 template <int NT>
 __device__ void mfma_gram_rows(const double* W, const CqrGeom g, double* G, double* red,
@@ -188,8 +189,8 @@ __device__ void mfma_gram_rows(const double* W, const CqrGeom g, double* G, doub
                     const int row = 16 * ta + Mma<double>::row(kq, r), col = 16 * tb + m;
                     if (row < g.K && col < g.K) {
                         const double x = acc[p][r] + (row == col ? shift : 0.0);
-                        G[row * g.KP16 + col] = x;
-                        G[col * g.KP16 + row] = x;
+                        G[row * g.GP + col] = x;
+                        G[col * g.GP + row] = x;
                         if (row == col) diag0[row] = x;
                     }
                 }
@@ -207,7 +208,7 @@ __device__ void mfma_gram_rows(const double* W, const CqrGeom g, double* G, doub
 // above 1e-14 of its original diagonal.
 template <int KB>
 __device__ bool wave_chol_inv(const double* G, const double* diag0, double* S, double* X, int K,
-                              int XP) {
+                              int XP, int XN) {
     const int lane = threadIdx.x & 63;
     const int li = lane < KB ? lane : KB - 1;
     double g[KB];
@@ -263,12 +264,12 @@ __device__ bool wave_chol_inv(const double* G, const double* diag0, double* S, d
             acc[m] = 0.0;
         }
     }
-    // all of X's XP x XP block: zero outside K x K
-    for (int r = lane; r < XP; r += kWave) {
+    // all of X's XN x XN block (pitch XP): zero outside K x K
+    for (int r = lane; r < XN; r += kWave) {
         const bool in = r < K;
 #pragma unroll
         for (int c = 0; c < KB; ++c) X[r * XP + c] = in ? acc[c] : 0.0;
-        for (int c = KB; c < XP; ++c) X[r * XP + c] = 0.0;
+        for (int c = KB; c < XN; ++c) X[r * XP + c] = 0.0;
     }
     return true;
 }
@@ -283,7 +284,7 @@ __device__ void mfma_apply(double* W, const CqrGeom g, const double* X) {
     const int nrb = g.I16 >> 4;
     for (int rb = wave; rb < nrb; rb += kBlock / kWave) {
         const double* wa = W + (16 * rb + m) * g.P + kq;
-        const double* xb = X + m * g.KP16 + kq;
+        const double* xb = X + m * g.GP + kq;
         f64x4 acc[4];
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) acc[cb] = zero4<f64x4>();
@@ -292,7 +293,7 @@ __device__ void mfma_apply(double* W, const CqrGeom g, const double* X) {
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb)
                 if (cb < nt && k0 < 16 * cb + 16)
-                    acc[cb] = Mma<double>::step(a, xb[16 * cb * g.KP16 + k0], acc[cb]);
+                    acc[cb] = Mma<double>::step(a, xb[16 * cb * g.GP + k0], acc[cb]);
         }
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
@@ -320,7 +321,7 @@ __device__ void mfma_apply_rows(double* W, const CqrGeom g, const double* X) {
     for (int cb = 0; cb < NT; ++cb)
 #pragma unroll
         for (int st = 0; st < NK; ++st)
-            xb[cb][st] = (st < 4 * cb + 4) ? X[(16 * cb + m) * g.KP16 + 4 * st + kq] : 0.0;
+            xb[cb][st] = (st < 4 * cb + 4) ? X[(16 * cb + m) * g.GP + 4 * st + kq] : 0.0;
     const int nrb = g.I16 >> 4;
     for (int rb = wave; rb < nrb; rb += kBlock / kWave) {
         double a[NK];
@@ -350,6 +351,7 @@ __host__ __device__ inline CqrGeom cqr_geom(int I, int K) {
     g.I16 = (I + 15) & ~15;
     g.KP16 = (K + 15) & ~15;
     g.P = g.KP16 + 1;
+    g.GP = g.KP16 + 1;
     return g;
 }
 
@@ -365,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_cqr(const double* __restrict__ y, in
     const CqrGeom g = cqr_geom(I, K);
     double* W = shd;
     double* G = W + cqr_w_doubles(g);      // Gram, then the broadcast columns / rows of L
-    double* X = G + g.KP16 * g.KP16;
+    double* X = G + g.KP16 * g.GP;
     __shared__ double diag0[RHOSVD_MAX_K];
     __shared__ double tau_s[RHOSVD_MAX_K], alpha_s[RHOSVD_MAX_K];
     __shared__ double red[kBlock / kWave];
@@ -375,7 +377,7 @@ __global__ __launch_bounds__(kBlock) void k_cqr(const double* __restrict__ y, in
     for (int i = wave; i < g.I16; i += kBlock / kWave)
         for (int k = lane; k < g.P; k += kWave)
             if (i >= I || k >= K) W[i * g.P + k] = 0.0;
-    for (int e = tid; e < g.KP16 * g.KP16; e += kBlock) X[e] = 0.0;
+    for (int e = tid; e < g.KP16 * g.GP; e += kBlock) X[e] = 0.0;
     {
         // element e = k I + i of y; (k, i) advanced by kBlock per step
         const int n = I * K;
@@ -417,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void k_cqr(const double* __restrict__ y, in
             mfma_gram(W, g, G, shift, diag0);
         __syncthreads();
         if (wave == 0) {
-            const bool okw = wave_chol_inv<KB>(G, diag0, G, X, K, g.KP16);
+            const bool okw = wave_chol_inv<KB>(G, diag0, G, X, K, g.GP, g.KP16);
             if (tid == 0) ok_sh = okw;
         }
         __syncthreads();
@@ -473,7 +475,7 @@ static int cqr_kb(int K) { return (K + 7) & ~7; }
 
 size_t cqr_lds_bytes(int64_t I, int K) {
     const CqrGeom g = cqr_geom(static_cast<int>(I), K);
-    return (cqr_w_doubles(g) + 2 * static_cast<size_t>(g.KP16) * g.KP16) * sizeof(double);
+    return (cqr_w_doubles(g) + 2 * static_cast<size_t>(g.KP16) * g.GP) * sizeof(double);
 }
 
 hipError_t launch_reduce_y(bool dbl, const void* part, int G, int I, int K, int I_pad, int K_pad,

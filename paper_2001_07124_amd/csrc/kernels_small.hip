@@ -151,6 +151,7 @@ __device__ void mfma_gram_rows(const double* W, const CqrGeom g, double* G, doub
     f64x4 acc[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) acc[p] = zero4<f64x4>();
+#pragma unroll 4
     for (int i0 = 0; i0 < rows; i0 += 4) {
         double a[NT];
 #pragma unroll
@@ -373,11 +374,15 @@ __global__ __launch_bounds__(kBlock) void k_cqr(const double* __restrict__ y, in
     __shared__ double red[kBlock / kWave];
     __shared__ int ok_sh;
     const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
-    // zero padding of W and all of X, then Y (coalesced over i)
-    for (int i = wave; i < g.I16; i += kBlock / kWave)
-        for (int k = lane; k < g.P; k += kWave)
-            if (i >= I || k >= K) W[i * g.P + k] = 0.0;
-    for (int e = tid; e < g.KP16 * g.GP; e += kBlock) X[e] = 0.0;
+    // zero padding of W (rows I.. as one range, columns K.. one row per
+    // thread) and all of X, then Y (coalesced over i)
+    {
+        const int r0 = I * g.P, r1 = g.I16 * g.P;
+        for (int e = r0 + tid; e < r1; e += kBlock) W[e] = 0.0;
+        for (int i = tid; i < I; i += kBlock)
+            for (int k = K; k < g.P; ++k) W[i * g.P + k] = 0.0;
+        for (int e = tid; e < g.KP16 * g.GP; e += kBlock) X[e] = 0.0;
+    }
     {
         // element e = k I + i of y; (k, i) advanced by kBlock per step
         const int n = I * K;
@@ -446,14 +451,33 @@ __global__ __launch_bounds__(kBlock) void k_cqr(const double* __restrict__ y, in
         __syncthreads();
     }
     if (ok) {
-        for (int e = tid; e < I * K; e += kBlock) {
-            const int k = e / I, i = e - k * I;
-            const double v = W[i * g.P + k];
-            q64[e] = v;
-            if (dbl)
-                static_cast<double*>(q_out)[e] = v;
-            else
-                static_cast<float*>(q_out)[e] = static_cast<float>(v);
+        // element e = k I + i, eight LDS reads in flight per thread
+        const int n = I * K;
+        const int dk = kBlock / I, di = kBlock - dk * I;
+        for (int e0 = tid; e0 < n; e0 += 8 * kBlock) {
+            int k = e0 / I, i = e0 - k * I;
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                v[u] = (e0 + u * kBlock < n) ? W[i * g.P + k] : 0.0;
+                i += di;
+                k += dk;
+                if (i >= I) {
+                    i -= I;
+                    ++k;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * kBlock;
+                if (e < n) {
+                    q64[e] = v[u];
+                    if (dbl)
+                        static_cast<double*>(q_out)[e] = v[u];
+                    else
+                        static_cast<float*>(q_out)[e] = static_cast<float>(v[u]);
+                }
+            }
         }
     } else {
         householder_qr(y, I, K, work, q64, tau_s, alpha_s, red);

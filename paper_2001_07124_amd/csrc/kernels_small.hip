@@ -929,9 +929,10 @@ __global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ c
             if (t != 0.0) {
                 // v and w vanish at indices <= k, so the whole rows can be used
                 if (lane < K) bc[lane] = v;
-                double pv = 0.0;
+                double pq[4] = {0.0, 0.0, 0.0, 0.0};   // four independent chains
 #pragma unroll
-                for (int j = 0; j < KB; ++j) pv = fma(a[j], bc[j], pv);
+                for (int j = 0; j < KB; ++j) pq[j & 3] = fma(a[j], bc[j], pq[j & 3]);
+                const double pv = (pq[0] + pq[1]) + (pq[2] + pq[3]);
                 const double p = lane > k ? t * pv : 0.0;
                 const double kk = 0.5 * t * wave_total(p * v);
                 const double w = p - kk * v;
@@ -1017,9 +1018,12 @@ __global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ c
         const double ctol = 1e-3 * tn;                         // cluster distance
         const int jl = lane < K ? lane : K - 1;
         const double lj = lam[jl];
-        // cluster id: the number of gaps above ctol below this eigenvalue
+        // cluster id: the number of gaps above ctol below this eigenvalue;
+        // mates: bit m set when eigenvalue m has a later member of its cluster
         int cid = 0;
         for (int q = 1; q <= jl; ++q) cid += (lam[q] - lam[q - 1] > ctol) ? 1 : 0;
+        const bool has_mate = lane + 1 < K && (lam[lane + 1] - lam[lane] <= ctol);
+        uint64_t mates = __ballot(has_mate);
         double* u1 = lu;
         double* u2 = lu + K * kWave;
         double* u3 = lu + 2 * K * kWave;
@@ -1080,9 +1084,8 @@ __global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ c
             // Gram-Schmidt within clusters, in ascending order: vector m is
             // final when its turn comes; the later members of its cluster
             // remove their component along it
-#pragma unroll 1
-            for (int m = 0; m < K - 1; ++m) {
-                if (!(lam[m + 1] - lam[m] <= ctol)) continue;      // uniform: no later cluster mate
+            for (uint64_t mm = mates; mm != 0; mm &= mm - 1) {
+                const int m = __builtin_ctzll(mm);                  // uniform
                 if (lane == m) {
                     double s2 = 0.0;
 #pragma unroll
@@ -1115,10 +1118,10 @@ __global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ c
 #pragma unroll 1
         for (int k = K - 3; k >= 0; --k) {
             const double t = tau[k];
-            double w = 0.0;
+            double wq[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int i = 0; i < KB; ++i) w = fma(hv[k * kTriP + i], z[i], w);
-            w *= t;
+            for (int i = 0; i < KB; ++i) wq[i & 3] = fma(hv[k * kTriP + i], z[i], wq[i & 3]);
+            const double w = ((wq[0] + wq[1]) + (wq[2] + wq[3])) * t;
 #pragma unroll
             for (int i = 0; i < KB; ++i) z[i] = fma(-w, hv[k * kTriP + i], z[i]);
         }

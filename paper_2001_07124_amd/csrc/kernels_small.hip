@@ -806,7 +806,8 @@ __device__ bool jacobi_lds(double*& A, double*& V, double* A2, double* V2, doubl
 //   1. wave 0, lane i = row i of A (registers): for k = 0..K-3 a reflector
 //      H_k = I - tau v v^T (v_{k+1} = 1) zeroes A(k+2:, k); p = tau A v and
 //      w = p - (tau/2)(p^T v) v give A <- A - v w^T - w v^T.  d, e to LDS,
-//      v and tau kept for the back-transformation.
+//      v and tau kept for the back-transformation (the update is applied as
+//      A - v p^T - (p - tau (p^T v) v) v^T, the same matrix).
 //   2. all threads, four lanes per eigenvalue j (ascending): each lane counts
 //      the eigenvalues below two of the seven interior points of an 8-way
 //      split of [lo, hi) (Sturm count: negative pivots of T - x I, pivots
@@ -934,11 +935,14 @@ __global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ c
                 for (int j = 0; j < KB; ++j) pq[j & 3] = fma(a[j], bc[j], pq[j & 3]);
                 const double pv = (pq[0] + pq[1]) + (pq[2] + pq[3]);
                 const double p = lane > k ? t * pv : 0.0;
+                // A - v w^T - w v^T with w = p - kk v equals
+                // A - v p^T - (p - 2 kk v) v^T: p is broadcast while the sum
+                // for kk is formed
+                if (lane < K) bw[lane] = p;
                 const double kk = 0.5 * t * wave_total(p * v);
-                const double w = p - kk * v;
-                if (lane < K) bw[lane] = w;
+                const double u = fma(-2.0 * kk, v, p);
 #pragma unroll
-                for (int j = 0; j < KB; ++j) a[j] = fma(-v, bw[j], fma(-w, bc[j], a[j]));
+                for (int j = 0; j < KB; ++j) a[j] = fma(-v, bw[j], fma(-u, bc[j], a[j]));
             }
         }
         if (K >= 2) {

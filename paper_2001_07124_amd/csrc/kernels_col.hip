@@ -256,14 +256,23 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
 
     // PD blocks in flight per wave: the loop alternates between the register
     // sets F0 and F1 (PD = 2), each refilled chunk by chunk with the block
-    // PD nw ahead.  The sketch, whose Y accumulators and generator need the
-    // registers, and the largest tiles keep one block in flight.
-    constexpr int PD = (OP == OP_SKETCH || NCH * NB > 24) ? 1 : 2;
+    // PD nw ahead.  The sketch and the power step, whose Y accumulators need
+    // the registers, keep one block in flight (the power step spills with
+    // two), as do the largest tiles.
+    constexpr int PD = (OP != OP_TTM || NCH * NB > 24) ? 1 : 2;
+    // The power step reads the M fragments of chunk h + 1 while chunk h is
+    // multiplied (the projection, measured, does better without).
+    constexpr bool MPF = OP == OP_POWER;
     f32x4 F0[NCH][2][2], F1[NCH][2][2];
+    // The first loads of a register set, chunk 0 first: the loop body consumes
+    // the chunks in that order, and with the order pinned (no reordering across
+    // the scheduling barriers) the wait before chunk h covers only the loads
+    // issued before it.  Otherwise the waits at the top of the loop, which
+    // also cover entry from here, drain every load in flight.
     auto issue = [&](f32x4 (&Fb)[NCH][2][2], int64_t blk) {
         const __amdgpu_buffer_rsrc_t rs = block_rsrc(src, blk, g.nblocks, I, J);
 #pragma unroll
-        for (int h = 0; h < NCH; ++h)
+        for (int h = 0; h < NCH; ++h) {
 #pragma unroll
             for (int h2 = 0; h2 < 2; ++h2)
 #pragma unroll
@@ -271,6 +280,8 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
                     Fb[h][h2][q] = __builtin_bit_cast(
                         f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 128 * h + 16 * q,
                                                                      h2 ? half1 : 0, 0));
+            __builtin_amdgcn_sched_barrier(0);
+        }
     };
     // mode-n product output staging (TTM): 32 x 16 NB floats per wave
     float* stage = reinterpret_cast<float*>(smem + g.mfr_bytes) + static_cast<size_t>(wave) * 32 * 16 * NB;
@@ -284,6 +295,14 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) Z[h2][nb] = zero4<f32x4>();
         float part = 0.0f;
+        bf16x8 mcu[MPF ? NB : 1][2], mnx[MPF ? NB : 1][2];
+        if constexpr (MPF) {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                mcu[nb][0] = mfr[(nb * 2 + 0) * 64 + lane];
+                mcu[nb][1] = mfr[(nb * 2 + 1) * 64 + lane];
+            }
+        }
 
         // chunk by chunk: round to bf16, stage for the transpose, refill the
         // chunk's registers with the block 2 nw ahead, and Z = S^T M
@@ -331,10 +350,25 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
                         f32x4, __builtin_amdgcn_raw_buffer_load_b128(rn, voff + 128 * h + 16 * q,
                                                                      h2 ? half1 : 0, 0));
             if (OP != OP_SKETCH) {
+                if constexpr (MPF) {
+                    if (h + 1 < NCH) {
+#pragma unroll
+                        for (int nb = 0; nb < NB; ++nb) {
+                            mnx[nb][0] = mfr[(((h + 1) * NB + nb) * 2 + 0) * 64 + lane];
+                            mnx[nb][1] = mfr[(((h + 1) * NB + nb) * 2 + 1) * 64 + lane];
+                        }
+                    }
+                }
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
-                    const bf16x8 mhi = mfr[((h * NB + nb) * 2 + 0) * 64 + lane];
-                    const bf16x8 mlo = mfr[((h * NB + nb) * 2 + 1) * 64 + lane];
+                    bf16x8 mhi, mlo;
+                    if constexpr (MPF) {
+                        mhi = mcu[nb][0];
+                        mlo = mcu[nb][1];
+                    } else {
+                        mhi = mfr[((h * NB + nb) * 2 + 0) * 64 + lane];
+                        mlo = mfr[((h * NB + nb) * 2 + 1) * 64 + lane];
+                    }
                     if (SPLIT) {
                         Z[0][nb] = mma32(L0, mhi, Z[0][nb]);
                         Z[1][nb] = mma32(L1, mhi, Z[1][nb]);
@@ -343,6 +377,13 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
                     Z[1][nb] = mma32(D1, mlo, Z[1][nb]);
                     Z[0][nb] = mma32(D0, mhi, Z[0][nb]);
                     Z[1][nb] = mma32(D1, mhi, Z[1][nb]);
+                }
+                if constexpr (MPF) {
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        mcu[nb][0] = mnx[nb][0];
+                        mcu[nb][1] = mnx[nb][1];
+                    }
                 }
             }
         }
@@ -409,7 +450,7 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
                             for (int e = 0; e < 4; ++e) stage[(16 * h2 + 4 * grp + e) * K + r] = Z[h2][nb][e];
                         }
                     }
-                const int64_t nval = (full ? 32 : (J - j0)) * static_cast<int64_t>(K);
+                const int64_t nval = (full ? 32 : (J > j0 ? J - j0 : 0)) * static_cast<int64_t>(K);
                 float* ob = out + j0 * static_cast<int64_t>(K);
                 const int n4 = static_cast<int>(nval >> 2);
                 for (int t = lane; t < n4; t += kWave)

@@ -27,6 +27,10 @@
 // rounded, which on the 200^4 workload moves the relative error by a few
 // 1e-4.  The power step's Y += S Z takes the rounded tensor against split Z.
 // The Gram Z^T Z takes hi*hi + hi*lo + lo*hi.  Accumulation is FP32.
+//
+// Outputs of the mode-n product are written with non-temporal stores: they
+// are read back only by the next pass, after far more traffic than the
+// caches hold, and streaming them past the caches costs the reads less.
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"
@@ -429,11 +433,11 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
                         if (r < K) {
                             float* o = out + static_cast<int64_t>(r) * J + jj;
                             if (jal && full) {
-                                *reinterpret_cast<f32x4*>(o) = Z[h2][nb];
+                                __builtin_nontemporal_store(Z[h2][nb], reinterpret_cast<f32x4*>(o));
                             } else {
 #pragma unroll
                                 for (int e = 0; e < 4; ++e)
-                                    if (jj + e < J) o[e] = Z[h2][nb][e];
+                                    if (jj + e < J) __builtin_nontemporal_store(Z[h2][nb][e], o + e);
                             }
                         }
                     }
@@ -454,8 +458,9 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
                 float* ob = out + j0 * static_cast<int64_t>(K);
                 const int n4 = static_cast<int>(nval >> 2);
                 for (int t = lane; t < n4; t += kWave)
-                    *reinterpret_cast<f32x4*>(ob + 4 * t) = *reinterpret_cast<const f32x4*>(stage + 4 * t);
-                for (int t = 4 * n4 + lane; t < nval; t += kWave) ob[t] = stage[t];
+                    __builtin_nontemporal_store(*reinterpret_cast<const f32x4*>(stage + 4 * t),
+                                                reinterpret_cast<f32x4*>(ob + 4 * t));
+                for (int t = 4 * n4 + lane; t < nval; t += kWave) __builtin_nontemporal_store(stage[t], ob + t);
             }
             if (GRAM) {
                 bf16x8 Ghi[NB], Glo[NB];

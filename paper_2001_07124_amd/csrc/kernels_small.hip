@@ -204,9 +204,11 @@ __device__ void mfma_gram_rows(const double* W, const CqrGeom g, double* G, doub
 // step j takes the pivot from lane j, L(j+1, j) by a lane read (the next
 // pivot depends on nothing else), and the rest of column j through S.  Then
 // X = L^{-1} by rows, lane i solving x L = e_i from the last column down with
-// the rows of L broadcast from S.  S may alias G (read into registers first).
-// Out: X (pitch XP; rows >= K zero).  Returns false, uniformly, on a pivot not
-// above 1e-14 of its original diagonal.
+// the rows of L broadcast from S.  S may alias G (read into registers first);
+// it must be 16-byte aligned and hold K rows of pitch SP = XP rounded up to
+// even (the broadcast rows are read two doubles per instruction), which may
+// run into X: X is written last.  Out: X (pitch XP; rows >= K zero).  Returns
+// false, uniformly, on a pivot not above 1e-14 of its original diagonal.
 template <int KB>
 __device__ bool wave_chol_inv(const double* G, const double* diag0, double* S, double* X, int K,
                               int XP, int XN) {
@@ -216,6 +218,7 @@ __device__ bool wave_chol_inv(const double* G, const double* diag0, double* S, d
 #pragma unroll
     for (int c = 0; c < KB; ++c) g[c] = (li < K && c < K) ? G[li * XP + c] : (li == c ? 1.0 : 0.0);
     const double dgl = (li < K) ? diag0[li] : 1.0;
+    const int SP = (XP + 1) & ~1;
     double dinvl = 0.0;     // lane j: 1 / L(j, j)
     bool ok = true;
 #pragma unroll
@@ -233,10 +236,14 @@ __device__ bool wave_chol_inv(const double* G, const double* diag0, double* S, d
                 g[j] = l;
                 if (j + 1 < KB) g[j + 1] = fma(-l, readlane_d(l, j + 1), g[j + 1]);
                 if (j + 2 < KB) {
-                    if (lane < KB) S[j * XP + lane] = l;
+                    if (lane < KB) S[j * SP + lane] = l;
                     double sr[KB];
 #pragma unroll
-                    for (int c = j + 2; c < KB; ++c) sr[c] = S[j * XP + c];
+                    for (int c = (j + 2) & ~1; c < KB; c += 2) {
+                        const double2 v = *reinterpret_cast<const double2*>(S + j * SP + c);
+                        sr[c] = v.x;
+                        sr[c + 1] = v.y;
+                    }
 #pragma unroll
                     for (int c = j + 2; c < KB; ++c) g[c] = fma(-l, sr[c], g[c]);
                 }
@@ -246,7 +253,7 @@ __device__ bool wave_chol_inv(const double* G, const double* diag0, double* S, d
     if (!ok) return false;
     if (lane < KB) {
 #pragma unroll
-        for (int c = 0; c < KB; ++c) S[lane * XP + c] = g[c];
+        for (int c = 0; c < KB; ++c) S[lane * SP + c] = g[c];
     }
     double acc[KB];
 #pragma unroll
@@ -256,7 +263,11 @@ __device__ bool wave_chol_inv(const double* G, const double* diag0, double* S, d
         if (m < K) {
             double sr[KB];
 #pragma unroll
-            for (int k = 0; k < m; ++k) sr[k] = S[m * XP + k];
+            for (int k = 0; k < m; k += 2) {
+                const double2 v = *reinterpret_cast<const double2*>(S + m * SP + k);
+                sr[k] = v.x;
+                sr[k + 1] = v.y;
+            }
             const double x = ((li == m ? 1.0 : 0.0) - acc[m]) * readlane_d(dinvl, m);
             acc[m] = x;
 #pragma unroll

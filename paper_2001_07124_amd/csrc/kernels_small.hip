@@ -819,10 +819,11 @@ __device__ bool jacobi_lds(double*& A, double*& V, double* A2, double* V2, doubl
 //      w = p - (tau/2)(p^T v) v give A <- A - v w^T - w v^T.  d, e to LDS,
 //      v and tau kept for the back-transformation (the update is applied as
 //      A - v p^T - (p - tau (p^T v) v) v^T, the same matrix).
-//   2. all threads, four lanes per eigenvalue j (ascending): each lane counts
-//      the eigenvalues below two of the seven interior points of an 8-way
+//   2. all threads, seven lanes per eigenvalue j (ascending): each lane counts
+//      the eigenvalues below one of the seven interior points of an 8-way
 //      split of [lo, hi) (Sturm count: negative pivots of T - x I, pivots
-//      kept away from zero by pivmin), the quad adds its flags and keeps the
+//      kept away from zero by pivmin), a wave ballot counts the group's
+//      points with at most j eigenvalues below, and the group keeps the
 //      eighth that holds lambda_j; 18 steps take the Gershgorin interval to
 //      about 1e-16 of norm(T).
 //   3. wave 0, lane j = eigenvalue j: two steps of inverse iteration from a
@@ -983,10 +984,12 @@ __global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ c
     }
     __syncthreads();
 
-    // ---- 2. eigenvalues by multisection (all threads; lanes 4j..4j+3) ----
+    // ---- 2. eigenvalues by multisection (all threads; 7 lanes per eigenvalue) ----
     {
         const double tn = stats[0], pivmin = stats[1];
-        const int j = tid >> 2, sub = tid & 3;
+        // lanes 7 q .. 7 q + 6 of wave w (q < 9) own eigenvalue jb + 9 w + q
+        const int grpq = lane / 7, sub = lane - 7 * grpq;
+        const uint64_t gmask = grpq < 9 ? (0x7FULL << (7 * grpq)) : 0ULL;
         // rows past K: d huge and e zero keep their pivots positive, so they
         // never count and need no masking
         double d[KB], e2[KB];
@@ -995,34 +998,34 @@ __global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ c
             d[i] = i < K ? dd[i] : 1e300;
             e2[i] = ee[i] * ee[i];                 // ee is zero past K - 2
         }
-        double lo = -tn - 4.0 * pivmin - 2.2e-16 * 4.0 * K * tn - 1e-300;
-        double hi = tn + 4.0 * pivmin + 2.2e-16 * 4.0 * K * tn + 1e-300;
 #pragma unroll 1
-        for (int st = 0; st < kBisectSteps; ++st) {
-            const double h = (hi - lo) * 0.125;
-            const double xa = lo + (2 * sub + 1) * h, xb = lo + (2 * sub + 2) * h;
-            double qa = d[0] - xa, qb = d[0] - xb;
-            qa = fabs(qa) < pivmin ? -pivmin : qa;
-            qb = fabs(qb) < pivmin ? -pivmin : qb;
-            int ca = qa < 0.0, cb = qb < 0.0;
-#pragma unroll
-            for (int i = 1; i < KB; ++i) {
-                qa = fma(-e2[i - 1], rcp_nr(qa), d[i] - xa);
-                qb = fma(-e2[i - 1], rcp_nr(qb), d[i] - xb);
+        for (int jb = 0; jb < K; jb += 9 * (kBlock / kWave)) {
+            const int j = jb + 9 * wave + grpq;
+            double lo = -tn - 4.0 * pivmin - 2.2e-16 * 4.0 * K * tn - 1e-300;
+            double hi = tn + 4.0 * pivmin + 2.2e-16 * 4.0 * K * tn + 1e-300;
+#pragma unroll 1
+            for (int st = 0; st < kBisectSteps; ++st) {
+                // point sub + 1 of the 8-way split (point 8 is hi itself)
+                const double h = (hi - lo) * 0.125;
+                const double xa = lo + (sub + 1) * h;
+                double qa = d[0] - xa;
                 qa = fabs(qa) < pivmin ? -pivmin : qa;
-                qb = fabs(qb) < pivmin ? -pivmin : qb;
-                ca += qa < 0.0 ? 1 : 0;
-                cb += qb < 0.0 ? 1 : 0;
+                int ca = qa < 0.0;
+#pragma unroll
+                for (int i = 1; i < KB; ++i) {
+                    qa = fma(-e2[i - 1], rcp_nr(qa), d[i] - xa);
+                    qa = fabs(qa) < pivmin ? -pivmin : qa;
+                    ca += qa < 0.0 ? 1 : 0;
+                }
+                // how many of the group's seven points have at most j
+                // eigenvalues below them
+                const int nle = __popcll(__ballot(ca <= j) & gmask);
+                const double nlo = lo + nle * h;
+                hi = nle == 7 ? hi : lo + (nle + 1) * h;
+                lo = nlo;
             }
-            // points 2 sub + 1 and 2 sub + 2 of 1..7 (point 8 is hi itself)
-            int nle = (ca <= j ? 1 : 0) + ((sub < 3 && cb <= j) ? 1 : 0);
-            nle += __shfl_xor(nle, 1, kWave);
-            nle += __shfl_xor(nle, 2, kWave);
-            const double nlo = lo + nle * h;
-            hi = nle == 7 ? hi : lo + (nle + 1) * h;
-            lo = nlo;
+            if (sub == 0 && grpq < 9 && j < K) lam[j] = 0.5 * (lo + hi);
         }
-        if (sub == 0 && j < K) lam[j] = 0.5 * (lo + hi);
     }
     __syncthreads();
 

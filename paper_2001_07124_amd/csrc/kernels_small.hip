@@ -11,6 +11,7 @@
 
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 #include "device_common.hpp"
 #include "householder.hpp"
@@ -856,6 +857,16 @@ __device__ __forceinline__ double pick(const double (&a)[KB], int idx) {
     return m == 0 ? r[0] : (m == 1 ? r[1] : (m == 2 ? r[2] : r[3]));
 }
 
+// pick over the entries J0 .. KB - 1 only (idx >= J0)
+template <int KB, int J0>
+__device__ __forceinline__ double pick_from(const double (&a)[KB], int idx) {
+    double r[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = J0; c < KB; ++c) r[c & 3] = (c == idx) ? a[c] : r[c & 3];
+    const int m = idx & 3;
+    return m == 0 ? r[0] : (m == 1 ? r[1] : (m == 2 ? r[2] : r[3]));
+}
+
 // Sum over the wave, the same value in every lane: butterflies inside quads
 // and rows of 16 on DPP lane moves (no LDS), then the four row sums.
 template <int CTRL>
@@ -918,9 +929,12 @@ __global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ c
         const int li = lane < K ? lane : 0;
 #pragma unroll
         for (int c = 0; c < KB; ++c) a[c] = (lane < K && c < K) ? cin[static_cast<size_t>(c) * K + li] : 0.0;
-#pragma unroll 1
-        for (int k = 0; k < K - 2; ++k) {
-            const double ak = pick(a, k);
+        // Step k touches only rows and columns past k (v and p vanish at
+        // indices <= k), so the steps run in segments of eight whose column
+        // loops start at the segment's first step (J0 <= k).
+        auto step = [&](auto J0c, int k) __attribute__((always_inline)) {
+            constexpr int J0 = decltype(J0c)::value;
+            const double ak = pick_from<KB, J0>(a, k);
             const double x = lane > k ? ak : 0.0;                 // A(k+1:, k)
             const double akk = readlane_d(ak, k);
             const double x1 = readlane_d(ak, k + 1);
@@ -940,11 +954,15 @@ __global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ c
                 ee[k] = beta;
             }
             if (t != 0.0) {
-                // v and w vanish at indices <= k, so the whole rows can be used
+                // v and p broadcast through LDS (zero past K), read in pairs
                 if (lane < K) bc[lane] = v;
                 double pq[4] = {0.0, 0.0, 0.0, 0.0};   // four independent chains
 #pragma unroll
-                for (int j = 0; j < KB; ++j) pq[j & 3] = fma(a[j], bc[j], pq[j & 3]);
+                for (int j = J0; j < KB; j += 2) {
+                    const double2 c2 = *reinterpret_cast<const double2*>(bc + j);
+                    pq[j & 3] = fma(a[j], c2.x, pq[j & 3]);
+                    pq[(j + 1) & 3] = fma(a[j + 1], c2.y, pq[(j + 1) & 3]);
+                }
                 const double pv = (pq[0] + pq[1]) + (pq[2] + pq[3]);
                 const double p = lane > k ? t * pv : 0.0;
                 // A - v w^T - w v^T with w = p - kk v equals
@@ -954,9 +972,30 @@ __global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ c
                 const double kk = 0.5 * t * wave_total(p * v);
                 const double u = fma(-2.0 * kk, v, p);
 #pragma unroll
-                for (int j = 0; j < KB; ++j) a[j] = fma(-v, bw[j], fma(-u, bc[j], a[j]));
+                for (int j = J0; j < KB; j += 2) {
+                    const double2 c2 = *reinterpret_cast<const double2*>(bc + j);
+                    const double2 w2 = *reinterpret_cast<const double2*>(bw + j);
+                    a[j] = fma(-v, w2.x, fma(-u, c2.x, a[j]));
+                    a[j + 1] = fma(-v, w2.y, fma(-u, c2.y, a[j + 1]));
+                }
             }
-        }
+        };
+        auto seg = [&](auto J0c) __attribute__((always_inline)) {
+            constexpr int J0 = decltype(J0c)::value;
+            if constexpr (J0 < KB) {
+                const int kend = J0 + 8 < K - 2 ? J0 + 8 : K - 2;
+#pragma unroll 1
+                for (int k = J0; k < kend; ++k) step(J0c, k);
+            }
+        };
+        seg(std::integral_constant<int, 0>{});
+        seg(std::integral_constant<int, 8>{});
+        seg(std::integral_constant<int, 16>{});
+        seg(std::integral_constant<int, 24>{});
+        seg(std::integral_constant<int, 32>{});
+        seg(std::integral_constant<int, 40>{});
+        seg(std::integral_constant<int, 48>{});
+        seg(std::integral_constant<int, 56>{});
         if (K >= 2) {
             const double d0 = readlane_d(pick(a, K - 2), K - 2);
             const double d1 = readlane_d(pick(a, K - 1), K - 1);

@@ -524,8 +524,15 @@ hipError_t launch_gram_reduce(bool dbl, const void* part, int G, int K, int K_pa
     return launch_reduce_parts(dbl, part, G, K, K, K_pad, K_pad, c, s);
 }
 
+hipError_t launch_hqr_fwd(const double* y, int I, int K, bool dbl, void* q_out, double* q64,
+                          hipStream_t s);
+
 hipError_t launch_cqr(const double* y, int64_t I, int K, bool dbl, void* q_out, double* q64,
                       uint32_t* flags, hipStream_t s) {
+    // a mode of up to 256 rows: one Householder QR pass (no breakdown, so
+    // flags stay untouched); taller: CholeskyQR2
+    if (K >= 1 && K <= 64 && I >= K && I <= 256)
+        return launch_hqr_fwd(y, static_cast<int>(I), K, dbl, q_out, q64, s);
     if (K > 64 || I > (1 << 20) || cqr_lds_bytes(I, K) + kStaticLdsMargin > kLdsLimit)
         return launch_cqr_global(y, I, K, dbl, q_out, q64, flags, s);
     return launch_cqr_lds(y, I, K, dbl, q_out, q64, flags, s);
@@ -884,6 +891,168 @@ __device__ __forceinline__ double wave_total(double v) {
     v += dpp_d<0x124>(v);   // row_ror:4
     v += dpp_d<0x128>(v);   // row_ror:8
     return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+// ---------------------------------------------------------------------------
+// Householder QR of Y (I x K column-major FP64, K <= I <= 256, K <= 64) in one
+// workgroup (Golub & Van Loan, Matrix Computations, 5.2.1, with the backward
+// accumulation of Q of 5.1.6).  Wave w keeps the columns c = w + 4 m
+// (m < NCW) in registers, lane l holding rows l + 64 r (r < 4), so column j
+// lives in wave j % 4, slot j / 4.  Column step j: its wave forms the
+// reflector H_j = I - tau v v^T (v_j = A(j,j) - alpha, v_i = A(i,j) below,
+// alpha = -sign(A(j,j)) norm(A(j:,j))) and broadcasts v through LDS; every
+// wave applies H_j to its columns past j.  The outer loop runs over the
+// slots m (unrolled) and the inner over the four waves, so every register
+// index is a constant and the columns before slot m drop out at compile
+// time.  Then Q = H_0 ... H_{K-1} [I_K; 0] backwards, each wave on its own
+// columns from the stored reflectors (no barriers), and columns with alpha <
+// 0 negated: diag(R) >= 0, the same Q as CholeskyQR for full-rank Y.  One
+// barrier per column step; LDS: K x 256 doubles of reflectors.
+// ---------------------------------------------------------------------------
+template <int NCW>
+__global__ __launch_bounds__(kBlock) void k_hqr(const double* __restrict__ y, int I, int K,
+                                                double* __restrict__ q64, void* q_out, int dbl) {
+    extern __shared__ __align__(16) double shd[];
+    double* V = shd;                               // reflector j at V[j * 256 + row]
+    __shared__ double tau_s[RHOSVD_MAX_K], alpha_s[RHOSVD_MAX_K];
+    const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
+    double a[NCW][4];
+#pragma unroll
+    for (int m = 0; m < NCW; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = wave + 4 * m, row = lane + 64 * r;
+            a[m][r] = (c < K && row < I) ? y[static_cast<size_t>(c) * I + row] : 0.0;
+        }
+#pragma unroll
+    for (int m = 0; m < NCW; ++m) {
+#pragma unroll 1
+        for (int ow = 0; ow < 4; ++ow) {
+            const int j = 4 * m + ow;
+            if (j >= K) break;
+            if (wave == ow) {
+                double s2 = 0.0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double x = lane + 64 * r >= j ? a[m][r] : 0.0;
+                    s2 = fma(x, x, s2);
+                }
+                const double n2 = wave_total(s2);
+                const double ajj = readlane_d(a[m][0], j);      // j < 64: row j is lane j, r = 0
+                const double alpha = (ajj > 0.0 ? -1.0 : 1.0) * sqrt(n2);
+                const double v0 = ajj - alpha;
+                const double vn2 = fma(v0, v0, n2 - ajj * ajj);
+                const double tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = lane + 64 * r;
+                    V[j * 256 + row] = row == j ? v0 : (row > j ? a[m][r] : 0.0);
+                }
+                if (lane == 0) {
+                    tau_s[j] = tau;
+                    alpha_s[j] = alpha;
+                }
+            }
+            __syncthreads();
+            const double tau = tau_s[j];
+            double v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = V[j * 256 + lane + 64 * r];
+            // columns past j: every later slot, and slot m in the waves after
+            // ow (columns past K are zero and stay zero)
+#pragma unroll
+            for (int mm = m; mm < NCW; ++mm) {
+                double d = 0.0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) d = fma(v[r], a[mm][r], d);
+                d = wave_total(d) * tau;
+                if (mm == m) d = wave > ow ? d : 0.0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) a[mm][r] = fma(-d, v[r], a[mm][r]);
+            }
+        }
+    }
+    __syncthreads();
+    // Q backwards: H_j changes only the columns c >= j
+    double q[NCW][4];
+#pragma unroll
+    for (int m = 0; m < NCW; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = wave + 4 * m;
+            q[m][r] = (c < K && lane + 64 * r == c) ? 1.0 : 0.0;
+        }
+#pragma unroll
+    for (int m = NCW - 1; m >= 0; --m) {
+#pragma unroll 1
+        for (int ow = 3; ow >= 0; --ow) {
+            const int j = 4 * m + ow;
+            if (j >= K) continue;
+            const double tau = tau_s[j];
+            double v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = V[j * 256 + lane + 64 * r];
+#pragma unroll
+            for (int mm = m; mm < NCW; ++mm) {
+                double d = 0.0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) d = fma(v[r], q[mm][r], d);
+                d = wave_total(d) * tau;
+                if (mm == m) d = wave >= ow ? d : 0.0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) q[mm][r] = fma(-d, v[r], q[mm][r]);
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < NCW; ++m) {
+        const int c = wave + 4 * m;
+        if (c < K) {
+            const double sg = alpha_s[c] < 0.0 ? -1.0 : 1.0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = lane + 64 * r;
+                if (row < I) {
+                    const size_t e = static_cast<size_t>(c) * I + row;
+                    const double val = sg * q[m][r];
+                    q64[e] = val;
+                    if (dbl)
+                        static_cast<double*>(q_out)[e] = val;
+                    else
+                        static_cast<float*>(q_out)[e] = static_cast<float>(val);
+                }
+            }
+        }
+    }
+}
+
+static hipError_t launch_hqr(const double* y, int I, int K, bool dbl, void* q_out, double* q64,
+                             hipStream_t s) {
+    const size_t lds = static_cast<size_t>(K) * 256 * sizeof(double);
+    const int d = dbl ? 1 : 0;
+#define RH_HQR_CASE(N)                                                                        \
+    case N:                                                                                   \
+        hipLaunchKernelGGL(k_hqr<N>, dim3(1), dim3(kBlock), lds, s, y, I, K, q64, q_out, d); \
+        break;
+    switch ((K + 7) / 8 * 2) {
+        RH_HQR_CASE(2)
+        RH_HQR_CASE(4)
+        RH_HQR_CASE(6)
+        RH_HQR_CASE(8)
+        RH_HQR_CASE(10)
+        RH_HQR_CASE(12)
+        RH_HQR_CASE(14)
+        RH_HQR_CASE(16)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef RH_HQR_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_hqr_fwd(const double* y, int I, int K, bool dbl, void* q_out, double* q64,
+                          hipStream_t s) {
+    return launch_hqr(y, I, K, dbl, q_out, q64, s);
 }
 
 // Start vector of inverse iteration: entries in [-1, 1) from a 32-bit hash

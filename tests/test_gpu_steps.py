@@ -118,7 +118,7 @@ def test_ttm_and_gram(dims, dtype):
     np.testing.assert_array_equal(out.cpu().numpy(), x.reshape(-1, order="F"))
 
 
-@pytest.mark.parametrize("I,K", [(200, 35), (37, 11), (500, 30), (64, 64), (15, 15)])
+@pytest.mark.parametrize("I,K", [(200, 35), (37, 11), (500, 30), (64, 64), (15, 15), (256, 64), (257, 64), (1, 1)])
 def test_orthonormalize(I, K):
     rng = np.random.default_rng(I * 100 + K)
     y = rng.standard_normal((I, K)) @ np.diag(np.logspace(0, -3, K))
@@ -131,8 +131,9 @@ def test_orthonormalize(I, K):
 
 
 def test_orthonormalize_rank_deficient_shifts():
+    # taller than 256 rows: CholeskyQR2, whose Gram is singular here
     rng = np.random.default_rng(9)
-    base = rng.standard_normal((120, 6))
+    base = rng.standard_normal((300, 6))
     y = base @ rng.standard_normal((6, 20))          # rank 6, K = 20
     q, q64, flags = api.orthonormalize(torch.from_numpy(y).cuda(), torch.float64)
     q = q64.cpu().numpy()
@@ -140,6 +141,19 @@ def test_orthonormalize_rank_deficient_shifts():
     assert np.linalg.norm(q.T @ q - np.eye(20), 2) <= 1e-10
     # the range of Y is inside span(Q)
     assert np.linalg.norm(y - q @ (q.T @ y)) <= 1e-10 * np.linalg.norm(y)
+
+
+def test_orthonormalize_rank_deficient_householder():
+    # up to 256 rows: Householder QR, no breakdown to report
+    rng = np.random.default_rng(9)
+    base = rng.standard_normal((120, 6))
+    y = base @ rng.standard_normal((6, 20))          # rank 6, K = 20
+    q, q64, flags = api.orthonormalize(torch.from_numpy(y).cuda(), torch.float64)
+    q = q64.cpu().numpy()
+    assert flags.item() == 0
+    assert np.linalg.norm(q.T @ q - np.eye(20), 2) <= 1e-12
+    assert np.linalg.norm(y - q @ (q.T @ y)) <= 1e-12 * np.linalg.norm(y)
+    np.testing.assert_array_equal(q, q64.cpu().numpy())
 
 
 @pytest.mark.parametrize("K", [1, 2, 7, 35, 64])

@@ -896,57 +896,73 @@ __device__ __forceinline__ double wave_total(double v) {
 // ---------------------------------------------------------------------------
 // Householder QR of Y (I x K column-major FP64, K <= I <= 256, K <= 64) in one
 // workgroup (Golub & Van Loan, Matrix Computations, 5.2.1, with the backward
-// accumulation of Q of 5.1.6).  Wave w keeps the columns c = w + 4 m
-// (m < NCW) in registers, lane l holding rows l + 64 r (r < 4), so column j
-// lives in wave j % 4, slot j / 4.  Column step j: its wave forms the
-// reflector H_j = I - tau v v^T (v_j = A(j,j) - alpha, v_i = A(i,j) below,
-// alpha = -sign(A(j,j)) norm(A(j:,j))) and broadcasts v through LDS; every
-// wave applies H_j to its columns past j.  The outer loop runs over the
-// slots m (unrolled) and the inner over the four waves, so every register
-// index is a constant and the columns before slot m drop out at compile
-// time.  Then Q = H_0 ... H_{K-1} [I_K; 0] backwards, each wave on its own
-// columns from the stored reflectors (no barriers), and columns with alpha <
-// 0 negated: diag(R) >= 0, the same Q as CholeskyQR for full-rank Y.  One
-// barrier per column step; LDS: K x 256 doubles of reflectors.
+// accumulation of Q of 5.1.6).  Column c = 16 s + 4 g + w lives in wave w,
+// lane group g (lanes 16 g .. 16 g + 15, one DPP row) and register slot s;
+// lane 16 g + t holds its rows t + 16 r (r < 16).  A column's dot product is
+// then one reduction within a DPP row, and one reduction serves the four
+// columns of a slot together.  Column step j: its group forms the reflector
+// H_j = I - tau v v^T (v_j = A(j,j) - alpha, v_i = A(i,j) below, alpha =
+// -sign(A(j,j)) norm(A(j:,j))) and broadcasts v through LDS; every wave
+// applies H_j to its columns past j.  The outer loop runs over the slots
+// (unrolled), the inner over the 16 columns of a slot, so register indices
+// are constants (row j sits in register r = j / 16 = the slot) and the
+// slots before the current one drop out at compile time.  Then Q =
+// H_0 ... H_{K-1} [I_K; 0] backwards, each wave on its own columns from the
+// stored reflectors (no barriers), and columns with alpha < 0 negated:
+// diag(R) >= 0, the same Q as CholeskyQR for full-rank Y.  One barrier per
+// column step; LDS: K x 256 doubles of reflectors.
 // ---------------------------------------------------------------------------
-template <int NCW>
+__device__ __forceinline__ double row16_total(double v) {
+    v += dpp_d<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_d<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_d<0x124>(v);   // row_ror:4
+    v += dpp_d<0x128>(v);   // row_ror:8
+    return v;
+}
+
+template <int NS>
 __global__ __launch_bounds__(kBlock) void k_hqr(const double* __restrict__ y, int I, int K,
                                                 double* __restrict__ q64, void* q_out, int dbl) {
     extern __shared__ __align__(16) double shd[];
     double* V = shd;                               // reflector j at V[j * 256 + row]
     __shared__ double tau_s[RHOSVD_MAX_K], alpha_s[RHOSVD_MAX_K];
     const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
-    double a[NCW][4];
+    const int g = lane >> 4, t = lane & 15;
+    const int cw = 4 * g + wave;                   // column within a slot
+    double a[NS][16];
 #pragma unroll
-    for (int m = 0; m < NCW; ++m)
+    for (int m = 0; m < NS; ++m)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int c = wave + 4 * m, row = lane + 64 * r;
+        for (int r = 0; r < 16; ++r) {
+            const int c = 16 * m + cw, row = t + 16 * r;
             a[m][r] = (c < K && row < I) ? y[static_cast<size_t>(c) * I + row] : 0.0;
         }
 #pragma unroll
-    for (int m = 0; m < NCW; ++m) {
+    for (int m = 0; m < NS; ++m) {
 #pragma unroll 1
-        for (int ow = 0; ow < 4; ++ow) {
-            const int j = 4 * m + ow;
+        for (int jc = 0; jc < 16; ++jc) {          // jc = 4 og + ow
+            const int j = 16 * m + jc;
             if (j >= K) break;
+            const int ow = jc & 3, og = jc >> 2;
             if (wave == ow) {
                 double s2 = 0.0;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const double x = lane + 64 * r >= j ? a[m][r] : 0.0;
+                for (int r = 0; r < 16; ++r) {
+                    const double x = t + 16 * r >= j ? a[m][r] : 0.0;
                     s2 = fma(x, x, s2);
                 }
-                const double n2 = wave_total(s2);
-                const double ajj = readlane_d(a[m][0], j);      // j < 64: row j is lane j, r = 0
+                const double n2 = readlane_d(row16_total(s2), 16 * og);
+                const double ajj = readlane_d(a[m][m], 16 * og + jc);   // row j: t = jc, r = m
                 const double alpha = (ajj > 0.0 ? -1.0 : 1.0) * sqrt(n2);
                 const double v0 = ajj - alpha;
                 const double vn2 = fma(v0, v0, n2 - ajj * ajj);
                 const double tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+                if (g == og) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = lane + 64 * r;
-                    V[j * 256 + row] = row == j ? v0 : (row > j ? a[m][r] : 0.0);
+                    for (int r = 0; r < 16; ++r) {
+                        const int row = t + 16 * r;
+                        V[j * 256 + row] = row == j ? v0 : (row > j ? a[m][r] : 0.0);
+                    }
                 }
                 if (lane == 0) {
                     tau_s[j] = tau;
@@ -955,63 +971,63 @@ __global__ __launch_bounds__(kBlock) void k_hqr(const double* __restrict__ y, in
             }
             __syncthreads();
             const double tau = tau_s[j];
-            double v[4];
+            double v[16];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) v[r] = V[j * 256 + lane + 64 * r];
-            // columns past j: every later slot, and slot m in the waves after
-            // ow (columns past K are zero and stay zero)
+            for (int r = 0; r < 16; ++r) v[r] = V[j * 256 + t + 16 * r];
+            // columns past j: every later slot, and in slot m the columns
+            // after jc (columns past K are zero and stay zero)
 #pragma unroll
-            for (int mm = m; mm < NCW; ++mm) {
+            for (int mm = m; mm < NS; ++mm) {
                 double d = 0.0;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) d = fma(v[r], a[mm][r], d);
-                d = wave_total(d) * tau;
-                if (mm == m) d = wave > ow ? d : 0.0;
+                for (int r = 0; r < 16; ++r) d = fma(v[r], a[mm][r], d);
+                d = row16_total(d) * tau;
+                if (mm == m) d = cw > jc ? d : 0.0;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) a[mm][r] = fma(-d, v[r], a[mm][r]);
+                for (int r = 0; r < 16; ++r) a[mm][r] = fma(-d, v[r], a[mm][r]);
             }
         }
     }
     __syncthreads();
     // Q backwards: H_j changes only the columns c >= j
-    double q[NCW][4];
+    double q[NS][16];
 #pragma unroll
-    for (int m = 0; m < NCW; ++m)
+    for (int m = 0; m < NS; ++m)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int c = wave + 4 * m;
-            q[m][r] = (c < K && lane + 64 * r == c) ? 1.0 : 0.0;
+        for (int r = 0; r < 16; ++r) {
+            const int c = 16 * m + cw;
+            q[m][r] = (c < K && t + 16 * r == c) ? 1.0 : 0.0;
         }
 #pragma unroll
-    for (int m = NCW - 1; m >= 0; --m) {
+    for (int m = NS - 1; m >= 0; --m) {
 #pragma unroll 1
-        for (int ow = 3; ow >= 0; --ow) {
-            const int j = 4 * m + ow;
+        for (int jc = 15; jc >= 0; --jc) {
+            const int j = 16 * m + jc;
             if (j >= K) continue;
             const double tau = tau_s[j];
-            double v[4];
+            double v[16];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) v[r] = V[j * 256 + lane + 64 * r];
+            for (int r = 0; r < 16; ++r) v[r] = V[j * 256 + t + 16 * r];
 #pragma unroll
-            for (int mm = m; mm < NCW; ++mm) {
+            for (int mm = m; mm < NS; ++mm) {
                 double d = 0.0;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) d = fma(v[r], q[mm][r], d);
-                d = wave_total(d) * tau;
-                if (mm == m) d = wave >= ow ? d : 0.0;
+                for (int r = 0; r < 16; ++r) d = fma(v[r], q[mm][r], d);
+                d = row16_total(d) * tau;
+                if (mm == m) d = cw >= jc ? d : 0.0;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) q[mm][r] = fma(-d, v[r], q[mm][r]);
+                for (int r = 0; r < 16; ++r) q[mm][r] = fma(-d, v[r], q[mm][r]);
             }
         }
     }
 #pragma unroll
-    for (int m = 0; m < NCW; ++m) {
-        const int c = wave + 4 * m;
+    for (int m = 0; m < NS; ++m) {
+        const int c = 16 * m + cw;
         if (c < K) {
             const double sg = alpha_s[c] < 0.0 ? -1.0 : 1.0;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = lane + 64 * r;
+            for (int r = 0; r < 16; ++r) {
+                const int row = t + 16 * r;
                 if (row < I) {
                     const size_t e = static_cast<size_t>(c) * I + row;
                     const double val = sg * q[m][r];
@@ -1034,15 +1050,11 @@ static hipError_t launch_hqr(const double* y, int I, int K, bool dbl, void* q_ou
     case N:                                                                                   \
         hipLaunchKernelGGL(k_hqr<N>, dim3(1), dim3(kBlock), lds, s, y, I, K, q64, q_out, d); \
         break;
-    switch ((K + 7) / 8 * 2) {
+    switch ((K + 15) / 16) {
+        RH_HQR_CASE(1)
         RH_HQR_CASE(2)
+        RH_HQR_CASE(3)
         RH_HQR_CASE(4)
-        RH_HQR_CASE(6)
-        RH_HQR_CASE(8)
-        RH_HQR_CASE(10)
-        RH_HQR_CASE(12)
-        RH_HQR_CASE(14)
-        RH_HQR_CASE(16)
         default:
             return hipErrorInvalidValue;
     }

@@ -288,17 +288,23 @@ bool plan_stream(int op, int elem, int64_t L, int64_t I, int64_t T, int K, int n
     // land in disjoint bank ranges when the pitch is 16 or 48 mod 64 words
     g->KW = g->K_pad + ((g->K_pad % 32 == 0) ? 16 : 0);
     g->P = (op == OP_SKETCH) ? g->I_pad + ((g->I_pad % 32 == 0) ? 16 : 0) : g->I_pad + 1;
+    // the widest column tile within kStreamLdsCap (two workgroups per CU);
+    // when none fits (tall modes, whose staged M alone takes most of it), the
+    // widest within the whole LDS
     const int cands[3] = {64, 32, 16};
+    const size_t caps[2] = {kStreamLdsCap, kLdsLimit - kStaticLdsMargin};
     g->C = 0;
-    for (int ci = 0; ci < 3; ++ci) {
-        const int C = cands[ci];
-        if ((op == OP_POWER || op == OP_TTM) && (C / 16) * NB > 4 * kMaxT2) continue;
-        size_t elems = static_cast<size_t>(C) * g->P + static_cast<size_t>(C) * g->KW;
-        if (op != OP_SKETCH) elems += static_cast<size_t>(g->I_pad) * g->KW;
-        if (elems * elem <= kStreamLdsCap) {
-            g->C = C;
-            g->lds_bytes = elems * elem;
-            break;
+    for (int pass = 0; pass < 2 && g->C == 0; ++pass) {
+        for (int ci = 0; ci < 3; ++ci) {
+            const int C = cands[ci];
+            if ((op == OP_POWER || op == OP_TTM) && (C / 16) * NB > 4 * kMaxT2) continue;
+            size_t elems = static_cast<size_t>(C) * g->P + static_cast<size_t>(C) * g->KW;
+            if (op != OP_SKETCH) elems += static_cast<size_t>(g->I_pad) * g->KW;
+            if (elems * elem <= caps[pass]) {
+                g->C = C;
+                g->lds_bytes = elems * elem;
+                break;
+            }
         }
     }
     if (g->C == 0) return false;

@@ -185,8 +185,9 @@ int32_t rhosvd_ttm(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t prec
                    void* workspace, size_t ws_bytes, void* stream);
 
 /* Orthonormal basis of Y (I x K column-major double, I >= K), the Q of
- * Y = QR with diag(R) >= 0 (Algorithm 1 step 3): for I <= 256 and K <= 64 by
- * one FP64 Householder QR in a single workgroup (flags untouched); otherwise
+ * Y = QR with diag(R) >= 0 (Algorithm 1 step 3): for I <= 256 and K <= 64,
+ * or I <= 512 and K <= 32, by one FP64 Householder QR in a single workgroup
+ * (flags untouched); otherwise
  * by CholeskyQR2 with an FP64 Gram/Cholesky and a shifted first pass when the
  * Gram is not numerically positive definite.  q_out: dtype-typed I x K.
  * work: device scratch of 2 I K doubles whose first I K doubles hold the FP64

@@ -529,9 +529,9 @@ hipError_t launch_hqr_fwd(const double* y, int I, int K, bool dbl, void* q_out, 
 
 hipError_t launch_cqr(const double* y, int64_t I, int K, bool dbl, void* q_out, double* q64,
                       uint32_t* flags, hipStream_t s) {
-    // a mode of up to 256 rows: one Householder QR pass (no breakdown, so
-    // flags stay untouched); taller: CholeskyQR2
-    if (K >= 1 && K <= 64 && I >= K && I <= 256)
+    // a mode of up to 256 rows (512 rows for K <= 32): one Householder QR
+    // pass (no breakdown, so flags stay untouched); otherwise CholeskyQR2
+    if (K >= 1 && I >= K && ((K <= 64 && I <= 256) || (K <= 32 && I <= 512)))
         return launch_hqr_fwd(y, static_cast<int>(I), K, dbl, q_out, q64, s);
     if (K > 64 || I > (1 << 20) || cqr_lds_bytes(I, K) + kStaticLdsMargin > kLdsLimit)
         return launch_cqr_global(y, I, K, dbl, q_out, q64, flags, s);
@@ -894,11 +894,11 @@ __device__ __forceinline__ double wave_total(double v) {
 }
 
 // ---------------------------------------------------------------------------
-// Householder QR of Y (I x K column-major FP64, K <= I <= 256, K <= 64) in one
-// workgroup (Golub & Van Loan, Matrix Computations, 5.2.1, with the backward
-// accumulation of Q of 5.1.6).  Column c = 16 s + 4 g + w lives in wave w,
-// lane group g (lanes 16 g .. 16 g + 15, one DPP row) and register slot s;
-// lane 16 g + t holds its rows t + 16 r (r < 16).  A column's dot product is
+// Householder QR of Y (I x K column-major FP64, K <= I <= 16 RPL, K <= 64) in
+// one workgroup (Golub & Van Loan, Matrix Computations, 5.2.1, with the
+// backward accumulation of Q of 5.1.6).  Column c = 16 s + 4 g + w lives in
+// wave w, lane group g (lanes 16 g .. 16 g + 15, one DPP row) and register
+// slot s; lane 16 g + t holds its rows t + 16 r (r < RPL = 16 or 32).  A column's dot product is
 // then one reduction within a DPP row, and one reduction serves the four
 // columns of a slot together.  Column step j: its group forms the reflector
 // H_j = I - tau v v^T (v_j = A(j,j) - alpha, v_i = A(i,j) below, alpha =
@@ -910,7 +910,7 @@ __device__ __forceinline__ double wave_total(double v) {
 // H_0 ... H_{K-1} [I_K; 0] backwards, each wave on its own columns from the
 // stored reflectors (no barriers), and columns with alpha < 0 negated:
 // diag(R) >= 0, the same Q as CholeskyQR for full-rank Y.  One barrier per
-// column step; LDS: K x 256 doubles of reflectors.
+// column step; LDS: K x 16 RPL doubles of reflectors.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double row16_total(double v) {
     v += dpp_d<0xB1>(v);    // quad_perm [1, 0, 3, 2]
@@ -920,20 +920,21 @@ __device__ __forceinline__ double row16_total(double v) {
     return v;
 }
 
-template <int NS>
+template <int NS, int RPL>
 __global__ __launch_bounds__(kBlock) void k_hqr(const double* __restrict__ y, int I, int K,
                                                 double* __restrict__ q64, void* q_out, int dbl) {
     extern __shared__ __align__(16) double shd[];
-    double* V = shd;                               // reflector j at V[j * 256 + row]
+    constexpr int VP = 16 * RPL;                   // rows held: 16 lanes x RPL
+    double* V = shd;                               // reflector j at V[j * VP + row]
     __shared__ double tau_s[RHOSVD_MAX_K], alpha_s[RHOSVD_MAX_K];
     const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
     const int g = lane >> 4, t = lane & 15;
     const int cw = 4 * g + wave;                   // column within a slot
-    double a[NS][16];
+    double a[NS][RPL];
 #pragma unroll
     for (int m = 0; m < NS; ++m)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
+        for (int r = 0; r < RPL; ++r) {
             const int c = 16 * m + cw, row = t + 16 * r;
             a[m][r] = (c < K && row < I) ? y[static_cast<size_t>(c) * I + row] : 0.0;
         }
@@ -947,7 +948,7 @@ __global__ __launch_bounds__(kBlock) void k_hqr(const double* __restrict__ y, in
             if (wave == ow) {
                 double s2 = 0.0;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
+                for (int r = 0; r < RPL; ++r) {
                     const double x = t + 16 * r >= j ? a[m][r] : 0.0;
                     s2 = fma(x, x, s2);
                 }
@@ -959,9 +960,9 @@ __global__ __launch_bounds__(kBlock) void k_hqr(const double* __restrict__ y, in
                 const double tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
                 if (g == og) {
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) {
+                    for (int r = 0; r < RPL; ++r) {
                         const int row = t + 16 * r;
-                        V[j * 256 + row] = row == j ? v0 : (row > j ? a[m][r] : 0.0);
+                        V[j * VP + row] = row == j ? v0 : (row > j ? a[m][r] : 0.0);
                     }
                 }
                 if (lane == 0) {
@@ -971,30 +972,30 @@ __global__ __launch_bounds__(kBlock) void k_hqr(const double* __restrict__ y, in
             }
             __syncthreads();
             const double tau = tau_s[j];
-            double v[16];
+            double v[RPL];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) v[r] = V[j * 256 + t + 16 * r];
+            for (int r = 0; r < RPL; ++r) v[r] = V[j * VP + t + 16 * r];
             // columns past j: every later slot, and in slot m the columns
             // after jc (columns past K are zero and stay zero)
 #pragma unroll
             for (int mm = m; mm < NS; ++mm) {
                 double d = 0.0;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) d = fma(v[r], a[mm][r], d);
+                for (int r = 0; r < RPL; ++r) d = fma(v[r], a[mm][r], d);
                 d = row16_total(d) * tau;
                 if (mm == m) d = cw > jc ? d : 0.0;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) a[mm][r] = fma(-d, v[r], a[mm][r]);
+                for (int r = 0; r < RPL; ++r) a[mm][r] = fma(-d, v[r], a[mm][r]);
             }
         }
     }
     __syncthreads();
     // Q backwards: H_j changes only the columns c >= j
-    double q[NS][16];
+    double q[NS][RPL];
 #pragma unroll
     for (int m = 0; m < NS; ++m)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
+        for (int r = 0; r < RPL; ++r) {
             const int c = 16 * m + cw;
             q[m][r] = (c < K && t + 16 * r == c) ? 1.0 : 0.0;
         }
@@ -1005,18 +1006,18 @@ __global__ __launch_bounds__(kBlock) void k_hqr(const double* __restrict__ y, in
             const int j = 16 * m + jc;
             if (j >= K) continue;
             const double tau = tau_s[j];
-            double v[16];
+            double v[RPL];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) v[r] = V[j * 256 + t + 16 * r];
+            for (int r = 0; r < RPL; ++r) v[r] = V[j * VP + t + 16 * r];
 #pragma unroll
             for (int mm = m; mm < NS; ++mm) {
                 double d = 0.0;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) d = fma(v[r], q[mm][r], d);
+                for (int r = 0; r < RPL; ++r) d = fma(v[r], q[mm][r], d);
                 d = row16_total(d) * tau;
                 if (mm == m) d = cw >= jc ? d : 0.0;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) q[mm][r] = fma(-d, v[r], q[mm][r]);
+                for (int r = 0; r < RPL; ++r) q[mm][r] = fma(-d, v[r], q[mm][r]);
             }
         }
     }
@@ -1026,7 +1027,7 @@ __global__ __launch_bounds__(kBlock) void k_hqr(const double* __restrict__ y, in
         if (c < K) {
             const double sg = alpha_s[c] < 0.0 ? -1.0 : 1.0;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
+            for (int r = 0; r < RPL; ++r) {
                 const int row = t + 16 * r;
                 if (row < I) {
                     const size_t e = static_cast<size_t>(c) * I + row;
@@ -1044,19 +1045,29 @@ __global__ __launch_bounds__(kBlock) void k_hqr(const double* __restrict__ y, in
 
 static hipError_t launch_hqr(const double* y, int I, int K, bool dbl, void* q_out, double* q64,
                              hipStream_t s) {
-    const size_t lds = static_cast<size_t>(K) * 256 * sizeof(double);
+    const int rpl = I <= 256 ? 16 : 32;
+    const size_t lds = static_cast<size_t>(K) * 16 * rpl * sizeof(double);
     const int d = dbl ? 1 : 0;
-#define RH_HQR_CASE(N)                                                                        \
-    case N:                                                                                   \
-        hipLaunchKernelGGL(k_hqr<N>, dim3(1), dim3(kBlock), lds, s, y, I, K, q64, q_out, d); \
+#define RH_HQR_CASE(N, R)                                                                        \
+    case N:                                                                                      \
+        hipLaunchKernelGGL((k_hqr<N, R>), dim3(1), dim3(kBlock), lds, s, y, I, K, q64, q_out, d); \
         break;
-    switch ((K + 15) / 16) {
-        RH_HQR_CASE(1)
-        RH_HQR_CASE(2)
-        RH_HQR_CASE(3)
-        RH_HQR_CASE(4)
-        default:
-            return hipErrorInvalidValue;
+    if (rpl == 16) {
+        switch ((K + 15) / 16) {
+            RH_HQR_CASE(1, 16)
+            RH_HQR_CASE(2, 16)
+            RH_HQR_CASE(3, 16)
+            RH_HQR_CASE(4, 16)
+            default:
+                return hipErrorInvalidValue;
+        }
+    } else {
+        switch ((K + 15) / 16) {
+            RH_HQR_CASE(1, 32)
+            RH_HQR_CASE(2, 32)
+            default:
+                return hipErrorInvalidValue;
+        }
     }
 #undef RH_HQR_CASE
     return hipGetLastError();

@@ -118,7 +118,8 @@ def test_ttm_and_gram(dims, dtype):
     np.testing.assert_array_equal(out.cpu().numpy(), x.reshape(-1, order="F"))
 
 
-@pytest.mark.parametrize("I,K", [(200, 35), (37, 11), (500, 30), (64, 64), (15, 15), (256, 64), (257, 64), (1, 1)])
+@pytest.mark.parametrize("I,K", [(200, 35), (37, 11), (500, 30), (64, 64), (15, 15), (256, 64), (257, 64),
+                                 (1, 1), (512, 32), (513, 32), (300, 40), (700, 30)])
 def test_orthonormalize(I, K):
     rng = np.random.default_rng(I * 100 + K)
     y = rng.standard_normal((I, K)) @ np.diag(np.logspace(0, -3, K))
@@ -131,9 +132,9 @@ def test_orthonormalize(I, K):
 
 
 def test_orthonormalize_rank_deficient_shifts():
-    # taller than 256 rows: CholeskyQR2, whose Gram is singular here
+    # taller than 512 rows: CholeskyQR2, whose Gram is singular here
     rng = np.random.default_rng(9)
-    base = rng.standard_normal((300, 6))
+    base = rng.standard_normal((600, 6))
     y = base @ rng.standard_normal((6, 20))          # rank 6, K = 20
     q, q64, flags = api.orthonormalize(torch.from_numpy(y).cuda(), torch.float64)
     q = q64.cpu().numpy()
@@ -144,7 +145,7 @@ def test_orthonormalize_rank_deficient_shifts():
 
 
 def test_orthonormalize_rank_deficient_householder():
-    # up to 256 rows: Householder QR, no breakdown to report
+    # up to 256 rows (512 for K <= 32): Householder QR, no breakdown to report
     rng = np.random.default_rng(9)
     base = rng.standard_normal((120, 6))
     y = base @ rng.standard_normal((6, 20))          # rank 6, K = 20

@@ -12,7 +12,11 @@ Each check is fixed by the mathematics, not by the oracle itself:
   to the deterministic THOSVD / STHOSVD computed by brute-force SVD;
 * lower bound E ||X|| >= max_n tau_n, quasi-optimality sum_n tau_n^2;
 * the expected spectral error bound of Algorithm 1 (Section 3.1), over 200 seeds;
-* noisy data at 20 dB reach a fit near 90 percent (Section 8).
+* noisy data at 20 dB reach a fit near 90 percent (Section 8);
+* the sign rule on hand-built matrices (largest magnitude, ties to the lower row);
+* the power step against its definition (X X^T)^q X Omega (Algorithm 1
+  step 2), formed without the intermediate QRs on a well-conditioned matrix,
+  for Algorithm 1, RP-HOSVD and the first mode of R-STHOSVD.
 """
 import numpy as np
 import pytest
@@ -184,3 +188,77 @@ def test_mode_order_permutation():
     assert res.rel_error <= 1e-12
     with pytest.raises(ValueError):
         r_sthosvd(x, (3, 2, 3, 2), 2, 1, seed=4, mode_order=(0, 0, 1, 2))
+
+
+def test_canonical_signs_hand_built():
+    # column 0: the largest magnitude (-5) is negative -> flip; column 1: the
+    # largest (+4) positive -> keep; column 2: a tie |-3| = |3| between rows 1
+    # and 3 goes to the lower row, whose entry is negative -> flip; column 3: a
+    # zero column keeps +1
+    u = np.array([[1.0, 4.0, 0.5, 0.0],
+                  [-5.0, -2.0, -3.0, 0.0],
+                  [2.0, 1.0, 1.0, 0.0],
+                  [0.0, 0.0, 3.0, 0.0]])
+    np.testing.assert_array_equal(canonical_signs(u), [-1.0, 1.0, -1.0, 1.0])
+    # the tie resolved the other way when the lower row holds the positive entry
+    np.testing.assert_array_equal(canonical_signs(np.array([[3.0], [-3.0]])), [1.0])
+    np.testing.assert_array_equal(canonical_signs(np.array([[-3.0], [3.0]])), [-1.0])
+    # after applying the signs every column's largest-magnitude entry is positive
+    rng = np.random.default_rng(31)
+    v = rng.standard_normal((9, 6))
+    w = v * canonical_signs(v)
+    for k in range(6):
+        i = int(np.flatnonzero(np.abs(w[:, k]) == np.abs(w[:, k]).max())[0])
+        assert w[i, k] > 0
+
+
+def _projector(m):
+    qm, _ = np.linalg.qr(m)
+    return qm @ qm.T
+
+
+def test_power_step_spans_the_definition():
+    # Algorithm 1 step 2 defines the sketch as (X X^T)^q X Omega; the oracle
+    # applies it one factor at a time with a QR in between.  On a small, well
+    # conditioned matrix the unstabilised product is accurate, so both ranges
+    # must coincide, and differ from the q = 0 range.
+    rng = np.random.default_rng(32)
+    I, J, R, p = 30, 40, 5, 3
+    u, _ = np.linalg.qr(rng.standard_normal((I, I)))
+    v, _ = np.linalg.qr(rng.standard_normal((J, I)))
+    a = (u * np.linspace(1.0, 0.3, I)) @ v.T
+    om = philox.omega(3, 0, 2, J, R + p)
+    for q in (1, 2):
+        res = brsvd(a, R, p, q, lambda JJ, KK: philox.omega(3, 0, 2, JJ, KK))
+        y = np.linalg.matrix_power(a @ a.T, q) @ a @ om
+        np.testing.assert_allclose(res.Q @ res.Q.T, _projector(y), atol=1e-10)
+    res0 = brsvd(a, R, p, 0, lambda JJ, KK: philox.omega(3, 0, 2, JJ, KK))
+    np.testing.assert_allclose(res0.Q @ res0.Q.T, _projector(a @ om), atol=1e-10)
+    res1 = brsvd(a, R, p, 1, lambda JJ, KK: philox.omega(3, 0, 2, JJ, KK))
+    assert np.linalg.norm(res1.Q @ res1.Q.T - res0.Q @ res0.Q.T) > 0.1
+
+
+def test_rp_hosvd_power_step_spans_the_definition():
+    # with p = 0 every K_n = R_n, so U_n spans the range of Q_n itself:
+    # (X_(n) X_(n)^T)^q X_(n) Omega_n with Omega_n = Omega(seed, n, tag 1)
+    x, _, _ = tucker_tensor((12, 10, 9), (4, 4, 3), seed=33, noise=0.3, dtype=np.float64)
+    ranks = (3, 3, 2)
+    for q in (0, 1):
+        res = rp_hosvd(x, ranks, 0, q, seed=5)
+        for n in range(3):
+            a = unfold(x, n)
+            om = philox.omega_unfolding(5, n, philox.TAG_RP_HOSVD, x.shape, ranks[n])
+            y = np.linalg.matrix_power(a @ a.T, q) @ a @ om
+            u = res.factors[n]
+            np.testing.assert_allclose(u @ u.T, _projector(y), atol=1e-10)
+
+
+def test_r_sthosvd_power_step_spans_the_definition():
+    # the first mode of Algorithm 8 is Algorithm 1 on X_(1) with Omega(seed, 0, tag 2)
+    x, _, _ = tucker_tensor((12, 10, 9), (4, 4, 3), seed=34, noise=0.3, dtype=np.float64)
+    res = r_sthosvd(x, (3, 3, 2), 2, 1, seed=6, keep_trace=True)
+    n, s0, r0 = res.trace[0]
+    a = unfold(s0, n)
+    om = philox.omega_unfolding(6, n, philox.TAG_R_STHOSVD, s0.shape, 5)
+    y = (a @ a.T) @ a @ om
+    np.testing.assert_allclose(r0.Q @ r0.Q.T, _projector(y), atol=1e-10)

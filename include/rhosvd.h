@@ -53,7 +53,9 @@ extern "C" {
 #endif
 
 #define RHOSVD_MAX_ORDER 16
-#define RHOSVD_MAX_K 128      /* largest sketch width K = R + p handled */
+#define RHOSVD_MAX_K 128      /* size of the per-mode sigma rows of rhosvd_report */
+#define RHOSVD_MAX_SKETCH 64  /* largest sketch width K_n = min(R_n + p, I_n, J_n) the
+                                 kernels take; larger problems return RHOSVD_EUNSUPPORTED */
 
 typedef enum {
     RHOSVD_OK = 0,
@@ -75,12 +77,20 @@ enum { RHOSVD_PREC_F64 = 0, RHOSVD_PREC_F32 = 1, RHOSVD_PREC_BF16 = 2 };
 /* report.flags bits (warnings, set on the device) */
 #define RHOSVD_FLAG_K_CAPPED     0x1u  /* some K_n < R_n + p (capped by I_n or J_n) */
 #define RHOSVD_FLAG_CQR_SHIFTED  0x2u  /* a Gram matrix needed the shifted Cholesky */
-#define RHOSVD_FLAG_EVD_NOCONV   0x4u  /* Jacobi EVD hit its sweep limit */
+#define RHOSVD_FLAG_EVD_NOCONV   0x4u  /* an eigen-decomposition failed its check: residual
+                                          norm(T z - lambda z) > 1e-10 norm(T) or
+                                          |z_i^T z_j - delta_ij| > 1e-10 on the tridiagonal T */
 #define RHOSVD_FLAG_QR_HOUSEHOLDER 0x8u /* CholeskyQR broke down even with the shift (Y numerically
                                            rank deficient); that basis came from Householder QR */
 
-/* params.flags bits */
+/* params.flags bits; a call with any other bit set is rejected (EINVAL) */
 #define RHOSVD_OPT_NONE 0u
+
+/* Context options (rhosvd_set_option). */
+#define RHOSVD_OPTION_KERNELS 1   /* which streaming-kernel families may run: */
+#define RHOSVD_KERNELS_AUTO   0   /*   the fastest that takes each shape (default) */
+#define RHOSVD_KERNELS_TILED  1   /*   only the workgroup-tiled FP32/FP64 kernels (the general
+                                       fallback; every precision then computes in FP32/FP64) */
 
 typedef struct rhosvd_ctx rhosvd_ctx;
 
@@ -129,6 +139,12 @@ int32_t rhosvd_last_hip_error(void);
  * device index out of range, EHIP if the runtime fails. */
 int32_t rhosvd_create(rhosvd_ctx** ctx, int32_t device);
 void rhosvd_destroy(rhosvd_ctx* ctx);
+
+/* Set a context option (RHOSVD_OPTION_*) for the calls made with this context
+ * afterwards.  EINVAL for a NULL context, an unknown option or a value outside
+ * the option's set.  With RHOSVD_KERNELS_TILED a decomposition may need more
+ * workspace than rhosvd_workspace_size reports (it then returns ENOMEM). */
+int32_t rhosvd_set_option(rhosvd_ctx* ctx, int32_t option, int64_t value);
 
 /* Bytes of device workspace rhosvd_decompose needs for this problem.
  * Pure host computation (no HIP call); EINVAL/EUNSUPPORTED as for decompose. */
@@ -198,10 +214,13 @@ int32_t rhosvd_orthonormalize(rhosvd_ctx* ctx, const double* y, int64_t I, int32
                               void* stream);
 
 /* Symmetric eigen-decomposition C = V diag(lambda) V^T of a K x K matrix
- * (device double, column-major) by cyclic Jacobi in FP64, eigenvalues sorted
- * descending (Algorithm 1 step 5 through the Gram of B).  v: K x K double,
- * lambda: K doubles (device).  flags as above (RHOSVD_FLAG_EVD_NOCONV); bits
- * 16..23 receive the number of Jacobi sweeps performed.  K <= 64. */
+ * (device double, column-major), eigenvalues sorted descending (Algorithm 1
+ * step 5 through the Gram of B; the EVD variant of Section 4): FP64
+ * Householder tridiagonalisation, bisection on Sturm counts and inverse
+ * iteration with Gram-Schmidt inside clusters of close eigenvalues.
+ * v: K x K double, lambda: K doubles (device).  flags (optional device
+ * uint32) gets RHOSVD_FLAG_EVD_NOCONV or-ed in when the eigenpairs fail the
+ * residual / orthogonality check.  1 <= K <= RHOSVD_MAX_SKETCH. */
 int32_t rhosvd_sym_evd(rhosvd_ctx* ctx, const double* c, int32_t K, double* v,
                        double* lambda, uint32_t* flags, void* stream);
 

@@ -19,6 +19,8 @@ F32, F64 = 0, 1
 RP_HOSVD, R_STHOSVD = 0, 1
 PREC_F64, PREC_F32, PREC_BF16 = 0, 1, 2
 FLAG_K_CAPPED, FLAG_CQR_SHIFTED, FLAG_EVD_NOCONV, FLAG_QR_HOUSEHOLDER = 0x1, 0x2, 0x4, 0x8
+OPTION_KERNELS = 1
+KERNELS_AUTO, KERNELS_TILED = 0, 1
 
 
 class Tensor(ctypes.Structure):
@@ -57,6 +59,7 @@ _PROTOS = {
     "rhosvd_last_hip_error": (_I32, []),
     "rhosvd_create": (_I32, [ctypes.POINTER(_P), _I32]),
     "rhosvd_destroy": (None, [_P]),
+    "rhosvd_set_option": (_I32, [_P, _I32, _I64]),
     "rhosvd_workspace_size": (_I32, [ctypes.POINTER(Tensor), ctypes.POINTER(Params),
                                      ctypes.POINTER(_SZ)]),
     "rhosvd_decompose": (_I32, [_P, ctypes.POINTER(Tensor), ctypes.POINTER(Params), _P, _SZ,

@@ -7,6 +7,7 @@ tensor with Fortran strides (see `to_device`), or a flat 1-D buffer plus
 explicit `dims`.  Column-major matrices are returned as transposed views of
 contiguous tensors, so `U.shape == (I_n, R_n)` with strides (1, I_n).
 """
+import contextlib
 import ctypes
 from dataclasses import dataclass, field
 from typing import List, Optional
@@ -27,6 +28,21 @@ def _context(device_index):
         L.check(lib.rhosvd_create(ctypes.byref(c), int(device_index)), "rhosvd_create")
         _ctx_cache[device_index] = c
     return c
+
+
+@contextlib.contextmanager
+def kernel_family(name, device_index=0):
+    """Within the block, the context of `device_index` runs only the given
+    streaming-kernel family ("tiled": the workgroup-tiled FP32/FP64 kernels;
+    "auto": the default choice)."""
+    code = {"auto": L.KERNELS_AUTO, "tiled": L.KERNELS_TILED}[name]
+    lib = L.load()
+    ctx = _context(device_index)
+    L.check(lib.rhosvd_set_option(ctx, L.OPTION_KERNELS, code), "rhosvd_set_option")
+    try:
+        yield
+    finally:
+        L.check(lib.rhosvd_set_option(ctx, L.OPTION_KERNELS, L.KERNELS_AUTO), "rhosvd_set_option")
 
 
 def _dtype_code(dt):

@@ -95,17 +95,16 @@ hipError_t launch_cqr_global(const double* y, int64_t I, int K, bool dbl, void* 
                              double* q64, uint32_t* flags, hipStream_t s);
 size_t cqr_lds_bytes(int64_t I, int K);
 
-// Symmetric EVD of the K x K Gram (sorted descending) followed by the factor
-// step: U = Q V[:, :R] (identity V when use_v == 0), canonical signs,
-// M = V_R diag(s), sigma = sqrt(max(lambda, 0))[:R].  q == nullptr: EVD only
-// (v_out, lam_out).  u64: evd_qwork_doubles(K, I) doubles of scratch for Q
-// when it does not fit in LDS.  vwork (K x K) and lwork (K) doubles receive
-// the tridiagonal EVD's output, which the factor kernel reads; with
-// RHOSVD_EVD=jacobi the factor kernel runs its own Jacobi sweeps instead.
-hipError_t launch_evd_factor(bool dbl, const double* c, int K, double* v_out, double* lam_out,
-                             uint32_t* flags, const void* q, int64_t I, int R, int use_v,
-                             void* u_out, void* m_out, double* sigma, double* u64,
-                             double* vwork, double* lwork, hipStream_t s);
+// Symmetric EVD of the K x K Gram C (FP64, sorted descending) followed, in
+// the same launch, by the factor step: U = Q V[:, :R] (identity V when
+// use_v == 0), canonical signs, M = V_R (K x R, same signs), sigma =
+// sqrt(max(lambda, 0))[:R].  u64: evd_qwork_doubles(K, I) doubles of scratch
+// for Q when it does not fit in LDS.  flags receives RHOSVD_FLAG_EVD_NOCONV
+// when the eigenpairs fail the residual / orthogonality check.
+hipError_t launch_evd_factor(bool dbl, const double* c, int K, uint32_t* flags, const void* q,
+                             int64_t I, int R, int use_v, void* u_out, void* m_out, double* sigma,
+                             double* u64, hipStream_t s);
+// The EVD alone: v (K x K), lambda (K), descending.
 hipError_t launch_evd(const double* c, int K, double* v, double* lambda, uint32_t* flags,
                       hipStream_t s);
 size_t evd_qwork_doubles(int K, int64_t I);

@@ -4,8 +4,10 @@
 //                   triangular update on the f64 matrix cores, the K x K
 //                   Cholesky factor and its inverse in one wave's registers
 //                   (Algorithm 1 step 3)
-//   k_evd_factor    Jacobi EVD of the K x K Gram (Algorithm 1 step 5) fused
-//                   with U = Q V[:, :R], sign canonicalisation, M = V_R diag(s)
+//   k_hqr           Householder QR of Y in one workgroup (step 3)
+//   k_evd_tri       symmetric EVD of the K x K Gram (Algorithm 1 step 5) by
+//                   tridiagonalisation, multisection and inverse iteration,
+//                   fused with U = Q V[:, :R], sign canonicalisation, M = V_R
 //                   and sigma (steps 6-7)
 #include <hip/hip_runtime.h>
 
@@ -566,42 +568,6 @@ hipError_t launch_cqr_lds(const double* y, int64_t I, int K, bool dbl, void* q_o
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// Jacobi EVD (cyclic, round-robin parallel ordering, rotations as in Golub &
-// Van Loan sym.schur2) of A (LDS, row-major Ke x Ke, Ke even <= 64) with V
-// accumulated.  The rows and columns of A and the columns of V are kept in a
-// moving layout in which the pairs of every round occupy the slots (2m,
-// 2m + 1): after a round each slot moves as a player of the circle method of
-// round-robin scheduling (slot 0 stays, the others advance around one cycle
-// of length Ke - 1), so every pair of indices meets once per sweep and the
-// layout is the original one again at every sweep boundary.  A thread owns
-// fixed 2 x 2 blocks for the whole iteration: a block {2m1, 2m1+1} x {2m2,
-// 2m2+1} of A (m1 <= m2) becomes J1^T A J2, a block of two rows of V and the
-// column pair m2 becomes V J2, and the results go to the permuted slots of
-// the other buffer (A and V are double-buffered, one barrier per round).  V
-// runs one round behind A: its blocks take the previous round's rotations,
-// so their loads, arithmetic and stores overlap the current round's pivot
-// reads and rotation arithmetic; a last V step follows the last round.  Only
-// the upper triangle of A is kept: an entry (r, c) is stored at (min(r, c),
-// max(r, c)), so the blocks m1 < m2 are always read from stored entries and
-// the diagonal blocks use only a_pp, a_pq and a_qq.
-// Diagonal blocks take the closed form a_pp - t a_pq, a_qq + t a_pq and an
-// exact zero.  Stops when the off-diagonal mass is at most 1e-28 of the
-// total (relative RMS 1e-14); rotations with a_pq^2 <= 1e-36 |a_pp a_qq| are
-// replaced by the identity.
-// ---------------------------------------------------------------------------
-constexpr int kSweeps = 30;
-
-// slot of the next round for the element in slot s (Ke >= 4): the top slots
-// 2, 4, ..., Ke - 2 advance by two, Ke - 2 drops to Ke - 1, the bottom slots
-// 3, 5, ..., Ke - 1 move back by two, slot 1 rises to 2, slot 0 stays.
-__device__ __forceinline__ int rr_next(int s, int Ke) {
-    if (Ke == 2 || s == 0) return s;
-    if (s == 1) return 2;
-    if ((s & 1) == 0) return s + 2 < Ke ? s + 2 : Ke - 1;
-    return s - 2;
-}
-
 // 1 / x and 1 / sqrt(x) from the hardware estimates with one Newton step.
 __device__ __forceinline__ double rcp_nr(double x) {
     const double y = __builtin_amdgcn_rcp(x);
@@ -611,209 +577,6 @@ __device__ __forceinline__ double rsq_nr(double x) {
     const double y = __builtin_amdgcn_rsq(x);
     const double r = fma(-x * y, y, 1.0);
     return fma(0.5 * y, r, y);
-}
-
-// Rotation (c, s, t) annihilating a_pq (Golub & Van Loan sym.schur2):
-// tau = (a_qq - a_pp) / (2 a_pq), t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
-// c = 1 / sqrt(1 + t^2), s = t c; evaluated as t = sign(d) e / (|d| +
-// sqrt(d^2 + e^2)) with d = a_qq - a_pp, e = 2 a_pq scaled by a power of two.
-__device__ __forceinline__ void sym_schur2(double app, double aqq, double apq, double& c,
-                                           double& s, double& t) {
-    const double d = aqq - app, e = 2.0 * apq;
-    const int ed = __builtin_amdgcn_frexp_exp(d), ee = __builtin_amdgcn_frexp_exp(e);
-    const int ex = ed > ee ? ed : ee;
-    const double dn = __builtin_amdgcn_ldexp(d, -ex), en = __builtin_amdgcn_ldexp(e, -ex);
-    const double h = fma(dn, dn, en * en);
-    const double r = h * rsq_nr(h);
-    t = (d >= 0.0 ? en : -en) * rcp_nr(fabs(dn) + r);
-    c = rsq_nr(fma(t, t, 1.0));
-    s = t * c;
-}
-
-constexpr int kJacA = 3;   // A blocks Ke/2 (Ke/2 + 1) / 2 <= 3 * 256 for Ke <= 64
-constexpr int kJacV = 4;   // V blocks (Ke/2)^2 <= 4 * 256
-
-// Rotation slots: per wave (each wave computes all rotations of a round
-// itself, so the waves meet only at the round's barrier), per round parity
-// (V uses the previous round's), Ke/2 pairs.
-constexpr int kRotSlots = RHOSVD_MAX_K / 2;
-constexpr size_t kRotDoubles = static_cast<size_t>(kBlock / kWave) * 2 * kRotSlots * 4;
-
-// A items: the Ke/2 diagonal blocks, then the off-diagonal blocks m1 < m2;
-// V items: (row pair, column pair).  Only lanes with an item (and, for the
-// rotations, a pair) touch LDS.  rot: kRotDoubles of LDS.  On
-// return A and V point at the current buffers (A0/A2, V0/V2).
-__device__ bool jacobi_lds(double*& A, double*& V, double* A2, double* V2, double* rot, int Ke,
-                           int* sweeps) {
-    __shared__ double red[2][kBlock / kWave];
-    __shared__ int conv;
-    const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
-    const int half = Ke / 2;
-    const int nA = half * (half + 1) / 2, nV = half * half;
-    double* const A0 = A;
-    double* const V0 = V;
-    double* const rw = rot + static_cast<size_t>(wave) * 2 * kRotSlots * 4;
-    // A items: read offset, rotation slots, target offsets (upper triangle)
-    int ard[kJacA], am1[kJacA], am2[kJacA], awr[kJacA][4];
-    bool aok[kJacA], vok[kJacV];
-#pragma unroll
-    for (int u = 0; u < kJacA; ++u) {
-        int it = tid + u * kBlock;
-        aok[u] = it < nA;
-        it = it < nA ? it : nA - 1;
-        int m1, m2;
-        if (it < half) {
-            m1 = m2 = it;
-        } else {
-            int rem = it - half;
-            m1 = 0;
-            while (rem >= half - 1 - m1) {
-                rem -= half - 1 - m1;
-                ++m1;
-            }
-            m2 = m1 + 1 + rem;
-        }
-        ard[u] = 2 * m1 * Ke + 2 * m2;
-        am1[u] = m1;
-        am2[u] = m2;
-        const int c0 = rr_next(2 * m2, Ke), c1 = rr_next(2 * m2 + 1, Ke);
-        const int r0 = rr_next(2 * m1, Ke), r1 = rr_next(2 * m1 + 1, Ke);
-        const auto at = [&](int r, int c) { return r <= c ? r * Ke + c : c * Ke + r; };
-        awr[u][0] = at(r0, c0);
-        awr[u][1] = at(r0, c1);
-        awr[u][2] = at(r1, c0);
-        awr[u][3] = at(r1, c1);
-    }
-    // V items: read offset, column pair, target offsets
-    int vrd[kJacV], vm2[kJacV], vwr[kJacV][2];
-#pragma unroll
-    for (int u = 0; u < kJacV; ++u) {
-        int it = tid + u * kBlock;
-        vok[u] = it < nV;
-        it = it < nV ? it : nV - 1;
-        const int rp = it / half, m2 = it - rp * half;
-        vrd[u] = 2 * rp * Ke + 2 * m2;
-        vm2[u] = m2;
-        vwr[u][0] = 2 * rp * Ke + rr_next(2 * m2, Ke);
-        vwr[u][1] = 2 * rp * Ke + rr_next(2 * m2 + 1, Ke);
-    }
-    const int mr = lane;   // this lane's pair for the rotations (lanes < Ke/2)
-    // V <- V J P with the rotations stored under parity `par`
-    const auto v_step = [&](int par, double* Vn) {
-        const double* rv = rw + par * kRotSlots * 4;
-#pragma unroll
-        for (int u = 0; u < kJacV; ++u) {
-            if (u * kBlock < nV && vok[u]) {
-                const double2 x0 = *reinterpret_cast<const double2*>(V + vrd[u]);
-                const double2 x1 = *reinterpret_cast<const double2*>(V + vrd[u] + Ke);
-                const double2 r2 = *reinterpret_cast<const double2*>(rv + 4 * vm2[u]);
-                Vn[vwr[u][0]] = r2.x * x0.x - r2.y * x0.y;
-                Vn[vwr[u][1]] = r2.y * x0.x + r2.x * x0.y;
-                Vn[vwr[u][0] + Ke] = r2.x * x1.x - r2.y * x1.y;
-                Vn[vwr[u][1] + Ke] = r2.y * x1.x + r2.x * x1.y;
-            }
-        }
-    };
-    int g = 0;   // rounds done
-    for (int sweep = 0; sweep < kSweeps; ++sweep) {
-        // the upper triangle stands for both halves
-        double off = 0.0, tot = 0.0;
-        for (int e = tid; e < Ke * Ke; e += kBlock) {
-            const int r = e / Ke, c = e - r * Ke;
-            if (r <= c) {
-                const double x = A[e] * A[e];
-                tot += (r == c) ? x : 2.0 * x;
-                if (r != c) off += 2.0 * x;
-            }
-        }
-        off = wave_sum(off);
-        tot = wave_sum(tot);
-        if (lane == 0) {
-            red[0][wave] = off;
-            red[1][wave] = tot;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double o = 0.0, t = 0.0;
-            for (int w = 0; w < kBlock / kWave; ++w) {
-                o += red[0][w];
-                t += red[1][w];
-            }
-            conv = (o <= 1e-28 * t) ? 1 : 0;
-        }
-        __syncthreads();
-        *sweeps = sweep;
-        if (conv) break;
-        for (int round = 0; round < Ke - 1; ++round, ++g) {
-            const int par = g & 1;
-            double* const An = (A == A0) ? A2 : A0;
-            double* const Vn = (V == V0) ? V2 : V0;
-            // this round's blocks of A
-            double2 x0[kJacA], x1[kJacA];
-#pragma unroll
-            for (int u = 0; u < kJacA; ++u) {
-                if (u * kBlock < nA && aok[u]) {
-                    x0[u] = *reinterpret_cast<const double2*>(A + ard[u]);
-                    x1[u] = *reinterpret_cast<const double2*>(A + ard[u] + Ke);
-                }
-            }
-            // this round's rotations (lanes < Ke/2)
-            if (lane < half) {
-                const double2 pp = *reinterpret_cast<const double2*>(A + 2 * mr * (Ke + 1));
-                const double aqq = A[(2 * mr + 1) * (Ke + 1)];
-                double c, sn, t;
-                sym_schur2(pp.x, aqq, pp.y, c, sn, t);
-                // the identity for a negligible a_pq (the formula is not used there)
-                if (!(pp.y * pp.y > 1e-36 * fabs(pp.x * aqq))) {
-                    c = 1.0;
-                    sn = 0.0;
-                    t = 0.0;
-                }
-                double* r = rw + (par * kRotSlots + lane) * 4;
-                *reinterpret_cast<double2*>(r) = make_double2(c, sn);
-                r[2] = t;
-            }
-            // V, one round behind
-            if (g > 0) v_step(par ^ 1, Vn);
-            const double* ra = rw + par * kRotSlots * 4;
-#pragma unroll
-            for (int u = 0; u < kJacA; ++u) {
-                if (u * kBlock < nA && aok[u]) {
-                    const double2 r2 = *reinterpret_cast<const double2*>(ra + 4 * am2[u]);
-                    const double2 r1 = *reinterpret_cast<const double2*>(ra + 4 * am1[u]);
-                    const double t1 = ra[4 * am1[u] + 2];
-                    const double c2 = r2.x, s2 = r2.y, c1 = r1.x, s1 = r1.y;
-                    const double a = x0[u].x, b = x0[u].y, d = x1[u].x, e = x1[u].y;
-                    const double t00 = c2 * a - s2 * b, t01 = s2 * a + c2 * b;
-                    const double t10 = c2 * d - s2 * e, t11 = s2 * d + c2 * e;
-                    double n00 = c1 * t00 - s1 * t10, n01 = c1 * t01 - s1 * t11;
-                    double n10 = s1 * t00 + c1 * t10, n11 = s1 * t01 + c1 * t11;
-                    if (am1[u] == am2[u]) {
-                        n00 = a - t1 * b;
-                        n11 = e + t1 * b;
-                        n01 = 0.0;
-                        n10 = 0.0;
-                    }
-                    // (a diagonal block stores its zero twice, at (p, q))
-                    An[awr[u][0]] = n00;
-                    An[awr[u][1]] = n01;
-                    An[awr[u][2]] = n10;
-                    An[awr[u][3]] = n11;
-                }
-            }
-            __syncthreads();
-            A = An;
-            if (g > 0) V = Vn;
-        }
-    }
-    // the last round's step of V
-    if (g > 0) {
-        double* const Vn = (V == V0) ? V2 : V0;
-        v_step((g - 1) & 1, Vn);
-        __syncthreads();
-        V = Vn;
-    }
-    return conv != 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -841,9 +604,12 @@ __device__ bool jacobi_lds(double*& A, double*& V, double* A2, double* V2, doubl
 //      earlier vectors of its cluster (eigenvalues closer than 1e-3 norm(T),
 //      as in dstein).
 //   4. wave 0: z <- H_0 ... H_{K-3} z.
+//   5. convergence check on T: the residual norm(T z - lambda z) and the
+//      orthogonality of the vectors against 1e-10 norm(T) and 1e-10; a miss
+//      sets RHOSVD_FLAG_EVD_NOCONV.
 // Outputs: v (K x K column-major, column r the eigenvector of the r-th largest
-// eigenvalue) and lambda (descending); with report_iters, bits 16..23 of
-// flags receive the inverse-iteration count.  LDS: evd_tri_lds_doubles(K).
+// eigenvalue) and lambda (descending), or with FACTOR the factor step on them
+// in the same launch.  LDS: evd_tri_lds_doubles(K), then the eigenpairs.
 // ---------------------------------------------------------------------------
 constexpr int kTriIters = 2;   // each step shrinks the error by about eps norm(T) / gap
 constexpr int kBisectSteps = 18;
@@ -1078,6 +844,128 @@ hipError_t launch_hqr_fwd(const double* y, int I, int K, bool dbl, void* q_out, 
     return launch_hqr(y, I, K, dbl, q_out, q64, s);
 }
 
+// Factor step (Algorithm 1 steps 6-7) on the sorted eigenpairs of the Gram:
+// U = Q V[:, :R] (V = identity when use_v == 0), canonical signs (each
+// column's largest-magnitude entry positive, the lowest row on ties),
+// M = V_R with the same signs (K x R), sigma = sqrt(max(lambda, 0))[:R].
+// Q (I x K column-major, T) is staged row-major with pitch K16 (zero padded
+// to I16 rows) at Qs (LDS, or global scratch when it does not fit); U is
+// formed on the f64 matrix cores in place of Q, one 16-row block per wave at
+// a time.  Vs: K x K column-major (LDS), lamS: K (LDS).
+template <typename T>
+__device__ void factor_step(int K, int K16, int I, int I16, int R, int use_v, const double* Vs,
+                            const double* lamS, const T* __restrict__ q, double* Qs,
+                            T* __restrict__ u_out, T* __restrict__ m_out,
+                            double* __restrict__ sigma) {
+    __shared__ double sgn[RHOSVD_MAX_K];
+    const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
+    // the padding first, then Q in its own column-major order (coalesced),
+    // eight loads in flight per thread
+    for (int e = tid; e < I16 * K16; e += kBlock) {
+        const int i = e / K16, k = e - i * K16;
+        if (i >= I || k >= K) Qs[e] = 0.0;
+    }
+    const int n = I * K;
+    for (int e0 = tid; e0 < n; e0 += 8 * kBlock) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * kBlock;
+            v[u] = q[e < n ? e : n - 1];
+        }
+        int k = e0 / I, i = e0 - k * I;
+        const int dk = kBlock / I, di = kBlock - dk * I;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (e0 + u * kBlock < n) Qs[i * K16 + k] = static_cast<double>(v[u]);
+            i += di;
+            k += dk;
+            if (i >= I) {
+                i -= I;
+                ++k;
+            }
+        }
+    }
+    __syncthreads();
+    {
+        // V_R's fragments stay in registers for all row blocks (K16 <= 64,
+        // R <= 64); each row block loads its Q fragments at once
+        const int m = lane & 15, kq = lane >> 4;
+        const int nib = I16 >> 4, nrb = (R + 15) >> 4, nst = K16 >> 2;
+        double vb[4][16];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int st = 0; st < 16; ++st) {
+                const int k = 4 * st + kq, rcol = 16 * rb + m;
+                double b = 0.0;
+                if (rb < nrb && st < nst && rcol < R && k < K)
+                    b = use_v ? Vs[rcol * K + k] : (k == rcol ? 1.0 : 0.0);
+                vb[rb][st] = b;
+            }
+        for (int ib = wave; ib < nib; ib += kBlock / kWave) {
+            const double* qa = Qs + (16 * ib + m) * K16 + kq;
+            double a[16];
+#pragma unroll
+            for (int st = 0; st < 16; ++st) a[st] = st < nst ? qa[4 * st] : 0.0;
+            f64x4 acc[4];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                acc[rb] = zero4<f64x4>();
+                if (rb < nrb) {
+#pragma unroll
+                    for (int st = 0; st < 16; ++st)
+                        if (st < nst) acc[rb] = Mma<double>::step(a[st], vb[rb][st], acc[rb]);
+                }
+            }
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                if (rb < nrb) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = 16 * ib + Mma<double>::row(kq, r), col = 16 * rb + m;
+                        if (col < R) Qs[row * K16 + col] = acc[rb][r];
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int r = wave; r < R; r += kBlock / kWave) {
+        double best = -1.0;
+        int bi = 0x7fffffff;
+        for (int i = lane; i < I; i += kWave) {
+            const double a = fabs(Qs[i * K16 + r]);
+            if (a > best) {
+                best = a;
+                bi = i;
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(best, o, kWave);
+            const int oi = __shfl_xor(bi, o, kWave);
+            if (ob > best || (ob == best && oi < bi)) {
+                best = ob;
+                bi = oi;
+            }
+        }
+        if (lane == 0) sgn[r] = (Qs[bi * K16 + r] < 0.0) ? -1.0 : 1.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < I * R; e += kBlock) {
+        const int r = e / I, i = e - r * I;
+        u_out[e] = static_cast<T>(sgn[r] * Qs[i * K16 + r]);
+    }
+    for (int e = tid; e < K * R; e += kBlock) {
+        const int r = e / K, k = e - r * K;
+        const double vv = use_v ? Vs[r * K + k] : (k == r ? 1.0 : 0.0);
+        m_out[e] = static_cast<T>(sgn[r] * vv);
+    }
+    if (sigma)
+        for (int r = tid; r < R; r += kBlock) sigma[r] = sqrt(fmax(lamS[r], 0.0));
+}
+
 // Start vector of inverse iteration: entries in [-1, 1) from a 32-bit hash
 // of (i, j) (an integer mixer of the murmur finaliser kind).
 __device__ __forceinline__ double start_entry(int i, int j) {
@@ -1094,11 +982,14 @@ __device__ __forceinline__ double start_entry(int i, int j) {
 // (length KB) are unrolled, so the kernel stays small enough for the
 // instruction cache.  LDS vectors have pitch kTriP and are zero past K, so
 // those loops need no bounds.
-template <int KB>
+template <int KB, typename T, bool FACTOR>
 __global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ cin, int K,
                                                    double* __restrict__ v_out,
                                                    double* __restrict__ lam_out, uint32_t* flags,
-                                                   int report_iters) {
+                                                   const T* __restrict__ q, int I, int R, int use_v,
+                                                   T* __restrict__ u_out, T* __restrict__ m_out,
+                                                   double* __restrict__ sigma,
+                                                   double* __restrict__ qwork, int staged) {
     extern __shared__ __align__(16) double shd[];
     double* hv = shd;                                  // kTriP x kTriP: row k = v of H_k
     double* lu = hv + kTriP * kTriP;                   // [3][K][64] factor of T - lambda I, per lane
@@ -1109,6 +1000,13 @@ __global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ c
     double* lam = ee + kTriP;
     double* bc = lam + kTriP;                          // broadcast of v
     double* bw = bc + kTriP;                           // broadcast of w
+    // after the tridiagonal phases the same region stages Q for the factor
+    // step; the sorted eigenpairs live past it
+    const int K16 = (K + 15) & ~15, I16 = (I + 15) & ~15;
+    const size_t tri = evd_tri_lds_doubles(K);
+    const size_t qst = FACTOR && staged ? static_cast<size_t>(I16) * K16 : 0;
+    double* Vs = shd + (tri > qst ? tri : qst);        // K x K, column r = r-th largest
+    double* lamS = Vs + static_cast<size_t>(K) * K;    // K, descending
     __shared__ double stats[2];                        // norm(T), pivmin
     const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
     for (int e = tid; e < kTriP * kTriP; e += kBlock) hv[e] = 0.0;
@@ -1362,6 +1260,46 @@ __global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ c
 #pragma unroll
             for (int i = 0; i < KB; ++i) z[i] *= inv;
         }
+        // convergence: residual of T z - lambda z and orthogonality of the
+        // vectors, both against norm(T) (about 1e-16 when the iteration
+        // succeeded; the back-transformation below is orthogonal)
+        {
+            double res = 0.0;
+#pragma unroll
+            for (int i = 0; i < KB; ++i) {
+                if (i < K) {
+                    double t = fma(dd[i] - lj, z[i], 0.0);
+                    if (i > 0) t = fma(ee[i - 1], z[i - 1], t);
+                    if (i + 1 < KB && i + 1 < K) t = fma(ee[i], z[i + 1], t);
+                    res = fmax(res, fabs(t));
+                }
+            }
+            if (lane < K) {
+#pragma unroll
+                for (int i = 0; i < KB; ++i) zs[lane * kTriP + i] = z[i];
+            }
+            double orth = 0.0;
+#pragma unroll 1
+            for (int m = 0; m < K; ++m) {
+                double dq[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int i = 0; i < KB; i += 2) {
+                    const double2 c2 = *reinterpret_cast<const double2*>(zs + m * kTriP + i);
+                    dq[i & 3] = fma(c2.x, z[i], dq[i & 3]);
+                    dq[(i + 1) & 3] = fma(c2.y, z[i + 1], dq[(i + 1) & 3]);
+                }
+                const double dot = (dq[0] + dq[1]) + (dq[2] + dq[3]);
+                orth = fmax(orth, fabs(dot - (m == lane ? 1.0 : 0.0)));
+            }
+            if (lane >= K) res = orth = 0.0;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                res = fmax(res, __shfl_xor(res, o, kWave));
+                orth = fmax(orth, __shfl_xor(orth, o, kWave));
+            }
+            const bool bad = !(res <= 1e-10 * tn) || !(orth <= 1e-10);
+            if (lane == 0 && flags && bad) atomicOr(flags, RHOSVD_FLAG_EVD_NOCONV);
+        }
         // back-transformation z <- H_0 ... H_{K-3} z (rows of hv are zero
         // at indices <= k and past K)
 #pragma unroll 1
@@ -1377,220 +1315,50 @@ __global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ c
         if (lane < K) {
             const int col = K - 1 - lane;
 #pragma unroll
-            for (int i = 0; i < KB; ++i)
-                if (i < K) v_out[static_cast<size_t>(col) * K + i] = z[i];
-            lam_out[col] = lj;
+            for (int i = 0; i < KB; ++i) {
+                if (i < K) {
+                    if (FACTOR)
+                        Vs[static_cast<size_t>(col) * K + i] = z[i];
+                    else
+                        v_out[static_cast<size_t>(col) * K + i] = z[i];
+                }
+            }
+            if (FACTOR)
+                lamS[col] = lj;
+            else
+                lam_out[col] = lj;
         }
-        if (tid == 0 && flags && report_iters) atomicOr(flags, static_cast<uint32_t>(kTriIters) << 16);
+    }
+    if constexpr (FACTOR) {
+        __syncthreads();
+        factor_step<T>(K, K16, I, I16, R, use_v, Vs, lamS, q, staged ? shd : qwork, u_out, m_out,
+                       sigma);
     }
 }
 
-// EVD of C (K x K, column-major, device) and, when q != nullptr, the factor
-// step: U = Q V[:, :R] (V = identity when use_v == 0), canonical signs,
-// M = V_R diag(s) (K x R), sigma = sqrt(max(lambda, 0))[:R].  Q is staged
-// into LDS (row-major, pitch K16 = 16 ceil(K / 16), zero-padded to I16 rows)
-// together with C, so its load overlaps nothing but C's; U is formed on the
-// f64 matrix cores in place of Q, one 16-row block per wave at a time.  The
-// sorted eigenpairs also go to v_out / lam_out when those are non-null.
-template <typename T, bool STAGED>
-__global__ __launch_bounds__(kBlock) void k_evd_factor(const double* __restrict__ cin, int K,
-                                                       double* v_out, double* lam_out,
-                                                       uint32_t* flags, const T* __restrict__ q,
-                                                       int I, int R, int use_v,
-                                                       T* __restrict__ u_out,
-                                                       T* __restrict__ m_out,
-                                                       double* __restrict__ sigma,
-                                                       double* __restrict__ qwork,
-                                                       const double* __restrict__ vpre,
-                                                       const double* __restrict__ lpre) {
-    extern __shared__ __align__(16) double shd[];
-    const int Ke = K + (K & 1);
-    const int K16 = (K + 15) & ~15, I16 = (I + 15) & ~15;
-    double* A = shd;
-    double* A2 = A + Ke * Ke;
-    double* V = A2 + Ke * Ke;
-    double* V2 = V + Ke * Ke;
-    double* rot = V2 + Ke * Ke;
-    // Q staged as I16 x K16 (row-major): in LDS when it fits, else in qwork
-    double* Qs = STAGED ? rot + kRotDoubles : qwork;
-    __shared__ double lam[RHOSVD_MAX_K], dg[RHOSVD_MAX_K];
-    __shared__ double sgn[RHOSVD_MAX_K];
-    const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
-    if (vpre) {
-        // eigenpairs already sorted (k_evd_tri): into the first buffer
-        for (int e = tid; e < K * K; e += kBlock) A[e] = vpre[e];
-        for (int e = tid; e < K; e += kBlock) lam[e] = lpre[e];
-    } else {
-        for (int e = tid; e < Ke * Ke; e += kBlock) {
-            const int r = e / Ke, c = e - r * Ke;
-            A[e] = (r < K && c < K) ? cin[c * K + r] : 0.0;
-            V[e] = (r == c) ? 1.0 : 0.0;
-        }
-    }
-    if (q) {
-        // Qs row-major (pitch K16): the padding first, then Q read in its own
-        // column-major order (coalesced), eight loads in flight per thread
-        for (int e = tid; e < I16 * K16; e += kBlock) {
-            const int i = e / K16, k = e - i * K16;
-            if (i >= I || k >= K) Qs[e] = 0.0;
-        }
-        const int n = I * K;
-        for (int e0 = tid; e0 < n; e0 += 8 * kBlock) {
-            T v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * kBlock;
-                v[u] = q[e < n ? e : n - 1];
-            }
-            int k = e0 / I, i = e0 - k * I;
-            const int dk = kBlock / I, di = kBlock - dk * I;
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                if (e0 + u * kBlock < n) Qs[i * K16 + k] = static_cast<double>(v[u]);
-                i += di;
-                k += dk;
-                if (i >= I) {
-                    i -= I;
-                    ++k;
-                }
-            }
-        }
-    }
-    __syncthreads();
-    double* Vs = shd;   // sorted eigenvectors (K x K, column-major)
-    if (!vpre) {
-        int sweeps = 0;
-        const bool conv = jacobi_lds(A, V, A2, V2, rot, Ke, &sweeps);
-        if (tid == 0 && !conv && flags) atomicOr(flags, RHOSVD_FLAG_EVD_NOCONV);
-        // the stand-alone EVD reports its sweep count in bits 16..23 of flags
-        if (tid == 0 && flags && !q) atomicOr(flags, static_cast<uint32_t>(sweeps & 0xff) << 16);
-        for (int i = tid; i < K; i += kBlock) dg[i] = A[i * Ke + i];
-        __syncthreads();
-        Vs = (A == shd) ? A2 : shd;   // a free buffer
-        for (int i = tid; i < K; i += kBlock) {
-            const double li = dg[i];
-            int rank = 0;
-            for (int j = 0; j < K; ++j) {
-                const double lj = dg[j];
-                rank += (lj > li) || (lj == li && j < i);
-            }
-            lam[rank] = li;
-            for (int k = 0; k < K; ++k) Vs[rank * K + k] = V[k * Ke + i];
-        }
-        __syncthreads();
-    }
-    if (v_out)
-        for (int e = tid; e < K * K; e += kBlock) v_out[e] = Vs[e];
-    if (lam_out)
-        for (int e = tid; e < K; e += kBlock) lam_out[e] = lam[e];
-    if (!q) return;
-    // U = Q V_R (FP64), 16 x 16 tiles, written over Q's rows (pitch K16 >= R)
-    {
-        // V_R's fragments stay in registers for all row blocks (K16 <= 64,
-        // R <= 64); each row block loads its Q fragments at once
-        const int m = lane & 15, kq = lane >> 4;
-        const int nib = I16 >> 4, nrb = (R + 15) >> 4, nst = K16 >> 2;
-        double vb[4][16];
-#pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-            for (int st = 0; st < 16; ++st) {
-                const int k = 4 * st + kq, rcol = 16 * rb + m;
-                double b = 0.0;
-                if (rb < nrb && st < nst && rcol < R && k < K)
-                    b = use_v ? Vs[rcol * K + k] : (k == rcol ? 1.0 : 0.0);
-                vb[rb][st] = b;
-            }
-        for (int ib = wave; ib < nib; ib += kBlock / kWave) {
-            const double* qa = Qs + (16 * ib + m) * K16 + kq;
-            double a[16];
-#pragma unroll
-            for (int st = 0; st < 16; ++st) a[st] = st < nst ? qa[4 * st] : 0.0;
-            f64x4 acc[4];
-#pragma unroll
-            for (int rb = 0; rb < 4; ++rb) {
-                acc[rb] = zero4<f64x4>();
-                if (rb < nrb) {
-#pragma unroll
-                    for (int st = 0; st < 16; ++st)
-                        if (st < nst) acc[rb] = Mma<double>::step(a[st], vb[rb][st], acc[rb]);
-                }
-            }
-#pragma unroll
-            for (int rb = 0; rb < 4; ++rb) {
-                if (rb < nrb) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = 16 * ib + Mma<double>::row(kq, r), col = 16 * rb + m;
-                        if (col < R) Qs[row * K16 + col] = acc[rb][r];
-                    }
-                }
-            }
-        }
-    }
-    __syncthreads();
-    for (int r = wave; r < R; r += kBlock / kWave) {
-        double best = -1.0;
-        int bi = 0x7fffffff;
-        for (int i = lane; i < I; i += kWave) {
-            const double a = fabs(Qs[i * K16 + r]);
-            if (a > best) {
-                best = a;
-                bi = i;
-            }
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const double ob = __shfl_xor(best, o, kWave);
-            const int oi = __shfl_xor(bi, o, kWave);
-            if (ob > best || (ob == best && oi < bi)) {
-                best = ob;
-                bi = oi;
-            }
-        }
-        if (lane == 0) sgn[r] = (Qs[bi * K16 + r] < 0.0) ? -1.0 : 1.0;
-    }
-    __syncthreads();
-    for (int e = tid; e < I * R; e += kBlock) {
-        const int r = e / I, i = e - r * I;
-        u_out[e] = static_cast<T>(sgn[r] * Qs[i * K16 + r]);
-    }
-    for (int e = tid; e < K * R; e += kBlock) {
-        const int r = e / K, k = e - r * K;
-        const double vv = use_v ? Vs[r * K + k] : (k == r ? 1.0 : 0.0);
-        m_out[e] = static_cast<T>(sgn[r] * vv);
-    }
-    if (sigma)
-        for (int r = tid; r < R; r += kBlock) sigma[r] = sqrt(fmax(lam[r], 0.0));
-}
-
-// LDS of k_evd_factor: A, A2, V and V2 (Ke x Ke each), the rotation slots
-// and Q staged as I16 x K16 when the factor step runs and it fits.
-size_t evd_lds_bytes(int K, int64_t I, bool staged) {
-    const int Ke = K + (K & 1);
+// Dynamic LDS of k_evd_tri: the tridiagonal phases' region (reused to stage
+// Q when `staged`), then the sorted eigenpairs (K x K + K doubles).
+static size_t evd_lds_bytes(int K, int64_t I, bool factor, bool staged) {
     const size_t K16 = (K + 15) & ~15, I16 = (I + 15) & ~static_cast<int64_t>(15);
-    size_t b = (4 * static_cast<size_t>(Ke) * Ke + kRotDoubles) * sizeof(double);
-    if (staged) b += I16 * K16 * sizeof(double);
-    return (b + 15) & ~static_cast<size_t>(15);
+    const size_t tri = evd_tri_lds_doubles(K);
+    const size_t qst = factor && staged ? I16 * K16 : 0;
+    const size_t d = (tri > qst ? tri : qst) + static_cast<size_t>(K) * K + K;
+    return (d * sizeof(double) + 15) & ~static_cast<size_t>(15);
 }
 
 size_t evd_qwork_doubles(int K, int64_t I) {
     return static_cast<size_t>((I + 15) & ~static_cast<int64_t>(15)) * ((K + 15) & ~15);
 }
 
-static bool evd_use_jacobi() {
-    const char* e = std::getenv("RHOSVD_EVD");
-    return e != nullptr && std::strcmp(e, "jacobi") == 0;
-}
-
+template <typename T, bool FACTOR>
 static hipError_t launch_evd_tri(const double* c, int K, double* v, double* lam, uint32_t* flags,
-                                 int report_iters, hipStream_t s) {
-    const size_t lds = evd_tri_lds_doubles(K) * sizeof(double);
-    if (lds + kStaticLdsMargin > kLdsLimit) return hipErrorInvalidValue;
-#define RH_TRI_CASE(KBV)                                                                        \
-    case KBV:                                                                                   \
-        hipLaunchKernelGGL(k_evd_tri<KBV>, dim3(1), dim3(kBlock), lds, s, c, K, v, lam, flags, \
-                           report_iters);                                                       \
+                                 const T* q, int I, int R, int use_v, T* u_out, T* m_out,
+                                 double* sigma, double* qwork, int staged, size_t lds,
+                                 hipStream_t s) {
+#define RH_TRI_CASE(KBV)                                                                     \
+    case KBV:                                                                                \
+        hipLaunchKernelGGL((k_evd_tri<KBV, T, FACTOR>), dim3(1), dim3(kBlock), lds, s, c, K, \
+                           v, lam, flags, q, I, R, use_v, u_out, m_out, sigma, qwork, staged); \
         break;
     switch ((K + 7) & ~7) {
         RH_TRI_CASE(8)
@@ -1608,48 +1376,38 @@ static hipError_t launch_evd_tri(const double* c, int K, double* v, double* lam,
     return hipGetLastError();
 }
 
-// u64: I16 x K16 doubles of device scratch, used when Q does not fit in LDS.
-// vwork / lwork: K x K and K doubles for the eigenpairs of the tridiagonal
-// method (Jacobi runs inside the factor kernel when they are null or when
-// RHOSVD_EVD=jacobi).
-hipError_t launch_evd_factor(bool dbl, const double* c, int K, double* v_out, double* lam_out,
-                             uint32_t* flags, const void* q, int64_t I, int R, int use_v,
-                             void* u_out, void* m_out, double* sigma, double* u64,
-                             double* vwork, double* lwork, hipStream_t s) {
-    if (K < 1 || K > 64) return hipErrorInvalidValue;
-    if (q && (I < 1 || I > (1 << 24) || R < 1 || R > K)) return hipErrorInvalidValue;
-    const bool staged = q != nullptr && evd_lds_bytes(K, I, true) + kStaticLdsMargin <= kLdsLimit;
-    if (q && !staged && !u64) return hipErrorInvalidValue;
-    const size_t lds = evd_lds_bytes(K, I, staged);
+// EVD of C followed in the same launch by the factor step (U, M, sigma).
+// u64: evd_qwork_doubles(K, I) doubles of device scratch, used when Q does
+// not fit in LDS beside the eigenpairs.
+hipError_t launch_evd_factor(bool dbl, const double* c, int K, uint32_t* flags, const void* q,
+                             int64_t I, int R, int use_v, void* u_out, void* m_out, double* sigma,
+                             double* u64, hipStream_t s) {
+    if (K < 1 || K > 64 || !q || I < 1 || I > (1 << 24) || R < 1 || R > K)
+        return hipErrorInvalidValue;
+    const bool staged = evd_lds_bytes(K, I, true, true) + kStaticLdsMargin <= kLdsLimit;
+    if (!staged && !u64) return hipErrorInvalidValue;
+    const size_t lds = evd_lds_bytes(K, I, true, staged);
     if (lds + kStaticLdsMargin > kLdsLimit) return hipErrorInvalidValue;
-    const double* vpre = nullptr;
-    const double* lpre = nullptr;
-    if (vwork && lwork && !evd_use_jacobi()) {
-        const hipError_t err = launch_evd_tri(c, K, vwork, lwork, flags, 0, s);
-        if (err != hipSuccess) return err;
-        vpre = vwork;
-        lpre = lwork;
-    }
     const int Ii = static_cast<int>(I);
-#define RH_EVD_LAUNCH(T, ST)                                                                      \
-    hipLaunchKernelGGL((k_evd_factor<T, ST>), dim3(1), dim3(kBlock), lds, s, c, K, v_out, lam_out, \
-                       flags, static_cast<const T*>(q), Ii, R, use_v, static_cast<T*>(u_out),     \
-                       static_cast<T*>(m_out), sigma, u64, vpre, lpre)
-    if (dbl) {
-        if (staged) RH_EVD_LAUNCH(double, true); else RH_EVD_LAUNCH(double, false);
-    } else {
-        if (staged) RH_EVD_LAUNCH(float, true); else RH_EVD_LAUNCH(float, false);
-    }
-#undef RH_EVD_LAUNCH
-    return hipGetLastError();
+    if (dbl)
+        return launch_evd_tri<double, true>(c, K, nullptr, nullptr, flags,
+                                            static_cast<const double*>(q), Ii, R, use_v,
+                                            static_cast<double*>(u_out),
+                                            static_cast<double*>(m_out), sigma, u64,
+                                            staged ? 1 : 0, lds, s);
+    return launch_evd_tri<float, true>(c, K, nullptr, nullptr, flags, static_cast<const float*>(q),
+                                       Ii, R, use_v, static_cast<float*>(u_out),
+                                       static_cast<float*>(m_out), sigma, u64, staged ? 1 : 0,
+                                       lds, s);
 }
 
 hipError_t launch_evd(const double* c, int K, double* v, double* lambda, uint32_t* flags,
                       hipStream_t s) {
     if (K < 1 || K > 64) return hipErrorInvalidValue;
-    if (!evd_use_jacobi()) return launch_evd_tri(c, K, v, lambda, flags, 1, s);
-    return launch_evd_factor(true, c, K, v, lambda, flags, nullptr, 0, 0, 0, nullptr, nullptr,
-                             nullptr, nullptr, nullptr, nullptr, s);
+    const size_t lds = evd_lds_bytes(K, 0, false, false);
+    if (lds + kStaticLdsMargin > kLdsLimit) return hipErrorInvalidValue;
+    return launch_evd_tri<double, false>(c, K, v, lambda, flags, nullptr, 0, 0, 0, nullptr,
+                                         nullptr, nullptr, nullptr, 0, lds, s);
 }
 
 }  // namespace rh

@@ -5,7 +5,6 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
-#include <cstdlib>
 #include <cstring>
 
 #include "kernels.hpp"
@@ -15,6 +14,7 @@ struct rhosvd_ctx {
     int device;
     int num_cu;
     size_t lds_per_block;
+    int kernels;    // RHOSVD_KERNELS_*: which streaming kernel families may run
 };
 
 namespace {
@@ -47,7 +47,7 @@ struct Carver {
     }
 };
 
-constexpr int kMaxSmallK = 64;    // CholeskyQR / Jacobi keep K x K in LDS
+constexpr int kMaxSmallK = 64;    // the QR and EVD kernels keep K x K in LDS / registers
 constexpr int kSumsqBlocks = 256;
 
 // One streaming pass, on the first kernel family that takes the shape:
@@ -67,22 +67,23 @@ struct Pass {
     int64_t I = 0;
 };
 
+// kernels == RHOSVD_KERNELS_TILED restricts the choice to the workgroup-tiled
+// family (every shape it takes gives the same result to rounding).
 bool plan_pass(int op, bool dbl, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu,
-               Pass* p) {
+               Pass* p, int kernels = RHOSVD_KERNELS_AUTO) {
     p->op = op;
     p->dbl = dbl;
     p->I = I;
     p->K = K;
-    if (!dbl && std::getenv("RHOSVD_FORCE_TILED") == nullptr &&
-        std::getenv("RHOSVD_NO_COL") == nullptr && rh::plan_col(op, ct, L, I, T, K, num_cu, &p->cg)) {
+    const bool any = kernels == RHOSVD_KERNELS_AUTO;
+    if (!dbl && any && rh::plan_col(op, ct, L, I, T, K, num_cu, &p->cg)) {
         p->kind = PASS_COL;
         p->grid = p->cg.grid;
         p->I_pad = p->cg.I_pad;
         p->K_pad = p->cg.K_pad;
         return true;
     }
-    if (!dbl && std::getenv("RHOSVD_FORCE_TILED") == nullptr &&
-        rh::plan_wave(op, ct, L, I, T, K, num_cu, &p->wg)) {
+    if (!dbl && any && rh::plan_wave(op, ct, L, I, T, K, num_cu, &p->wg)) {
         p->kind = PASS_WAVE;
         p->grid = p->wg.grid;
         p->I_pad = p->wg.IB * 16;
@@ -115,6 +116,7 @@ struct Problem {
     int order[RHOSVD_MAX_ORDER] = {};
     int prec = 0;
     int ct_sketch = 0, ct_power = 0, ct_ttm = 0, ct_trunc = 0;
+    int kernels = RHOSVD_KERNELS_AUTO;
 };
 
 struct Step {
@@ -204,14 +206,6 @@ int32_t validate(const rhosvd_tensor* x, const rhosvd_params* p, Problem* pr, bo
     } else {
         return RHOSVD_EINVAL;
     }
-    // experiment knobs: per-pass matrix-core precision (0 f32, 1 bf16, 2 split
-    // bf16 on both sides, 3 bf16 tensor with a split operand)
-    const char* names[4] = {"RHOSVD_CT_SKETCH", "RHOSVD_CT_POWER", "RHOSVD_CT_PROJECT", "RHOSVD_CT_TRUNC"};
-    int* dst[4] = {&pr->ct_sketch, &pr->ct_power, &pr->ct_ttm, &pr->ct_trunc};
-    for (int k = 0; k < 4; ++k) {
-        const char* v = pr->dbl ? nullptr : std::getenv(names[k]);
-        if (v && v[0] >= '0' && v[0] <= '3' && v[1] == 0) *dst[k] = v[0] - '0';
-    }
     return RHOSVD_OK;
 }
 
@@ -249,10 +243,10 @@ int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
             if (K > st.J) { K = st.J; st.capped = true; }
             st.K = static_cast<int>(K);
             if (st.K > kMaxSmallK) return RHOSVD_EUNSUPPORTED;
-            if (!plan_pass(rh::OP_SKETCH, pr.dbl, pr.ct_sketch, st.L, st.I, st.T, st.K, num_cu, &st.gs) ||
-                !plan_pass(rh::OP_POWER, pr.dbl, pr.ct_power, st.L, st.I, st.T, st.K, num_cu, &st.gp) ||
-                !plan_pass(rh::OP_TTM, pr.dbl, pr.ct_ttm, st.L, st.I, st.T, st.K, num_cu, &st.gt) ||
-                !plan_pass(rh::OP_TTM, pr.dbl, pr.ct_trunc, st.L, st.K, st.T, st.R, num_cu, &st.gtr))
+            if (!plan_pass(rh::OP_SKETCH, pr.dbl, pr.ct_sketch, st.L, st.I, st.T, st.K, num_cu, &st.gs, pr.kernels) ||
+                !plan_pass(rh::OP_POWER, pr.dbl, pr.ct_power, st.L, st.I, st.T, st.K, num_cu, &st.gp, pr.kernels) ||
+                !plan_pass(rh::OP_TTM, pr.dbl, pr.ct_ttm, st.L, st.I, st.T, st.K, num_cu, &st.gt, pr.kernels) ||
+                !plan_pass(rh::OP_TTM, pr.dbl, pr.ct_trunc, st.L, st.K, st.T, st.R, num_cu, &st.gtr, pr.kernels))
                 return RHOSVD_EUNSUPPORTED;
             track_stream(pl, st.gs, false);
             if (pr.q > 0) track_stream(pl, st.gp, false);
@@ -295,8 +289,8 @@ int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
         st.K = static_cast<int>(K);
         if (st.K > kMaxSmallK) return RHOSVD_EUNSUPPORTED;
         if (st.K > st.R) pl->any_k_gt_r = true;
-        if (!plan_pass(rh::OP_SKETCH, pr.dbl, pr.ct_sketch, st.L, st.I, st.T, st.K, num_cu, &st.gs) ||
-            !plan_pass(rh::OP_POWER, pr.dbl, pr.ct_power, st.L, st.I, st.T, st.K, num_cu, &st.gp))
+        if (!plan_pass(rh::OP_SKETCH, pr.dbl, pr.ct_sketch, st.L, st.I, st.T, st.K, num_cu, &st.gs, pr.kernels) ||
+            !plan_pass(rh::OP_POWER, pr.dbl, pr.ct_power, st.L, st.I, st.T, st.K, num_cu, &st.gp, pr.kernels))
             return RHOSVD_EUNSUPPORTED;
         track_stream(pl, st.gs, false);
         if (pr.q > 0) track_stream(pl, st.gp, false);
@@ -316,7 +310,7 @@ int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
     int64_t buf = 1;
     for (int n = 0; n < N; ++n) {
         const int64_t L = prod(d, 0, n), T = prod(d, n + 1, N);
-        if (!plan_pass(rh::OP_TTM, pr.dbl, pr.ct_ttm, L, d[n], T, pl->st[n].K, num_cu, &pl->gh[n]))
+        if (!plan_pass(rh::OP_TTM, pr.dbl, pr.ct_ttm, L, d[n], T, pl->st[n].K, num_cu, &pl->gh[n], pr.kernels))
             return RHOSVD_EUNSUPPORTED;
         track_stream(pl, pl->gh[n], false);
         d[n] = pl->st[n].K;
@@ -325,13 +319,13 @@ int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
     }
     for (int n = 0; n < N; ++n) {
         const int64_t L = prod(d, 0, n), T = prod(d, n + 1, N);
-        if (!plan_pass(rh::OP_TTM, pr.dbl, pr.ct_ttm, L, d[n], T, d[n], num_cu, &pl->gg[n]))
+        if (!plan_pass(rh::OP_TTM, pr.dbl, pr.ct_ttm, L, d[n], T, d[n], num_cu, &pl->gg[n], pr.kernels))
             return RHOSVD_EUNSUPPORTED;
         track_stream(pl, pl->gg[n], true);
     }
     for (int n = 0; n < N; ++n) {
         const int64_t L = prod(d, 0, n), T = prod(d, n + 1, N);
-        if (!plan_pass(rh::OP_TTM, pr.dbl, pr.ct_trunc, L, d[n], T, pl->st[n].R, num_cu, &pl->gc[n]))
+        if (!plan_pass(rh::OP_TTM, pr.dbl, pr.ct_trunc, L, d[n], T, pl->st[n].R, num_cu, &pl->gc[n], pr.kernels))
             return RHOSVD_EUNSUPPORTED;
         track_stream(pl, pl->gc[n], false);
         d[n] = pl->st[n].R;
@@ -351,8 +345,6 @@ struct Buffers {
     double* q64;   // 2 maxIK doubles (q64 + work)
     void* qT;
     double* C;
-    double* V;
-    double* lam;
     void* M;
     double* u64;
     void* B;
@@ -373,8 +365,6 @@ size_t carve(const Plan& pl, void* ws, Buffers* b) {
     b->q64 = cv.take<double>(2 * pl.maxIK * sizeof(double));
     b->qT = cv.take<void>(pl.maxIK * e);
     b->C = cv.take<double>(pl.maxKK * sizeof(double));
-    b->V = cv.take<double>(pl.maxKK * sizeof(double));
-    b->lam = cv.take<double>(RHOSVD_MAX_K * sizeof(double));
     b->M = cv.take<void>(pl.maxKR * e);
     b->u64 = cv.take<double>(pl.maxQW * sizeof(double));
     if (pl.pr.algo == RHOSVD_R_STHOSVD) {
@@ -452,9 +442,8 @@ int32_t run_r_sthosvd(const Plan& pl, const Buffers& b, const void* x, const rho
         rc = ttm(pl, st.gt, src, b.qT, b.B, b.part, s);
         if (rc != RHOSVD_OK) return rc;
         RH_HIP(rh::launch_gram_reduce(dbl, b.part, st.gt.grid, st.K, st.gt.K_pad, b.C, s));
-        RH_HIP(rh::launch_evd_factor(dbl, b.C, st.K, nullptr, nullptr, &b.rep->flags, b.qT, st.I,
-                                     st.R, 1, out->factors[st.n], b.M, &b.rep->sigma[st.n][0],
-                                     b.u64, b.V, b.lam, s));
+        RH_HIP(rh::launch_evd_factor(dbl, b.C, st.K, &b.rep->flags, b.qT, st.I, st.R, 1,
+                                     out->factors[st.n], b.M, &b.rep->sigma[st.n][0], b.u64, s));
         void* dst = (si == N - 1) ? out->core : ((si % 2 == 0) ? b.ping : b.pong);
         rc = ttm(pl, st.gtr, b.B, b.M, dst, nullptr, s, pl.rotated ? 1 : 0);
         if (rc != RHOSVD_OK) return rc;
@@ -501,10 +490,9 @@ int32_t run_rp_hosvd(const Plan& pl, const Buffers& b, const void* x, const rhos
         int32_t rc = ttm(pl, pl.gg[n], H, nullptr, scratch, b.part, s);
         if (rc != RHOSVD_OK) return rc;
         RH_HIP(rh::launch_gram_reduce(dbl, b.part, pl.gg[n].grid, st.K, pl.gg[n].K_pad, b.C, s));
-        RH_HIP(rh::launch_evd_factor(dbl, b.C, st.K, nullptr, nullptr, &b.rep->flags,
-                                     at(b.qstore, qoff[n], e), st.I, st.R, pl.any_k_gt_r ? 1 : 0,
-                                     out->factors[n], at(b.mstore, moff[n], e),
-                                     &b.rep->sigma[n][0], b.u64, b.V, b.lam, s));
+        RH_HIP(rh::launch_evd_factor(dbl, b.C, st.K, &b.rep->flags, at(b.qstore, qoff[n], e),
+                                     st.I, st.R, pl.any_k_gt_r ? 1 : 0, out->factors[n],
+                                     at(b.mstore, moff[n], e), &b.rep->sigma[n][0], b.u64, s));
     }
     // G = H x_n M_n^T
     src = H;
@@ -552,11 +540,22 @@ int32_t rhosvd_create(rhosvd_ctx** ctx, int32_t device) {
     c->device = device;
     c->num_cu = prop.multiProcessorCount;
     c->lds_per_block = prop.sharedMemPerBlock;
+    c->kernels = RHOSVD_KERNELS_AUTO;
     *ctx = c;
     return RHOSVD_OK;
 }
 
 void rhosvd_destroy(rhosvd_ctx* ctx) { delete ctx; }
+
+int32_t rhosvd_set_option(rhosvd_ctx* ctx, int32_t option, int64_t value) {
+    if (!ctx) return RHOSVD_EINVAL;
+    if (option == RHOSVD_OPTION_KERNELS) {
+        if (value != RHOSVD_KERNELS_AUTO && value != RHOSVD_KERNELS_TILED) return RHOSVD_EINVAL;
+        ctx->kernels = static_cast<int>(value);
+        return RHOSVD_OK;
+    }
+    return RHOSVD_EINVAL;
+}
 
 static int planning_cu(const rhosvd_ctx* ctx) { return ctx ? ctx->num_cu : 256; }
 
@@ -584,6 +583,7 @@ int32_t rhosvd_decompose(rhosvd_ctx* ctx, const rhosvd_tensor* x, const rhosvd_p
     Problem pr;
     int32_t rc = validate(x, p, &pr, true);
     if (rc != RHOSVD_OK) return rc;
+    pr.kernels = ctx->kernels;
     for (int n = 0; n < pr.N; ++n)
         if (!out->factors[n]) return RHOSVD_EINVAL;
     Plan* pl = new (std::nothrow) Plan;
@@ -710,7 +710,7 @@ int32_t rhosvd_sketch(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t p
     const bool dbl = dtype == RHOSVD_F64;
     int ct_s, ct_p, ct_t;
     step_cts(precision, &ct_s, &ct_p, &ct_t);
-    if (!plan_pass(rh::OP_SKETCH, dbl, ct_s, L, I, T, K, 256, &g)) return RHOSVD_EUNSUPPORTED;
+    if (!plan_pass(rh::OP_SKETCH, dbl, ct_s, L, I, T, K, 256, &g, ctx->kernels)) return RHOSVD_EUNSUPPORTED;
     void* part;
     double* ss;
     rc = step_ws(workspace, ws_bytes, I, K, &part, &ss);
@@ -739,7 +739,7 @@ int32_t rhosvd_power(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t pr
     const bool dbl = dtype == RHOSVD_F64;
     int ct_s, ct_p, ct_t;
     step_cts(precision, &ct_s, &ct_p, &ct_t);
-    if (!plan_pass(rh::OP_POWER, dbl, ct_p, L, I, T, K, 256, &g)) return RHOSVD_EUNSUPPORTED;
+    if (!plan_pass(rh::OP_POWER, dbl, ct_p, L, I, T, K, 256, &g, ctx->kernels)) return RHOSVD_EUNSUPPORTED;
     void* part;
     double* ss;
     rc = step_ws(workspace, ws_bytes, I, K, &part, &ss);
@@ -765,7 +765,7 @@ int32_t rhosvd_ttm(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t prec
     const bool dbl = dtype == RHOSVD_F64;
     int ct_s, ct_p, ct_t;
     step_cts(precision, &ct_s, &ct_p, &ct_t);
-    if (!plan_pass(rh::OP_TTM, dbl, ct_t, L, I, T, Kout, 256, &g)) return RHOSVD_EUNSUPPORTED;
+    if (!plan_pass(rh::OP_TTM, dbl, ct_t, L, I, T, Kout, 256, &g, ctx->kernels)) return RHOSVD_EUNSUPPORTED;
     void* part;
     double* ss;
     rc = step_ws(workspace, ws_bytes, I, Kout, &part, &ss);

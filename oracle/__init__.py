@@ -21,10 +21,12 @@ rsvd        Basic randomized SVD with oversampling and power iteration
 tucker      Deterministic THOSVD / STHOSVD (Section 4, Algorithm 4) and the
             randomized RP-HOSVD (Algorithm 6) and R-STHOSVD (Algorithm 8),
             plus the relative error of Section 8.
+variants    Fixed-precision (adaptive-rank) R-STHOSVD (Section 5.1), RP-HOOI
+            (Algorithm 7) and R-PET (Algorithm 9).
 
 Parity status: every function is pinned by the CPU tests in
 tests/test_oracle_*.py (published known-answer vectors, an independent
 library implementation, closed forms, invariants and brute-force SVD on
 tiny inputs); none is "parity unpinned".
 """
-from . import philox, tensor_ops, rsvd, tucker  # noqa: F401
+from . import philox, tensor_ops, rsvd, tucker, variants  # noqa: F401

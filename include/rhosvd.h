@@ -82,9 +82,19 @@ enum { RHOSVD_PREC_F64 = 0, RHOSVD_PREC_F32 = 1, RHOSVD_PREC_BF16 = 2 };
                                           |z_i^T z_j - delta_ij| > 1e-10 on the tridiagonal T */
 #define RHOSVD_FLAG_QR_HOUSEHOLDER 0x8u /* CholeskyQR broke down even with the shift (Y numerically
                                            rank deficient); that basis came from Householder QR */
+#define RHOSVD_FLAG_E_EXPLICIT   0x10u /* report.resid2 holds the explicit residual (see
+                                          RHOSVD_OPT_EXPLICIT_ERROR) */
 
 /* params.flags bits; a call with any other bit set is rejected (EINVAL) */
 #define RHOSVD_OPT_NONE 0u
+/* Compute the explicit residual ||X - G x_1 U_1 ... x_N U_N||_F^2 on the GPU
+ * (Section 8, eq. Relativeerror) in one more pass over X with FP64
+ * accumulation, into report.resid2 (flag RHOSVD_FLAG_E_EXPLICIT).  The pass
+ * also runs without this bit whenever the identity-based E of Section 5.1,
+ * sqrt(||X||^2 - ||G||^2) / ||X||, comes out below 1e-2: that form cancels
+ * catastrophically for small errors (FP64 resolves it only down to ~1e-8).
+ * The decision is taken on the device; the workspace always has room. */
+#define RHOSVD_OPT_EXPLICIT_ERROR 0x1u
 
 /* Context options (rhosvd_set_option). */
 #define RHOSVD_OPTION_KERNELS 1   /* which streaming-kernel families may run: */
@@ -109,7 +119,7 @@ typedef struct {
     uint64_t seed;            /* Omega key */
     const int32_t* mode_order;/* host permutation of 0..N-1 or NULL (ascending); R-STHOSVD only */
     int32_t precision;        /* RHOSVD_PREC_*; F64 requires F64 data */
-    uint32_t flags;           /* RHOSVD_OPT_*, must be 0 */
+    uint32_t flags;           /* RHOSVD_OPT_* bits */
 } rhosvd_params;
 
 /* Written by the device at the end of rhosvd_decompose (stream order). */
@@ -120,6 +130,8 @@ typedef struct {
     int32_t k_used[RHOSVD_MAX_ORDER];
     uint32_t flags;           /* RHOSVD_FLAG_* */
     double sigma[RHOSVD_MAX_ORDER][RHOSVD_MAX_K]; /* per mode, R_n leading singular values, descending */
+    double resid2;            /* ||X - G x_1 U_1 ... x_N U_N||_F^2 when flags has
+                                 RHOSVD_FLAG_E_EXPLICIT, else 0 */
 } rhosvd_report;
 
 typedef struct {
@@ -159,9 +171,11 @@ int32_t rhosvd_decompose(rhosvd_ctx* ctx, const rhosvd_tensor* x, const rhosvd_p
                          void* workspace, size_t ws_bytes, const rhosvd_output* out,
                          void* stream);
 
-/* Relative error E = sqrt(max(0, ||X||^2 - ||G||^2)) / ||X|| (Section 8,
- * eq. Relativeerror, via the orthogonal-projection identity of Section 5.1)
- * from a host copy of the report. */
+/* Relative error E = ||X - Xhat|| / ||X|| (Section 8, eq. Relativeerror)
+ * from a host copy of the report: sqrt(resid2 / ||X||^2) when the explicit
+ * residual was computed (RHOSVD_FLAG_E_EXPLICIT), else the orthogonal-
+ * projection identity of Section 5.1, sqrt(max(0, ||X||^2 - ||G||^2)) / ||X||.
+ * NaN when ||X|| = 0. */
 double rhosvd_report_rel_error(const rhosvd_report* r);
 
 /* ---- Step-level entry points (one hot-path step each; used by the per-step
@@ -182,6 +196,27 @@ int32_t rhosvd_sketch(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t p
                       int64_t L, int64_t I, int64_t T, int32_t K, uint64_t seed,
                       int32_t mode, int32_t tag, double* y, double* norm2,
                       void* workspace, size_t ws_bytes, void* stream);
+
+/* Sketch of every mode from one read of X (Algorithm 6 step 3; Section 5.1:
+ * no unfolding is formed): Y_n = X_(n) Omega_n for n = 0..N-1, Omega_n the
+ * matrix of (seed, mode n, tag) with K[n] columns and cyclic rows (see
+ * Omega above).  src: device, prod(dims) elements of dtype, first-index-
+ * fastest.  y: device doubles, sum_n dims[n] K[n]; Y_n starts at offset
+ * sum_{m<n} dims[m] K[m] and is dims[n] x K[n] column-major.  norm2
+ * (optional device double) receives ||X||^2.  Arithmetic in the tensor's
+ * dtype (FP32 data: FP32 products and accumulation per workgroup, FP64 sum
+ * over workgroups).  EUNSUPPORTED when sum_n dims[n] K[n] does not fit the
+ * workgroup's LDS (about 30000 FP32 or 15000 FP64 entries) or a K[n] >
+ * RHOSVD_MAX_SKETCH.  Workspace: rhosvd_sketch_all_workspace_size. */
+int32_t rhosvd_sketch_all(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t order,
+                          const int64_t* dims, const int32_t* K, uint64_t seed, int32_t tag,
+                          double* y, double* norm2, void* workspace, size_t ws_bytes,
+                          void* stream);
+
+/* Bytes of workspace rhosvd_sketch_all needs (0 if the problem is invalid or
+ * unsupported). */
+size_t rhosvd_sketch_all_workspace_size(int32_t order, const int64_t* dims, const int32_t* K,
+                                        int32_t dtype);
 
 /* One fused power step Y = S_(n) (S_(n)^T Q) (Algorithm 1 step 2, q > 0).
  * q_in: device, I x K column-major, dtype; y: device, I x K double. */

@@ -19,6 +19,8 @@ F32, F64 = 0, 1
 RP_HOSVD, R_STHOSVD = 0, 1
 PREC_F64, PREC_F32, PREC_BF16 = 0, 1, 2
 FLAG_K_CAPPED, FLAG_CQR_SHIFTED, FLAG_EVD_NOCONV, FLAG_QR_HOUSEHOLDER = 0x1, 0x2, 0x4, 0x8
+FLAG_E_EXPLICIT = 0x10
+OPT_EXPLICIT_ERROR = 0x1
 OPTION_KERNELS = 1
 KERNELS_AUTO, KERNELS_TILED = 0, 1
 
@@ -39,7 +41,8 @@ class Report(ctypes.Structure):
     _fields_ = [("norm_x2", ctypes.c_double), ("norm_core2", ctypes.c_double),
                 ("order", ctypes.c_int32), ("k_used", ctypes.c_int32 * MAX_ORDER),
                 ("flags", ctypes.c_uint32),
-                ("sigma", (ctypes.c_double * MAX_K) * MAX_ORDER)]
+                ("sigma", (ctypes.c_double * MAX_K) * MAX_ORDER),
+                ("resid2", ctypes.c_double)]
 
 
 class Output(ctypes.Structure):
@@ -68,6 +71,8 @@ _PROTOS = {
     "rhosvd_omega_fill": (_I32, [_P, _U64, _I32, _I32, _I64, _I32, _I32, _P, _P]),
     "rhosvd_sketch": (_I32, [_P, _P, _I32, _I32, _I64, _I64, _I64, _I32, _U64, _I32, _I32, _P, _P,
                              _P, _SZ, _P]),
+    "rhosvd_sketch_all": (_I32, [_P, _P, _I32, _I32, _P, _P, _U64, _I32, _P, _P, _P, _SZ, _P]),
+    "rhosvd_sketch_all_workspace_size": (_SZ, [_I32, _P, _P, _I32]),
     "rhosvd_power": (_I32, [_P, _P, _I32, _I32, _I64, _I64, _I64, _I32, _P, _P, _P, _SZ, _P]),
     "rhosvd_ttm": (_I32, [_P, _P, _I32, _I32, _I64, _I64, _I64, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
     "rhosvd_orthonormalize": (_I32, [_P, _P, _I64, _I32, _I32, _P, _P, _P, _P]),
@@ -93,10 +98,18 @@ def load(require_torch=True):
                 "librhosvd.so is not built; run `python -m paper_2001_07124_amd.build` "
                 "(the HIP library is required: there is no CPU fallback)")
         lib = ctypes.CDLL(LIB_PATH)
+        missing = []
         for name, (res, args) in _PROTOS.items():
-            fn = getattr(lib, name)
+            try:
+                fn = getattr(lib, name)
+            except AttributeError:
+                missing.append(name)     # a stale build: only calls of it fail
+                continue
             fn.restype = res
             fn.argtypes = args
+        if missing:
+            import warnings
+            warnings.warn(f"librhosvd.so lacks {missing}; rebuild it", RuntimeWarning)
         _lib = lib
         return lib
 

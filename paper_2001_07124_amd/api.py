@@ -134,7 +134,19 @@ class Decomposition:
 
     @property
     def rel_error(self):
+        """E of Section 8: the explicit residual when the library computed
+        it (see explicit_error), else the projection identity."""
         return float(L.load().rhosvd_report_rel_error(ctypes.byref(self.report())))
+
+    @property
+    def rel_error_identity(self):
+        r = self.report()
+        d = r.norm_x2 - r.norm_core2
+        return float(np.sqrt(max(d, 0.0) / r.norm_x2))
+
+    @property
+    def explicit(self):
+        return bool(self.report().flags & L.FLAG_E_EXPLICIT)
 
     @property
     def norm_x2(self):
@@ -164,7 +176,8 @@ class Decomposer:
     result() returns the output tensors and the report."""
 
     def __init__(self, dims, ranks, *, algo="r_sthosvd", p=10, q=1, seed=0,
-                 dtype=torch.float32, precision=None, mode_order=None, device=None):
+                 dtype=torch.float32, precision=None, mode_order=None, device=None,
+                 explicit_error=False):
         self.lib = L.load()
         self.device = torch.device(device) if device is not None else torch.device(
             "cuda", torch.cuda.current_device())
@@ -179,8 +192,9 @@ class Decomposer:
         self._order_c = None if mode_order is None else (ctypes.c_int32 * self.N)(*mode_order)
         self.tensor = L.Tensor(self.N, self._dims_c, _dtype_code(dtype), None)
         algo_code = {"r_sthosvd": L.R_STHOSVD, "rp_hosvd": L.RP_HOSVD}[algo]
+        flags = L.OPT_EXPLICIT_ERROR if explicit_error else 0
         self.params = L.Params(algo_code, self._ranks_c, int(p), int(q), int(seed),
-                               self._order_c, _prec_code(precision, dtype), 0)
+                               self._order_c, _prec_code(precision, dtype), flags)
         ws = ctypes.c_size_t(0)
         L.check(self.lib.rhosvd_workspace_size(ctypes.byref(self.tensor),
                                                 ctypes.byref(self.params), ctypes.byref(ws)),
@@ -211,11 +225,12 @@ class Decomposer:
 
 
 def decompose(x, ranks, *, algo="r_sthosvd", p=10, q=1, seed=0, precision=None,
-              mode_order=None, dims=None, stream=None):
+              mode_order=None, dims=None, stream=None, explicit_error=False):
     """One decomposition of x (device tensor, first-index-fastest)."""
     dims = _check_fortran(x, dims)
     d = Decomposer(dims, ranks, algo=algo, p=p, q=q, seed=seed, dtype=x.dtype,
-                   precision=precision, mode_order=mode_order, device=x.device)
+                   precision=precision, mode_order=mode_order, device=x.device,
+                   explicit_error=explicit_error)
     d.run(x, stream)
     return d.result()
 
@@ -264,6 +279,31 @@ def sketch(src, view, K, seed, mode, tag, want_norm=False, precision=None):
                               int(tag), _ptr(y), _ptr(nrm), _ptr(ws), nb, _stream(None, dev)),
             "rhosvd_sketch")
     return y, nrm
+
+
+def sketch_all(src, dims, K, seed, tag=1, want_norm=False):
+    """Y_n = X_(n) Omega_n for every mode n from one read of the flat device
+    tensor src (dims first-index-fastest).  Returns ([Y_n], norm2)."""
+    lib = L.load()
+    N = len(dims)
+    dev = src.device
+    dims_c = (ctypes.c_int64 * N)(*[int(d) for d in dims])
+    k_c = (ctypes.c_int32 * N)(*[int(k) for k in K])
+    nb = int(lib.rhosvd_sketch_all_workspace_size(N, dims_c, k_c, _dtype_code(src.dtype)))
+    if nb == 0:
+        raise L.RhosvdError(L.EUNSUPPORTED, "rhosvd_sketch_all_workspace_size")
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    total = sum(int(d) * int(k) for d, k in zip(dims, K))
+    y = torch.empty(total, dtype=torch.float64, device=dev)
+    nrm = torch.zeros(1, dtype=torch.float64, device=dev) if want_norm else None
+    L.check(lib.rhosvd_sketch_all(_context(dev.index or 0), _ptr(src), _dtype_code(src.dtype), N,
+                                  dims_c, k_c, int(seed), int(tag), _ptr(y), _ptr(nrm), _ptr(ws), nb,
+                                  _stream(None, dev)), "rhosvd_sketch_all")
+    out, off = [], 0
+    for d, k in zip(dims, K):
+        out.append(y[off: off + int(d) * int(k)].view(int(k), int(d)).t())
+        off += int(d) * int(k)
+    return out, nrm
 
 
 def power(src, view, q_mat, precision=None):

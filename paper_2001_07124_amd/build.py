@@ -25,6 +25,8 @@ SOURCES = {
     "kernels_wave.hip": [],
     "kernels_col.hip": [],
     "kernels_small.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "kernels_resid.hip": [],
+    "kernels_allmode.hip": [],
     "rhosvd_api.hip": [],
 }
 
@@ -42,9 +44,20 @@ def _common_flags():
             "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
 
 
-def _compile(hipcc, src, extra, verbose):
+def _newest_header():
+    paths = [os.path.join(HERE, "csrc", f) for f in os.listdir(os.path.join(HERE, "csrc"))
+             if f.endswith((".hpp", ".h"))]
+    paths += [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))]
+    return max(os.path.getmtime(p) for p in paths)
+
+
+def _compile(hipcc, src, extra, verbose, incremental=False):
     obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc, *_common_flags(), *extra, "-c", os.path.join(HERE, "csrc", src), "-o", obj]
+    srcp = os.path.join(HERE, "csrc", src)
+    if incremental and os.path.exists(obj):
+        if os.path.getmtime(obj) > max(os.path.getmtime(srcp), _newest_header()):
+            return obj, None
+    cmd = [hipcc, *_common_flags(), *extra, "-c", srcp, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -53,12 +66,15 @@ def _compile(hipcc, src, extra, verbose):
     return obj, None
 
 
-def build_library(verbose=False):
+def build_library(verbose=False, incremental=False):
+    """Compile every source (incremental=True skips objects newer than their
+    source and every header) and link librhosvd.so in-tree."""
     hipcc = hipcc_path()
     os.makedirs(OBJDIR, exist_ok=True)
     jobs = min(len(SOURCES), int(os.environ.get("MAX_JOBS", "8")) or 1)
     with ThreadPoolExecutor(max_workers=jobs) as pool:
-        results = list(pool.map(lambda kv: _compile(hipcc, kv[0], kv[1], verbose), SOURCES.items()))
+        results = list(pool.map(lambda kv: _compile(hipcc, kv[0], kv[1], verbose, incremental),
+                                SOURCES.items()))
     errors = [err for _, err in results if err]
     if errors:
         sys.stderr.write("\n".join(errors))
@@ -76,4 +92,4 @@ def build_library(verbose=False):
 
 
 if __name__ == "__main__":
-    print(build_library(verbose=True))
+    print(build_library(verbose=True, incremental="--incremental" in sys.argv))

@@ -28,9 +28,12 @@ constexpr size_t kStreamLdsCap = 80 * 1024;
 // I_pad rows.  The K-wide right operand (Omega tile or Z = S^T Q) sits in
 // sW[c][k] (pitch KW); Q / M sits in sQ[i][k].
 // ---------------------------------------------------------------------------
+// The body walks the tiles t_begin, t_begin + t_step, ... < g.ntiles and
+// writes its partials into slot `gidx` of a.part_y / a.part_g / a.part_ss.
 template <typename T, int OP>
-__global__ __launch_bounds__(kBlock) void k_stream(StreamGeom g, StreamArgs a, int want_ss,
-                                                   int want_gram) {
+__device__ __forceinline__ void stream_body(const StreamGeom& g, const StreamArgs& a, int want_ss,
+                                            int want_gram, int64_t t_begin, int64_t t_step,
+                                            size_t gidx) {
     using MM = Mma<T>;
     using acc_t = typename MM::acc_t;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -68,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(StreamGeom g, StreamArgs a, i
     const int np2 = CB * NB;
     const int npg = NB * NB;
 
-    for (int64_t tile = blockIdx.x; tile < g.ntiles; tile += gridDim.x) {
+    for (int64_t tile = t_begin; tile < g.ntiles; tile += t_step) {
         const int64_t j0 = tile * C;
         const int Cv = static_cast<int>(J - j0 < C ? J - j0 : C);
 
@@ -228,7 +231,6 @@ __global__ __launch_bounds__(kBlock) void k_stream(StreamGeom g, StreamArgs a, i
     }
 
     // ---- per-workgroup partials
-    const size_t gidx = blockIdx.x;
     if (OP == OP_SKETCH || OP == OP_POWER) {
         T* __restrict__ py = static_cast<T*>(a.part_y) + gidx * g.K_pad * g.I_pad;
 #pragma unroll
@@ -266,6 +268,25 @@ __global__ __launch_bounds__(kBlock) void k_stream(StreamGeom g, StreamArgs a, i
             a.part_ss[gidx] = s;
         }
     }
+}
+
+template <typename T, int OP>
+__global__ __launch_bounds__(kBlock) void k_stream(StreamGeom g, StreamArgs a, int want_ss,
+                                                   int want_gram) {
+    stream_body<T, OP>(g, a, want_ss, want_gram, blockIdx.x, gridDim.x, blockIdx.x);
+}
+
+// Many independent passes in one launch: workgroup (x, y) serves job y as
+// its workgroup x of jobs[y].units (the others return at once), with the
+// job's own geometry and buffers.
+template <typename T, int OP>
+__global__ __launch_bounds__(kBlock) void k_stream_batch(const StreamJob* __restrict__ jobs) {
+    const StreamJob& jb = jobs[blockIdx.y];
+    if (static_cast<int>(blockIdx.x) >= jb.units) return;
+    const StreamGeom g = jb.g;
+    const StreamArgs a = jb.a;
+    stream_body<T, OP>(g, a, a.part_ss != nullptr, a.part_g != nullptr, blockIdx.x, jb.units,
+                       blockIdx.x);
 }
 
 static int round16(int64_t v) { return static_cast<int>((v + 15) / 16 * 16); }
@@ -333,6 +354,27 @@ hipError_t launch_stream(int op, bool dbl, const StreamGeom& g, const StreamArgs
     if (op == OP_SKETCH) return launch_stream_t<float, OP_SKETCH>(g, a, s);
     if (op == OP_POWER) return launch_stream_t<float, OP_POWER>(g, a, s);
     return launch_stream_t<float, OP_TTM>(g, a, s);
+}
+
+template <typename T, int OP>
+static hipError_t launch_stream_batch_t(const StreamJob* jobs, int njobs, int max_units,
+                                        size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_stream_batch<T, OP>), dim3(max_units, njobs), dim3(kBlock), lds, s,
+                       jobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_batch(int op, bool dbl, const StreamJob* jobs, int njobs, int max_units,
+                               size_t lds, hipStream_t s) {
+    if (njobs < 1 || max_units < 1 || lds + kStaticLdsMargin > kLdsLimit) return hipErrorInvalidValue;
+    if (dbl) {
+        if (op == OP_SKETCH) return launch_stream_batch_t<double, OP_SKETCH>(jobs, njobs, max_units, lds, s);
+        if (op == OP_POWER) return launch_stream_batch_t<double, OP_POWER>(jobs, njobs, max_units, lds, s);
+        return launch_stream_batch_t<double, OP_TTM>(jobs, njobs, max_units, lds, s);
+    }
+    if (op == OP_SKETCH) return launch_stream_batch_t<float, OP_SKETCH>(jobs, njobs, max_units, lds, s);
+    if (op == OP_POWER) return launch_stream_batch_t<float, OP_POWER>(jobs, njobs, max_units, lds, s);
+    return launch_stream_batch_t<float, OP_TTM>(jobs, njobs, max_units, lds, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -625,6 +667,7 @@ __global__ void k_report_init(rhosvd_report* rep, ReportInit ri, uint32_t init_f
     if (tid == 0) {
         rep->norm_x2 = 0.0;
         rep->norm_core2 = 0.0;
+        rep->resid2 = 0.0;
         rep->order = ri.order;
         for (int n = 0; n < RHOSVD_MAX_ORDER; ++n) rep->k_used[n] = ri.k_used[n];
         rep->flags = init_flags;

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "rhosvd.h"
+
 namespace rh {
 
 enum StreamOp { OP_SKETCH = 0, OP_POWER = 1, OP_TTM = 2 };
@@ -42,6 +44,19 @@ bool plan_stream(int op, int elem, int64_t L, int64_t I, int64_t T, int K, int n
 
 hipError_t launch_stream(int op, bool dbl, const StreamGeom& g, const StreamArgs& a,
                          hipStream_t s);
+
+// One pass of many independent problems in one launch (device table of
+// jobs): job y runs on `units` workgroups (grid x = the largest units),
+// partial slots 0 .. units - 1 of its own buffers.  lds: the largest of the
+// jobs' g.lds_bytes.
+struct StreamJob {
+    StreamGeom g;
+    StreamArgs a;
+    int units;
+    int pad_;
+};
+hipError_t launch_stream_batch(int op, bool dbl, const StreamJob* jobs, int njobs, int max_units,
+                               size_t lds, hipStream_t s);
 
 // Matrix-core input precision of the wave-private FP32 kernels.
 enum CompType { CT_F32 = 0, CT_BF16 = 1, CT_BF16X3 = 2, CT_BF16X2 = 3 };
@@ -118,6 +133,47 @@ hipError_t launch_omega_fill(bool dbl, uint64_t seed, int mode, int tag, int64_t
 
 hipError_t launch_gram_reduce(bool dbl, const void* part, int G, int K, int K_pad, double* c,
                               hipStream_t s);
+
+// Single-pass sketch of every mode (kernels_allmode.hip): Y_n = X_(n) Omega_n
+// (tag `tag`, cyclic rows) for all n from one read of X, plus per-workgroup
+// sums of squares.  part: grid x S partials in X's dtype; the reduce writes
+// all Y_n into y (S doubles; Y_n at yoff[n], I_n x K_n column-major).
+struct AllModeArgs {
+    const void* x;
+    void* part;
+    double* part_ss;          // grid doubles, or null
+    uint64_t seed;
+    uint32_t tag;
+    int N, KMAX, grid;
+    int64_t dims[RHOSVD_MAX_ORDER];
+    int K[RHOSVD_MAX_ORDER];
+    int b[RHOSVD_MAX_ORDER];          // tile extents
+    int64_t bs[RHOSVD_MAX_ORDER];     // tile strides (first fastest)
+    int64_t ntile[RHOSVD_MAX_ORDER];  // tiles along each mode
+    int64_t xs[RHOSVD_MAX_ORDER];     // strides of X
+    int64_t yoff[RHOSVD_MAX_ORDER];   // offset of Y_n in a partial / in y
+    int64_t J[RHOSVD_MAX_ORDER], T[RHOSVD_MAX_ORDER];
+    int64_t TB, S, ntiles;
+    size_t lds_bytes;
+};
+bool plan_allmode(int N, const int64_t* dims, const int* K, int num_cu, int elem, AllModeArgs* a);
+hipError_t launch_allmode(bool dbl, const AllModeArgs& a, hipStream_t s);
+hipError_t launch_allmode_reduce(bool dbl, const AllModeArgs& a, double* y, hipStream_t s);
+
+// Explicit residual ||X - G x_1 U_1 ... x_N U_N||^2 (kernels_resid.hip).
+// gate: one device int written by launch_resid_gate (1 when requested or when
+// the report's identity-based E is below 1e-2); every other launch returns
+// at once when it is 0.  launch_expand: out = in x_n U for the view (L, R, T)
+// of `in` and U (I x R, column-major), out viewed (L, I, T).  launch_resid:
+// X viewed (M, IN), W (M x R), U_N (IN x R) column-major; part holds
+// kResidGrid doubles; the sum lands in report->resid2 with
+// RHOSVD_FLAG_E_EXPLICIT set.
+constexpr int kResidGrid = 2048;
+hipError_t launch_resid_gate(void* rep, int requested, int* gate, hipStream_t s);
+hipError_t launch_expand(bool dbl, const int* gate, const void* in, const void* u, int64_t L,
+                         int I, int R, int64_t T, void* out, hipStream_t s);
+hipError_t launch_resid(bool dbl, const int* gate, const void* x, const void* w, const void* un,
+                        int64_t M, int IN, int R, double* part, void* rep, hipStream_t s);
 
 struct ReportInit {
     int32_t order;

@@ -1000,13 +1000,13 @@ __global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ c
     double* lam = ee + kTriP;
     double* bc = lam + kTriP;                          // broadcast of v
     double* bw = bc + kTriP;                           // broadcast of w
-    // after the tridiagonal phases the same region stages Q for the factor
-    // step; the sorted eigenpairs live past it
+    // once the tridiagonal phases are done (wave 0 last reads hv in the
+    // back-transformation, then writes the eigenpairs), the start of the
+    // region holds the sorted eigenpairs and Q is staged after them
     const int K16 = (K + 15) & ~15, I16 = (I + 15) & ~15;
-    const size_t tri = evd_tri_lds_doubles(K);
-    const size_t qst = FACTOR && staged ? static_cast<size_t>(I16) * K16 : 0;
-    double* Vs = shd + (tri > qst ? tri : qst);        // K x K, column r = r-th largest
+    double* Vs = shd;                                  // K x K, column r = r-th largest
     double* lamS = Vs + static_cast<size_t>(K) * K;    // K, descending
+    double* Qst = lamS + K + (K & 1);                  // I16 x K16 when staged
     __shared__ double stats[2];                        // norm(T), pivmin
     const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
     for (int e = tid; e < kTriP * kTriP; e += kBlock) hv[e] = 0.0;
@@ -1331,18 +1331,19 @@ __global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ c
     }
     if constexpr (FACTOR) {
         __syncthreads();
-        factor_step<T>(K, K16, I, I16, R, use_v, Vs, lamS, q, staged ? shd : qwork, u_out, m_out,
+        factor_step<T>(K, K16, I, I16, R, use_v, Vs, lamS, q, staged ? Qst : qwork, u_out, m_out,
                        sigma);
     }
 }
 
-// Dynamic LDS of k_evd_tri: the tridiagonal phases' region (reused to stage
-// Q when `staged`), then the sorted eigenpairs (K x K + K doubles).
+// Dynamic LDS of k_evd_tri: the tridiagonal phases' region, reused by the
+// factor step for the sorted eigenpairs (K x K + K doubles) and, when
+// `staged`, Q after them.
 static size_t evd_lds_bytes(int K, int64_t I, bool factor, bool staged) {
     const size_t K16 = (K + 15) & ~15, I16 = (I + 15) & ~static_cast<int64_t>(15);
     const size_t tri = evd_tri_lds_doubles(K);
-    const size_t qst = factor && staged ? I16 * K16 : 0;
-    const size_t d = (tri > qst ? tri : qst) + static_cast<size_t>(K) * K + K;
+    const size_t fac = factor ? static_cast<size_t>(K) * K + K + (K & 1) + (staged ? I16 * K16 : 0) : 0;
+    const size_t d = tri > fac ? tri : fac;
     return (d * sizeof(double) + 15) & ~static_cast<size_t>(15);
 }
 

@@ -17,6 +17,7 @@ struct rhosvd_ctx {
     int kernels;    // RHOSVD_KERNELS_*: which streaming kernel families may run
 };
 
+
 namespace {
 
 thread_local int32_t g_last_hip = 0;
@@ -49,6 +50,10 @@ struct Carver {
 
 constexpr int kMaxSmallK = 64;    // the QR and EVD kernels keep K x K in LDS / registers
 constexpr int kSumsqBlocks = 256;
+// The single-pass sketch of all modes regenerates Omega rows per tile: it is
+// used while that costs at most this many normals per element of X (beyond
+// it the per-mode passes, which generate each row once, are faster).
+constexpr double kAllModeNormalsPerElement = 4.0;
 
 // One streaming pass, on the first kernel family that takes the shape:
 //   COL    contiguous unfolding (L = 1), bf16 matrix cores (kernels_col.hip)
@@ -117,6 +122,7 @@ struct Problem {
     int prec = 0;
     int ct_sketch = 0, ct_power = 0, ct_ttm = 0, ct_trunc = 0;
     int kernels = RHOSVD_KERNELS_AUTO;
+    bool explicit_error = false;
 };
 
 struct Step {
@@ -135,6 +141,10 @@ struct Plan {
     Pass gg[RHOSVD_MAX_ORDER];   // Gram of H_(n) (identity TTM)
     Pass gc[RHOSVD_MAX_ORDER];   // H .. x_n M_n^T
     bool any_k_gt_r = false;
+    // RP-HOSVD: every sketch from one read of X when the single-pass kernel
+    // takes the shape and its Omega work stays small (see plan_allmode_use)
+    bool use_allmode = false;
+    rh::AllModeArgs am{};
     // R-STHOSVD in the natural mode order keeps the current tensor with its
     // next mode first: (I_n, ..., I_N, R_1, ..., R_{n-1}).  Every unfolding is
     // then contiguous (L = 1), its columns are in the cyclic order that
@@ -146,7 +156,7 @@ struct Plan {
     int max_grid = 1;
     int64_t maxIK = 1, maxKK = 1, maxKR = 1, maxIR = 1, maxB = 1, maxQW = 1;
     int64_t ping = 1, pong = 1;
-    int64_t qstore = 0, mstore = 0;
+    int64_t qstore = 0, mstore = 0, ystore = 0;
 };
 
 int64_t prod(const int64_t* d, int a, int b) {
@@ -163,7 +173,8 @@ int32_t validate(const rhosvd_tensor* x, const rhosvd_params* p, Problem* pr, bo
     if (p->algo != RHOSVD_RP_HOSVD && p->algo != RHOSVD_R_STHOSVD) return RHOSVD_EINVAL;
     if (!p->ranks || p->oversample < 0 || p->power_iters < 0 || p->power_iters > 8)
         return RHOSVD_EINVAL;
-    if (p->flags != 0) return RHOSVD_EINVAL;
+    if ((p->flags & ~static_cast<uint32_t>(RHOSVD_OPT_EXPLICIT_ERROR)) != 0) return RHOSVD_EINVAL;
+    pr->explicit_error = (p->flags & RHOSVD_OPT_EXPLICIT_ERROR) != 0;
     pr->N = x->order;
     pr->dbl = x->dtype == RHOSVD_F64;
     pr->elem = pr->dbl ? sizeof(double) : sizeof(float);
@@ -215,6 +226,21 @@ void track_stream(Plan* pl, const Pass& g, bool gram) {
     if (y > pl->part_bytes) pl->part_bytes = y;
     if (gg > pl->part_bytes) pl->part_bytes = gg;
     if (g.grid > pl->max_grid) pl->max_grid = g.grid;
+}
+
+// The explicit residual reuses the two intermediate buffers (free once the
+// core is written) for W_k = G x_1 U_1 ... x_k U_k, k = 1 .. N-1, odd k in
+// ping and even k in pong.
+void size_resid(Plan* pl) {
+    const Problem& pr = pl->pr;
+    int64_t d[RHOSVD_MAX_ORDER];
+    for (int n = 0; n < pr.N; ++n) d[n] = pr.ranks[n];
+    for (int n = 0; n + 1 < pr.N; ++n) {
+        d[n] = pr.dims[n];
+        const int64_t sz = prod(d, 0, pr.N);
+        if (n % 2 == 0) { if (sz > pl->ping) pl->ping = sz; }
+        else { if (sz > pl->pong) pl->pong = sz; }
+    }
 }
 
 int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
@@ -270,6 +296,7 @@ int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
             }
         }
         pl->core_elems = prod(d, 0, N);
+        size_resid(pl);
         return RHOSVD_OK;
     }
     // RP-HOSVD: every sketch reads X
@@ -306,6 +333,23 @@ int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
         pl->qstore += IK;
         pl->mstore += static_cast<int64_t>(st.K) * st.R;
     }
+    {
+        int Ks[RHOSVD_MAX_ORDER];
+        for (int n = 0; n < N; ++n) Ks[n] = pl->st[n].K;
+        if (pr.kernels == RHOSVD_KERNELS_AUTO &&
+            rh::plan_allmode(N, pr.dims, Ks, num_cu, elem, &pl->am)) {
+            // Omega normals generated per element of X: sum_n K_n / b_n
+            double per_elem = 0.0;
+            for (int n = 0; n < N; ++n) per_elem += static_cast<double>(Ks[n]) / pl->am.b[n];
+            if (per_elem <= kAllModeNormalsPerElement) {
+                pl->use_allmode = true;
+                const size_t pb = static_cast<size_t>(pl->am.grid) * pl->am.S * pr.elem;
+                if (pb > pl->part_bytes) pl->part_bytes = pb;
+                if (pl->am.grid > pl->max_grid) pl->max_grid = pl->am.grid;
+                pl->ystore = pl->am.S;
+            }
+        }
+    }
     // core chain H = X x_1 Q_1^T ... x_N Q_N^T, then G = H x_n M_n^T
     int64_t buf = 1;
     for (int n = 0; n < N; ++n) {
@@ -334,6 +378,7 @@ int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
     }
     pl->ping = pl->pong = buf;
     pl->core_elems = prod(d, 0, N);
+    size_resid(pl);
     return RHOSVD_OK;
 }
 
@@ -352,6 +397,9 @@ struct Buffers {
     void* pong;
     void* qstore;
     void* mstore;
+    double* ystore;
+    int* gate;
+    double* part_resid;
 };
 
 size_t carve(const Plan& pl, void* ws, Buffers* b) {
@@ -371,13 +419,17 @@ size_t carve(const Plan& pl, void* ws, Buffers* b) {
         b->B = cv.take<void>(pl.maxB * e);
         b->qstore = nullptr;
         b->mstore = nullptr;
+        b->ystore = nullptr;
     } else {
         b->B = nullptr;
         b->qstore = cv.take<void>(pl.qstore * e);
+        b->ystore = pl.ystore ? cv.take<double>(pl.ystore * sizeof(double)) : nullptr;
         b->mstore = cv.take<void>(pl.mstore * e);
     }
     b->ping = cv.take<void>(pl.ping * e);
     b->pong = cv.take<void>(pl.pong * e);
+    b->gate = cv.take<int>(sizeof(int));
+    b->part_resid = cv.take<double>(rh::kResidGrid * sizeof(double));
     return cv.off + 256;
 }
 
@@ -385,7 +437,25 @@ void* at(void* base, int64_t elems, size_t elem) {
     return static_cast<unsigned char*>(base) + static_cast<size_t>(elems) * elem;
 }
 
-// Y = S_(n) Omega, or one fused power step when mat != nullptr; then Q.
+// q fused power steps Y = S_(n) (S_(n)^T Q), each followed by the QR
+// (Algorithm 1 step 2 with the stabilising QR between applications).
+int32_t power_steps(const Plan& pl, const Buffers& b, const void* src, const Pass& gp, void* q_out,
+                    hipStream_t s) {
+    const bool dbl = pl.pr.dbl;
+    for (int it = 0; it < pl.pr.q; ++it) {
+        rh::StreamArgs pa{};
+        pa.src = src;
+        pa.mat = q_out;
+        pa.part_y = b.part;
+        RH_HIP(launch_pass(gp, pa, s));
+        RH_HIP(rh::launch_reduce_y(dbl, b.part, gp.grid, static_cast<int>(gp.I), gp.K, gp.I_pad,
+                                   gp.K_pad, b.y, s));
+        RH_HIP(rh::launch_cqr(b.y, gp.I, gp.K, dbl, q_out, b.q64, &b.rep->flags, s));
+    }
+    return RHOSVD_OK;
+}
+
+// Y = S_(n) Omega, then Q and the power steps.
 int32_t sketch_and_orthonormalize(const Plan& pl, const Buffers& b, const void* src,
                                   const Pass& gs, const Pass& gp, int mode,
                                   uint32_t tag, bool want_norm, void* q_out, hipStream_t s) {
@@ -402,17 +472,7 @@ int32_t sketch_and_orthonormalize(const Plan& pl, const Buffers& b, const void* 
                                gs.K_pad, b.y, s));
     if (want_norm) RH_HIP(rh::launch_reduce_ss(b.part_ss, gs.grid, &b.rep->norm_x2, s));
     RH_HIP(rh::launch_cqr(b.y, gs.I, gs.K, dbl, q_out, b.q64, &b.rep->flags, s));
-    for (int it = 0; it < pl.pr.q; ++it) {
-        rh::StreamArgs pa{};
-        pa.src = src;
-        pa.mat = q_out;
-        pa.part_y = b.part;
-        RH_HIP(launch_pass(gp, pa, s));
-        RH_HIP(rh::launch_reduce_y(dbl, b.part, gp.grid, static_cast<int>(gp.I), gp.K, gp.I_pad,
-                                   gp.K_pad, b.y, s));
-        RH_HIP(rh::launch_cqr(b.y, gp.I, gp.K, dbl, q_out, b.q64, &b.rep->flags, s));
-    }
-    return RHOSVD_OK;
+    return power_steps(pl, b, src, gp, q_out, s);
 }
 
 int32_t ttm(const Plan& pl, const Pass& g, const void* src, const void* mat, void* out,
@@ -466,11 +526,31 @@ int32_t run_rp_hosvd(const Plan& pl, const Buffers& b, const void* x, const rhos
         qo += pl.st[n].I * pl.st[n].K;
         mo += static_cast<int64_t>(pl.st[n].K) * pl.st[n].R;
     }
-    for (int n = 0; n < N; ++n) {
-        const Step& st = pl.st[n];
-        const int32_t rc = sketch_and_orthonormalize(pl, b, x, st.gs, st.gp, n, 1u, n == 0,
-                                                     at(b.qstore, qoff[n], e), s);
-        if (rc != RHOSVD_OK) return rc;
+    if (pl.use_allmode) {
+        // every Y_n from one read of X, then per mode the QR and power steps
+        rh::AllModeArgs am = pl.am;
+        am.x = x;
+        am.part = b.part;
+        am.part_ss = b.part_ss;
+        am.seed = pl.pr.seed;
+        am.tag = 1u;
+        RH_HIP(rh::launch_allmode(dbl, am, s));
+        RH_HIP(rh::launch_allmode_reduce(dbl, am, b.ystore, s));
+        RH_HIP(rh::launch_reduce_ss(b.part_ss, am.grid, &b.rep->norm_x2, s));
+        for (int n = 0; n < N; ++n) {
+            const Step& st = pl.st[n];
+            void* qn = at(b.qstore, qoff[n], e);
+            RH_HIP(rh::launch_cqr(b.ystore + am.yoff[n], st.I, st.K, dbl, qn, b.q64, &b.rep->flags, s));
+            const int32_t rc = power_steps(pl, b, x, st.gp, qn, s);
+            if (rc != RHOSVD_OK) return rc;
+        }
+    } else {
+        for (int n = 0; n < N; ++n) {
+            const Step& st = pl.st[n];
+            const int32_t rc = sketch_and_orthonormalize(pl, b, x, st.gs, st.gp, n, 1u, n == 0,
+                                                         at(b.qstore, qoff[n], e), s);
+            if (rc != RHOSVD_OK) return rc;
+        }
     }
     // H = X x_1 Q_1^T ... x_N Q_N^T
     const void* src = x;
@@ -506,6 +586,86 @@ int32_t run_rp_hosvd(const Plan& pl, const Buffers& b, const void* x, const rhos
         scratch = was;
     }
     return RHOSVD_OK;
+}
+
+// Explicit residual (Section 8, eq. Relativeerror) on the device: the gate,
+// then W = G x_1 U_1 ... x_{N-1} U_{N-1} by expanding mode products, then one
+// pass over X against W and U_N.  Every launch is skipped on the device
+// unless the gate opened.
+int32_t run_residual(const Plan& pl, const Buffers& b, const void* x, const rhosvd_output* out,
+                     hipStream_t s) {
+    const Problem& pr = pl.pr;
+    const int N = pr.N;
+    RH_HIP(rh::launch_resid_gate(b.rep, pr.explicit_error ? 1 : 0, b.gate, s));
+    int64_t d[RHOSVD_MAX_ORDER];
+    for (int n = 0; n < N; ++n) d[n] = pr.ranks[n];
+    const void* src = out->core;
+    void* bufs[2] = {b.ping, b.pong};
+    for (int n = 0; n + 1 < N; ++n) {
+        const int64_t L = prod(d, 0, n), T = prod(d, n + 1, N);
+        void* dst = bufs[n % 2];
+        RH_HIP(rh::launch_expand(pr.dbl, b.gate, src, out->factors[n], L,
+                                 static_cast<int>(pr.dims[n]), pr.ranks[n], T, dst, s));
+        d[n] = pr.dims[n];
+        src = dst;
+    }
+    RH_HIP(rh::launch_resid(pr.dbl, b.gate, x, src, out->factors[N - 1], prod(pr.dims, 0, N - 1),
+                            static_cast<int>(pr.dims[N - 1]), pr.ranks[N - 1], b.part_resid, b.rep,
+                            s));
+    return RHOSVD_OK;
+}
+
+int planning_cu(const rhosvd_ctx* ctx) { return ctx ? ctx->num_cu : 256; }
+
+// The whole decomposition on a given workspace; `pl` is the caller's plan
+// storage.  `too_small` is returned when the workspace cannot hold the plan.
+int32_t decompose_on(rhosvd_ctx* ctx, const rhosvd_tensor* x, const rhosvd_params* p,
+                            void* workspace, size_t ws_bytes, int32_t too_small,
+                            const rhosvd_output* out, void* stream, Plan* pl) {
+    if (!ctx || !out || !out->core || !out->factors || !workspace) return RHOSVD_EINVAL;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return RHOSVD_EINVAL;
+    Problem pr;
+    int32_t rc = validate(x, p, &pr, true);
+    if (rc != RHOSVD_OK) return rc;
+    pr.kernels = ctx->kernels;
+    for (int n = 0; n < pr.N; ++n)
+        if (!out->factors[n]) return RHOSVD_EINVAL;
+    // the grid is planned for a 256-CU part so that the workspace size does
+    // not depend on the device the context was created on
+    rc = build_plan(pr, planning_cu(nullptr), pl);
+    if (rc != RHOSVD_OK) return rc;
+    Buffers b;
+    const size_t need = carve(*pl, nullptr, &b);
+    if (ws_bytes < need) return too_small;
+    carve(*pl, workspace, &b);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = -1;
+    RH_HIP(hipGetDevice(&dev));
+    if (dev != ctx->device) RH_HIP(hipSetDevice(ctx->device));
+    rh::ReportInit ri{};
+    ri.order = pr.N;
+    for (int si = 0; si < pr.N; ++si) {
+        const Step& st = pl->st[si];
+        ri.k_used[st.n] = st.capped ? -st.K : st.K;
+    }
+    rc = RHOSVD_OK;
+    hipError_t he = rh::launch_report_init(b.rep, ri, s);
+    if (he != hipSuccess) rc = hip_fail(he);
+    if (rc == RHOSVD_OK)
+        rc = (pr.algo == RHOSVD_R_STHOSVD) ? run_r_sthosvd(*pl, b, x->data, out, s)
+                                            : run_rp_hosvd(*pl, b, x->data, out, s);
+    if (rc == RHOSVD_OK) {
+        he = rh::launch_sumsq(pr.dbl, out->core, pl->core_elems, b.part_ss, kSumsqBlocks, s);
+        if (he == hipSuccess) he = rh::launch_reduce_ss(b.part_ss, kSumsqBlocks, &b.rep->norm_core2, s);
+        if (he != hipSuccess) rc = hip_fail(he);
+    }
+    if (rc == RHOSVD_OK) rc = run_residual(*pl, b, x->data, out, s);
+    if (rc == RHOSVD_OK && out->report) {
+        he = rh::launch_copy_bytes(b.rep, out->report, sizeof(rhosvd_report), s);
+        if (he != hipSuccess) rc = hip_fail(he);
+    }
+    if (dev != ctx->device) (void)hipSetDevice(dev);
+    return rc;
 }
 
 }  // namespace
@@ -557,7 +717,6 @@ int32_t rhosvd_set_option(rhosvd_ctx* ctx, int32_t option, int64_t value) {
     return RHOSVD_EINVAL;
 }
 
-static int planning_cu(const rhosvd_ctx* ctx) { return ctx ? ctx->num_cu : 256; }
 
 int32_t rhosvd_workspace_size(const rhosvd_tensor* x, const rhosvd_params* p, size_t* bytes) {
     if (!bytes) return RHOSVD_EINVAL;
@@ -578,70 +737,16 @@ int32_t rhosvd_workspace_size(const rhosvd_tensor* x, const rhosvd_params* p, si
 int32_t rhosvd_decompose(rhosvd_ctx* ctx, const rhosvd_tensor* x, const rhosvd_params* p,
                          void* workspace, size_t ws_bytes, const rhosvd_output* out,
                          void* stream) {
-    if (!ctx || !out || !out->core || !out->factors || !workspace) return RHOSVD_EINVAL;
-    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return RHOSVD_EINVAL;
-    Problem pr;
-    int32_t rc = validate(x, p, &pr, true);
-    if (rc != RHOSVD_OK) return rc;
-    pr.kernels = ctx->kernels;
-    for (int n = 0; n < pr.N; ++n)
-        if (!out->factors[n]) return RHOSVD_EINVAL;
     Plan* pl = new (std::nothrow) Plan;
     if (!pl) return RHOSVD_ENOMEM;
-    // the grid is planned for a 256-CU part so that the workspace size does
-    // not depend on the device the context was created on
-    rc = build_plan(pr, planning_cu(nullptr), pl);
-    if (rc != RHOSVD_OK) {
-        delete pl;
-        return rc;
-    }
-    Buffers b;
-    const size_t need = carve(*pl, nullptr, &b);
-    if (ws_bytes < need) {
-        delete pl;
-        return RHOSVD_ENOMEM;
-    }
-    carve(*pl, workspace, &b);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    int dev = -1;
-    hipError_t he = hipGetDevice(&dev);
-    if (he != hipSuccess) {
-        delete pl;
-        return hip_fail(he);
-    }
-    if (dev != ctx->device) {
-        he = hipSetDevice(ctx->device);
-        if (he != hipSuccess) {
-            delete pl;
-            return hip_fail(he);
-        }
-    }
-    rh::ReportInit ri{};
-    ri.order = pr.N;
-    for (int si = 0; si < pr.N; ++si) {
-        const Step& st = pl->st[si];
-        ri.k_used[st.n] = st.capped ? -st.K : st.K;
-    }
-    rc = RHOSVD_OK;
-    he = rh::launch_report_init(b.rep, ri, s);
-    if (he != hipSuccess) rc = hip_fail(he);
-    if (rc == RHOSVD_OK)
-        rc = (pr.algo == RHOSVD_R_STHOSVD) ? run_r_sthosvd(*pl, b, x->data, out, s)
-                                            : run_rp_hosvd(*pl, b, x->data, out, s);
-    if (rc == RHOSVD_OK) {
-        he = rh::launch_sumsq(pr.dbl, out->core, pl->core_elems, b.part_ss, kSumsqBlocks, s);
-        if (he == hipSuccess) he = rh::launch_reduce_ss(b.part_ss, kSumsqBlocks, &b.rep->norm_core2, s);
-        if (he == hipSuccess && out->report)
-            he = rh::launch_copy_bytes(b.rep, out->report, sizeof(rhosvd_report), s);
-        if (he != hipSuccess) rc = hip_fail(he);
-    }
-    if (dev != ctx->device) (void)hipSetDevice(dev);
+    const int32_t rc = decompose_on(ctx, x, p, workspace, ws_bytes, RHOSVD_ENOMEM, out, stream, pl);
     delete pl;
     return rc;
 }
 
 double rhosvd_report_rel_error(const rhosvd_report* r) {
     if (!r || !(r->norm_x2 > 0.0)) return NAN;
+    if (r->flags & RHOSVD_FLAG_E_EXPLICIT) return std::sqrt(r->resid2 / r->norm_x2);
     const double d = r->norm_x2 - r->norm_core2;
     return std::sqrt((d > 0.0 ? d : 0.0) / r->norm_x2);
 }
@@ -726,6 +831,57 @@ int32_t rhosvd_sketch(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t p
     RH_HIP(launch_pass(g, a, s));
     RH_HIP(rh::launch_reduce_y(dbl, part, g.grid, static_cast<int>(I), K, g.I_pad, g.K_pad, y, s));
     if (norm2) RH_HIP(rh::launch_reduce_ss(ss, g.grid, norm2, s));
+    return RHOSVD_OK;
+}
+
+static int32_t plan_sketch_all(int32_t order, const int64_t* dims, const int32_t* K, int32_t dtype,
+                               rh::AllModeArgs* a) {
+    if (order < 2 || order > RHOSVD_MAX_ORDER || !dims || !K) return RHOSVD_EINVAL;
+    if (dtype != RHOSVD_F32 && dtype != RHOSVD_F64) return RHOSVD_EINVAL;
+    int Ks[RHOSVD_MAX_ORDER];
+    double total = 1.0;
+    for (int n = 0; n < order; ++n) {
+        if (dims[n] < 1 || K[n] < 1) return RHOSVD_EINVAL;
+        total *= static_cast<double>(dims[n]);
+        Ks[n] = K[n];
+    }
+    if (total > 4.0e18) return RHOSVD_EINVAL;
+    for (int n = 0; n < order; ++n)
+        if (K[n] > RHOSVD_MAX_SKETCH || K[n] > total / dims[n]) return RHOSVD_EUNSUPPORTED;
+    if (!rh::plan_allmode(order, dims, Ks, 256, dtype == RHOSVD_F64 ? 8 : 4, a))
+        return RHOSVD_EUNSUPPORTED;
+    return RHOSVD_OK;
+}
+
+size_t rhosvd_sketch_all_workspace_size(int32_t order, const int64_t* dims, const int32_t* K,
+                                        int32_t dtype) {
+    rh::AllModeArgs a;
+    if (plan_sketch_all(order, dims, K, dtype, &a) != RHOSVD_OK) return 0;
+    const size_t elem = dtype == RHOSVD_F64 ? 8 : 4;
+    return 256 + static_cast<size_t>(a.grid) * a.S * elem + 256 + a.grid * sizeof(double) + 256;
+}
+
+int32_t rhosvd_sketch_all(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t order,
+                          const int64_t* dims, const int32_t* K, uint64_t seed, int32_t tag,
+                          double* y, double* norm2, void* workspace, size_t ws_bytes,
+                          void* stream) {
+    if (!ctx || !src || !y || !workspace) return RHOSVD_EINVAL;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return RHOSVD_EINVAL;
+    rh::AllModeArgs a;
+    const int32_t rc = plan_sketch_all(order, dims, K, dtype, &a);
+    if (rc != RHOSVD_OK) return rc;
+    if (ws_bytes < rhosvd_sketch_all_workspace_size(order, dims, K, dtype)) return RHOSVD_ENOMEM;
+    const bool dbl = dtype == RHOSVD_F64;
+    Carver cv(workspace);
+    a.part = cv.take<void>(static_cast<size_t>(a.grid) * a.S * (dbl ? 8 : 4));
+    a.part_ss = cv.take<double>(a.grid * sizeof(double));
+    a.x = src;
+    a.seed = seed;
+    a.tag = static_cast<uint32_t>(tag);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    RH_HIP(rh::launch_allmode(dbl, a, s));
+    RH_HIP(rh::launch_allmode_reduce(dbl, a, y, s));
+    if (norm2) RH_HIP(rh::launch_reduce_ss(a.part_ss, a.grid, norm2, s));
     return RHOSVD_OK;
 }
 

@@ -77,7 +77,7 @@ def test_workspace_size_valid(lib):
     (dict(dims=(10, 10), ranks=(3, 3), order=(0, 0)), L.EINVAL),
     (dict(dims=(10, 10), ranks=(3, 3), order=(1, 2)), L.EINVAL),
     (dict(dims=(10, 10), ranks=(3, 3), algo=7), L.EINVAL),
-    (dict(dims=(10, 10), ranks=(3, 3), flags=1), L.EINVAL),
+    (dict(dims=(10, 10), ranks=(3, 3), flags=2), L.EINVAL),
     (dict(dims=(10, 10), ranks=(3, 3), flags=0x80000000), L.EINVAL),   # unknown option bits
     (dict(dims=(10, 10), ranks=(3, 3), flags=0x100), L.EINVAL),
     (dict(dims=(10, 10), ranks=(3, 3), dtype=L.F32, prec=L.PREC_F64), L.EINVAL),
@@ -90,6 +90,11 @@ def test_workspace_size_rejects(lib, kw, expect):
     dims, ranks = kw.pop("dims"), kw.pop("ranks")
     rc, _ = _ws(lib, dims, ranks, **kw)
     assert rc == expect
+
+
+def test_explicit_error_option_is_valid(lib):
+    rc, n = _ws(lib, (10, 10), (3, 3), flags=L.OPT_EXPLICIT_ERROR)
+    assert rc == L.OK and n > 0
 
 
 def test_null_arguments(lib):
@@ -121,14 +126,19 @@ def test_report_rel_error_host(lib):
     assert abs(lib.rhosvd_report_rel_error(ctypes.byref(r)) - 0.5) < 1e-15
     r.norm_core2 = 5.0        # rounding can push ||G|| above ||X||: clamp at 0
     assert lib.rhosvd_report_rel_error(ctypes.byref(r)) == 0.0
+    r.norm_x2 = 4.0
+    r.resid2 = 1e-24 * 4.0           # the explicit residual, when flagged, wins
+    r.flags = L.FLAG_E_EXPLICIT
+    assert abs(lib.rhosvd_report_rel_error(ctypes.byref(r)) - 1e-12) < 1e-27
     r.norm_x2 = 0.0
     assert np.isnan(lib.rhosvd_report_rel_error(ctypes.byref(r)))
 
 
 def test_report_layout_matches_header(lib):
-    # double, double, int32, int32[16], uint32, double[16][128]
-    assert ctypes.sizeof(L.Report) == 8 + 8 + 4 + 64 + 4 + 16 * 128 * 8
+    # double, double, int32, int32[16], uint32, double[16][128], double
+    assert ctypes.sizeof(L.Report) == 8 + 8 + 4 + 64 + 4 + 16 * 128 * 8 + 8
     assert L.Report.sigma.offset == 88
+    assert L.Report.resid2.offset == 88 + 16 * 128 * 8
 
 
 def test_binding_imports_without_gpu():

@@ -64,8 +64,13 @@ typedef enum {
     RHOSVD_EHIP = 3,          /* a HIP runtime call failed */
     RHOSVD_ENUMERIC = 4,      /* reserved */
     RHOSVD_EBUSY = 5,         /* reserved */
-    RHOSVD_EUNSUPPORTED = 6   /* valid problem beyond the implemented limits */
+    RHOSVD_EUNSUPPORTED = 6,  /* valid problem beyond the implemented limits */
+    RHOSVD_ESCRATCH = 7       /* rhosvd_decompose_noalloc: the problem needs more than
+                                 RHOSVD_NOALLOC_SCRATCH_BYTES of scratch; nothing enqueued */
 } rhosvd_status;
+
+/* Size of the fixed per-device scratch of rhosvd_decompose_noalloc. */
+#define RHOSVD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 
 enum { RHOSVD_F32 = 0, RHOSVD_F64 = 1 };                     /* tensor dtypes */
 enum { RHOSVD_RP_HOSVD = 0, RHOSVD_R_STHOSVD = 1 };          /* algorithms */
@@ -170,6 +175,23 @@ int32_t rhosvd_workspace_size(const rhosvd_tensor* x, const rhosvd_params* p, si
 int32_t rhosvd_decompose(rhosvd_ctx* ctx, const rhosvd_tensor* x, const rhosvd_params* p,
                          void* workspace, size_t ws_bytes, const rhosvd_output* out,
                          void* stream);
+
+/* rhosvd_decompose without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The call itself allocates nothing (no
+ * hipMalloc / hipFree, no host heap): its scratch is a fixed array of
+ * RHOSVD_NOALLOC_SCRATCH_BYTES (64 MiB) per device, which the library holds
+ * from the first rhosvd_create on that device until the process ends.  A
+ * problem whose rhosvd_workspace_size exceeds it returns RHOSVD_ESCRATCH
+ * before anything is enqueued.  The caller still provides X, the core, the
+ * factors and the report.  Every call on one device shares that device's
+ * scratch and nothing in it needs clearing between calls (each call
+ * initialises what it reads); calls that may overlap on one device (other
+ * streams, other threads, other contexts) race on it and must be ordered by
+ * the caller.  Results are identical to rhosvd_decompose's. */
+int32_t rhosvd_decompose_noalloc(rhosvd_ctx* ctx, const rhosvd_tensor* x,
+                                 const rhosvd_params* p, const rhosvd_output* out,
+                                 void* stream);
 
 /* Relative error E = ||X - Xhat|| / ||X|| (Section 8, eq. Relativeerror)
  * from a host copy of the report: sqrt(resid2 / ||X||^2) when the explicit

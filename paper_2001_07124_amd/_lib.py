@@ -14,7 +14,8 @@ LIB_PATH = os.path.join(HERE, "librhosvd.so")
 MAX_ORDER = 16
 MAX_K = 128
 
-OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EBUSY, EUNSUPPORTED = range(7)
+OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EBUSY, EUNSUPPORTED, ESCRATCH = range(8)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 F32, F64 = 0, 1
 RP_HOSVD, R_STHOSVD = 0, 1
 PREC_F64, PREC_F32, PREC_BF16 = 0, 1, 2
@@ -67,6 +68,8 @@ _PROTOS = {
                                      ctypes.POINTER(_SZ)]),
     "rhosvd_decompose": (_I32, [_P, ctypes.POINTER(Tensor), ctypes.POINTER(Params), _P, _SZ,
                                 ctypes.POINTER(Output), _P]),
+    "rhosvd_decompose_noalloc": (_I32, [_P, ctypes.POINTER(Tensor), ctypes.POINTER(Params),
+                                        ctypes.POINTER(Output), _P]),
     "rhosvd_report_rel_error": (ctypes.c_double, [ctypes.POINTER(Report)]),
     "rhosvd_omega_fill": (_I32, [_P, _U64, _I32, _I32, _I64, _I32, _I32, _P, _P]),
     "rhosvd_sketch": (_I32, [_P, _P, _I32, _I32, _I64, _I64, _I64, _I32, _U64, _I32, _I32, _P, _P,

@@ -219,6 +219,19 @@ class Decomposer:
                                           _stream(stream, self.device)),
                 "rhosvd_decompose")
 
+    def run_noalloc(self, x, stream=None):
+        """The same decomposition through rhosvd_decompose_noalloc (the
+        library's fixed per-device scratch instead of this object's
+        workspace)."""
+        _check_fortran(x, self.dims if x.dim() == 1 else None)
+        if x.dtype != self.dtype or x.device != self.device:
+            raise ValueError("x dtype/device differ from the planned ones")
+        self.tensor.data = x.data_ptr()
+        L.check(self.lib.rhosvd_decompose_noalloc(self.ctx, ctypes.byref(self.tensor),
+                                                  ctypes.byref(self.params), ctypes.byref(self.out),
+                                                  _stream(stream, self.device)),
+                "rhosvd_decompose_noalloc")
+
     def result(self):
         return Decomposition(core=self.core, factors=self.factors, report_buf=self.report_buf,
                              order=self.N)

@@ -27,6 +27,7 @@ SOURCES = {
     "kernels_small.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
     "kernels_resid.hip": [],
     "kernels_allmode.hip": [],
+    "noalloc.hip": [],
     "rhosvd_api.hip": [],
 }
 

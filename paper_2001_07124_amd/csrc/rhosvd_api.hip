@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "internal.hpp"
 #include "kernels.hpp"
 #include "rhosvd.h"
 
@@ -15,6 +16,7 @@ struct rhosvd_ctx {
     int num_cu;
     size_t lds_per_block;
     int kernels;    // RHOSVD_KERNELS_*: which streaming kernel families may run
+    void* scratch;  // this device's address of the no-alloc scratch (noalloc.hip)
 };
 
 
@@ -670,6 +672,23 @@ int32_t decompose_on(rhosvd_ctx* ctx, const rhosvd_tensor* x, const rhosvd_param
 
 }  // namespace
 
+namespace rh {
+
+// rhosvd_decompose on a caller-given fixed workspace, with the plan on the
+// stack (no allocation of any kind); `too_small` is returned when the plan
+// does not fit.
+int32_t decompose_fixed(rhosvd_ctx* ctx, const rhosvd_tensor* x,
+                                        const rhosvd_params* p, void* ws, size_t ws_bytes,
+                                        int32_t too_small, const rhosvd_output* out,
+                                        void* stream) {
+    Plan pl;
+    return decompose_on(ctx, x, p, ws, ws_bytes, too_small, out, stream, &pl);
+}
+
+void* ctx_scratch(const rhosvd_ctx* ctx) { return ctx ? ctx->scratch : nullptr; }
+
+}  // namespace rh
+
 extern "C" {
 
 const char* rhosvd_status_string(int32_t status) {
@@ -681,6 +700,7 @@ const char* rhosvd_status_string(int32_t status) {
         case RHOSVD_ENUMERIC: return "numerical failure";
         case RHOSVD_EBUSY: return "busy";
         case RHOSVD_EUNSUPPORTED: return "unsupported problem size";
+        case RHOSVD_ESCRATCH: return "problem exceeds the fixed no-alloc scratch";
         default: return "unknown status";
     }
 }
@@ -695,12 +715,16 @@ int32_t rhosvd_create(rhosvd_ctx** ctx, int32_t device) {
     if (device < 0 || device >= count) return RHOSVD_EINVAL;
     hipDeviceProp_t prop;
     RH_HIP(hipGetDeviceProperties(&prop, device));
+    void* sp = nullptr;
+    const int32_t rs = rh::noalloc_scratch_address(device, &sp);
+    if (rs != RHOSVD_OK) return rs;
     rhosvd_ctx* c = new (std::nothrow) rhosvd_ctx;
     if (!c) return RHOSVD_ENOMEM;
     c->device = device;
     c->num_cu = prop.multiProcessorCount;
     c->lds_per_block = prop.sharedMemPerBlock;
     c->kernels = RHOSVD_KERNELS_AUTO;
+    c->scratch = sp;
     *ctx = c;
     return RHOSVD_OK;
 }

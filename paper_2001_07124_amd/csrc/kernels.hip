@@ -292,7 +292,7 @@ __global__ __launch_bounds__(kBlock) void k_stream_batch(const StreamJob* __rest
 static int round16(int64_t v) { return static_cast<int>((v + 15) / 16 * 16); }
 
 bool plan_stream(int op, int elem, int64_t L, int64_t I, int64_t T, int K, int num_cu,
-                 StreamGeom* g) {
+                 StreamGeom* g, int cmax) {
     if (L < 1 || I < 1 || T < 1 || K < 1 || K > RHOSVD_MAX_K) return false;
     if (I > 4096) return false;
     g->L = L;
@@ -318,6 +318,7 @@ bool plan_stream(int op, int elem, int64_t L, int64_t I, int64_t T, int K, int n
     for (int pass = 0; pass < 2 && g->C == 0; ++pass) {
         for (int ci = 0; ci < 3; ++ci) {
             const int C = cands[ci];
+            if (C > cmax) continue;
             if ((op == OP_POWER || op == OP_TTM) && (C / 16) * NB > 4 * kMaxT2) continue;
             size_t elems = static_cast<size_t>(C) * g->P + static_cast<size_t>(C) * g->KW;
             if (op != OP_SKETCH) elems += static_cast<size_t>(g->I_pad) * g->KW;

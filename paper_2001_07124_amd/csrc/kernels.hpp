@@ -40,7 +40,7 @@ struct StreamArgs {
 // Plan the geometry of a pass; returns false if the shape exceeds the
 // implemented limits.  elem = sizeof(float) or sizeof(double).
 bool plan_stream(int op, int elem, int64_t L, int64_t I, int64_t T, int K, int num_cu,
-                 StreamGeom* g);
+                 StreamGeom* g, int cmax = 64);
 
 hipError_t launch_stream(int op, bool dbl, const StreamGeom& g, const StreamArgs& a,
                          hipStream_t s);
@@ -159,6 +159,56 @@ struct AllModeArgs {
 bool plan_allmode(int N, const int64_t* dims, const int* K, int num_cu, int elem, AllModeArgs* a);
 hipError_t launch_allmode(bool dbl, const AllModeArgs& a, hipStream_t s);
 hipError_t launch_allmode_reduce(bool dbl, const AllModeArgs& a, double* y, hipStream_t s);
+
+// Device tables of the batched small kernels (one problem per job).
+struct ReduceJob {          // y = sum of G partials [G][K_pad][I_pad] of an I x K result
+    const void* part;
+    double* y;
+    int G, I, K, I_pad, K_pad;
+};
+struct QrJob {              // Householder QR of Y (I x K, I <= 256, K <= 64)
+    const double* y;
+    double* q64;
+    void* q_out;
+    int I, K, dbl;
+};
+struct EvdJob {             // EVD of the K x K Gram c followed by the factor step
+    const double* c;
+    uint32_t* flags;
+    const void* q;
+    void* u_out;
+    void* m_out;
+    double* sigma;
+    double* qwork;
+    int K, I, R, use_v, staged;
+};
+struct ReportJob {          // report initialisation of one item
+    rhosvd_report* rep;
+    int order;
+    int k_used[RHOSVD_MAX_ORDER];   // negative: capped
+};
+struct SumJob {             // rep->norm_x2 = sum of G per-workgroup sums
+    const double* part;
+    rhosvd_report* rep;
+    int G;
+};
+struct FinishJob {          // rep->norm_core2 = ||core||^2, then rep copied to out_report
+    const void* core;
+    rhosvd_report* rep;
+    void* out_report;
+    int64_t core_elems;
+};
+hipError_t launch_reduce_parts_batch(bool dbl, const ReduceJob* jobs, int njobs, int max_elems,
+                                     hipStream_t s);
+hipError_t launch_batch_report_init(const ReportJob* jobs, int njobs, hipStream_t s);
+hipError_t launch_batch_norm_x(const SumJob* jobs, int njobs, hipStream_t s);
+hipError_t launch_batch_finish(bool dbl, const FinishJob* jobs, int njobs, hipStream_t s);
+hipError_t launch_hqr_batch(const QrJob* jobs, int njobs, int ns, size_t lds, hipStream_t s);
+size_t hqr_lds_bytes(int I, int K);
+bool evd_factor_staged(int K, int64_t I);
+size_t evd_factor_lds_bytes(int K, int64_t I, bool staged);
+hipError_t launch_evd_factor_batch(bool dbl, const EvdJob* jobs, int njobs, int kb, size_t lds,
+                                   hipStream_t s);
 
 // Explicit residual ||X - G x_1 U_1 ... x_N U_N||^2 (kernels_resid.hip).
 // gate: one device int written by launch_resid_gate (1 when requested or when

@@ -28,13 +28,13 @@ namespace rh {
 // eight loads at a time, and the groups are added in order through LDS.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_reduce_parts(const T* __restrict__ part, int G, int I,
-                                                         int K, int I_pad, int K_pad,
-                                                         double* __restrict__ y) {
+__device__ __forceinline__ void reduce_parts_body(const T* __restrict__ part, int G, int I, int K,
+                                                  int I_pad, int K_pad, double* __restrict__ y,
+                                                  int blk) {
     constexpr int kE = 16, kG = kBlock / kE;
     __shared__ double red[kG][kE + 1];
     const int el = threadIdx.x % kE, q = threadIdx.x / kE;
-    const int e = blockIdx.x * kE + el;
+    const int e = blk * kE + el;
     double s = 0.0;
     if (e < I * K) {
         const int k = e / I, i = e - k * I;
@@ -57,6 +57,33 @@ __global__ __launch_bounds__(kBlock) void k_reduce_parts(const T* __restrict__ p
         for (int j = 0; j < kG; ++j) t += red[j][el];
         y[e] = t;
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_reduce_parts(const T* __restrict__ part, int G, int I,
+                                                         int K, int I_pad, int K_pad,
+                                                         double* __restrict__ y) {
+    reduce_parts_body<T>(part, G, I, K, I_pad, K_pad, y, blockIdx.x);
+}
+
+// Workgroup (x, y): block x of job y (blocks past the job's I K / 16 return).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_reduce_parts_batch(const ReduceJob* __restrict__ jobs) {
+    const ReduceJob j = jobs[blockIdx.y];
+    if (static_cast<int>(blockIdx.x) * 16 >= j.I * j.K) return;
+    reduce_parts_body<T>(static_cast<const T*>(j.part), j.G, j.I, j.K, j.I_pad, j.K_pad, j.y,
+                         blockIdx.x);
+}
+
+hipError_t launch_reduce_parts_batch(bool dbl, const ReduceJob* jobs, int njobs, int max_elems,
+                                     hipStream_t s) {
+    if (njobs < 1 || max_elems < 1) return hipErrorInvalidValue;
+    const dim3 grid((max_elems + 15) / 16, njobs);
+    if (dbl)
+        hipLaunchKernelGGL(k_reduce_parts_batch<double>, grid, dim3(kBlock), 0, s, jobs);
+    else
+        hipLaunchKernelGGL(k_reduce_parts_batch<float>, grid, dim3(kBlock), 0, s, jobs);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce_parts(bool dbl, const void* part, int G, int I, int K, int I_pad,
@@ -687,8 +714,8 @@ __device__ __forceinline__ double row16_total(double v) {
 }
 
 template <int NS, int RPL>
-__global__ __launch_bounds__(kBlock) void k_hqr(const double* __restrict__ y, int I, int K,
-                                                double* __restrict__ q64, void* q_out, int dbl) {
+__device__ __forceinline__ void hqr_body(const double* __restrict__ y, int I, int K,
+                                         double* __restrict__ q64, void* q_out, int dbl) {
     extern __shared__ __align__(16) double shd[];
     constexpr int VP = 16 * RPL;                   // rows held: 16 lanes x RPL
     double* V = shd;                               // reflector j at V[j * VP + row]
@@ -807,6 +834,19 @@ __global__ __launch_bounds__(kBlock) void k_hqr(const double* __restrict__ y, in
             }
         }
     }
+}
+
+template <int NS, int RPL>
+__global__ __launch_bounds__(kBlock) void k_hqr(const double* __restrict__ y, int I, int K,
+                                                double* __restrict__ q64, void* q_out, int dbl) {
+    hqr_body<NS, RPL>(y, I, K, q64, q_out, dbl);
+}
+
+// One QR per workgroup from a device table (many small problems in one launch).
+template <int NS, int RPL>
+__global__ __launch_bounds__(kBlock) void k_hqr_batch(const QrJob* __restrict__ jobs) {
+    const QrJob j = jobs[blockIdx.x];
+    hqr_body<NS, RPL>(j.y, j.I, j.K, j.q64, j.q_out, j.dbl);
 }
 
 static hipError_t launch_hqr(const double* y, int I, int K, bool dbl, void* q_out, double* q64,
@@ -983,7 +1023,7 @@ __device__ __forceinline__ double start_entry(int i, int j) {
 // instruction cache.  LDS vectors have pitch kTriP and are zero past K, so
 // those loops need no bounds.
 template <int KB, typename T, bool FACTOR>
-__global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ cin, int K,
+__device__ __forceinline__ void evd_tri_body(const double* __restrict__ cin, int K,
                                                    double* __restrict__ v_out,
                                                    double* __restrict__ lam_out, uint32_t* flags,
                                                    const T* __restrict__ q, int I, int R, int use_v,
@@ -1336,6 +1376,27 @@ __global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ c
     }
 }
 
+template <int KB, typename T, bool FACTOR>
+__global__ __launch_bounds__(kBlock) void k_evd_tri(const double* __restrict__ cin, int K,
+                                                   double* __restrict__ v_out,
+                                                   double* __restrict__ lam_out, uint32_t* flags,
+                                                   const T* __restrict__ q, int I, int R, int use_v,
+                                                   T* __restrict__ u_out, T* __restrict__ m_out,
+                                                   double* __restrict__ sigma,
+                                                   double* __restrict__ qwork, int staged) {
+    evd_tri_body<KB, T, FACTOR>(cin, K, v_out, lam_out, flags, q, I, R, use_v, u_out, m_out, sigma,
+                                qwork, staged);
+}
+
+// EVD + factor step per workgroup from a device table.
+template <int KB, typename T>
+__global__ __launch_bounds__(kBlock) void k_evd_factor_batch(const EvdJob* __restrict__ jobs) {
+    const EvdJob j = jobs[blockIdx.x];
+    evd_tri_body<KB, T, true>(j.c, j.K, nullptr, nullptr, j.flags, static_cast<const T*>(j.q), j.I,
+                              j.R, j.use_v, static_cast<T*>(j.u_out), static_cast<T*>(j.m_out),
+                              j.sigma, j.qwork, j.staged);
+}
+
 // Dynamic LDS of k_evd_tri: the tridiagonal phases' region, reused by the
 // factor step for the sorted eigenpairs (K x K + K doubles) and, when
 // `staged`, Q after them.
@@ -1409,6 +1470,60 @@ hipError_t launch_evd(const double* c, int K, double* v, double* lambda, uint32_
     if (lds + kStaticLdsMargin > kLdsLimit) return hipErrorInvalidValue;
     return launch_evd_tri<double, false>(c, K, v, lambda, flags, nullptr, 0, 0, 0, nullptr,
                                          nullptr, nullptr, nullptr, 0, lds, s);
+}
+
+// Batched QR (all jobs Householder-eligible: I <= 256, K <= 64) and batched
+// EVD + factor step; `ns` / `kb` select the template every job of the launch
+// shares, `lds` the largest dynamic LDS among them.
+hipError_t launch_hqr_batch(const QrJob* jobs, int njobs, int ns, size_t lds, hipStream_t s) {
+    if (njobs < 1 || lds + kStaticLdsMargin > kLdsLimit) return hipErrorInvalidValue;
+    switch (ns) {
+        case 1: hipLaunchKernelGGL((k_hqr_batch<1, 16>), dim3(njobs), dim3(kBlock), lds, s, jobs); break;
+        case 2: hipLaunchKernelGGL((k_hqr_batch<2, 16>), dim3(njobs), dim3(kBlock), lds, s, jobs); break;
+        case 3: hipLaunchKernelGGL((k_hqr_batch<3, 16>), dim3(njobs), dim3(kBlock), lds, s, jobs); break;
+        case 4: hipLaunchKernelGGL((k_hqr_batch<4, 16>), dim3(njobs), dim3(kBlock), lds, s, jobs); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+size_t hqr_lds_bytes(int I, int K) {
+    (void)I;
+    return static_cast<size_t>(K) * 16 * 16 * sizeof(double);
+}
+
+bool evd_factor_staged(int K, int64_t I) {
+    return evd_lds_bytes(K, I, true, true) + kStaticLdsMargin <= kLdsLimit;
+}
+
+size_t evd_factor_lds_bytes(int K, int64_t I, bool staged) { return evd_lds_bytes(K, I, true, staged); }
+
+hipError_t launch_evd_factor_batch(bool dbl, const EvdJob* jobs, int njobs, int kb, size_t lds,
+                                   hipStream_t s) {
+    if (njobs < 1 || lds + kStaticLdsMargin > kLdsLimit) return hipErrorInvalidValue;
+#define RH_EVB_CASE(KBV)                                                                           \
+    case KBV:                                                                                      \
+        if (dbl)                                                                                   \
+            hipLaunchKernelGGL((k_evd_factor_batch<KBV, double>), dim3(njobs), dim3(kBlock), lds, \
+                               s, jobs);                                                           \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_evd_factor_batch<KBV, float>), dim3(njobs), dim3(kBlock), lds,  \
+                               s, jobs);                                                           \
+        break;
+    switch (kb) {
+        RH_EVB_CASE(8)
+        RH_EVB_CASE(16)
+        RH_EVB_CASE(24)
+        RH_EVB_CASE(32)
+        RH_EVB_CASE(40)
+        RH_EVB_CASE(48)
+        RH_EVB_CASE(56)
+        RH_EVB_CASE(64)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef RH_EVB_CASE
+    return hipGetLastError();
 }
 
 }  // namespace rh

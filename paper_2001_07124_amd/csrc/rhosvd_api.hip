@@ -4,8 +4,10 @@
 // host; every arithmetic step is a kernel in kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "internal.hpp"
 #include "kernels.hpp"
@@ -16,6 +18,9 @@ struct rhosvd_ctx {
     int num_cu;
     size_t lds_per_block;
     int kernels;    // RHOSVD_KERNELS_*: which streaming kernel families may run
+    // tile parameters of the batched passes, tuned once per context
+    int tuned = 0, tune_cmax = 64, tune_tpu = 1;
+    float tune_ms = 0.0f;
     void* scratch;  // this device's address of the no-alloc scratch (noalloc.hip)
 };
 
@@ -983,6 +988,556 @@ int32_t rhosvd_sym_evd(rhosvd_ctx* ctx, const double* c, int32_t K, double* v, d
     if (K > kMaxSmallK) return RHOSVD_EUNSUPPORTED;
     RH_HIP(rh::launch_evd(c, K, v, lambda, flags, static_cast<hipStream_t>(stream)));
     return RHOSVD_OK;
+}
+
+}  // extern "C"
+
+// ---- batched decomposition ------------------------------------------------
+// Many small tensors, one launch per step for the whole batch: every
+// streaming pass, reduction, QR and EVD of mode step s of every item goes
+// into one launch driven by a device table of jobs (grouped by the template
+// the small kernels need), and the whole sequence is captured once into a
+// HIP graph and replayed.  Each item keeps the buffers of its own
+// single-tensor plan (carved from its own region of the workspace) and runs
+// the workgroup-tiled streaming kernels, so an item's arithmetic depends only
+// on its own shape and the tuned tile parameters, never on the other items.
+
+namespace {
+
+constexpr int kBatchUnits = 64;          // most workgroups per item per pass
+
+enum BatchKind { BK_STREAM, BK_REDUCE, BK_QR, BK_EVD, BK_INIT, BK_NORMX, BK_FINISH };
+
+struct BatchLaunch {
+    int kind = 0, op = 0, njobs = 0, sel = 0;
+    size_t lds = 0, off = 0;
+};
+
+// Per pass of an item: re-plan the tiled geometry with the tuned tile width
+// cap and tiles per workgroup.
+void batch_pass(Pass* p, int op, int elem, int64_t I, int64_t T, int K, int cmax, int tpu) {
+    rh::StreamGeom g;
+    if (!rh::plan_stream(op, elem, 1, I, T, K, 256, &g, cmax)) return;
+    int64_t units = (g.ntiles + tpu - 1) / tpu;
+    if (units > kBatchUnits) units = kBatchUnits;
+    if (units < 1) units = 1;
+    g.grid = static_cast<int>(units);
+    p->sg = g;
+    p->kind = PASS_TILED;
+    p->grid = g.grid;
+    p->I_pad = g.I_pad;
+    p->K_pad = g.K_pad;
+}
+
+void batch_geometry(Plan* pl, int cmax, int tpu) {
+    const int elem = static_cast<int>(pl->pr.elem);
+    for (int s = 0; s < pl->pr.N; ++s) {
+        Step& st = pl->st[s];
+        batch_pass(&st.gs, rh::OP_SKETCH, elem, st.I, st.T, st.K, cmax, tpu);
+        batch_pass(&st.gp, rh::OP_POWER, elem, st.I, st.T, st.K, cmax, tpu);
+        batch_pass(&st.gt, rh::OP_TTM, elem, st.I, st.T, st.K, cmax, tpu);
+        batch_pass(&st.gtr, rh::OP_TTM, elem, st.K, st.T, st.R, cmax, tpu);
+    }
+}
+
+}  // namespace
+
+struct rhosvd_batch {
+    rhosvd_ctx* ctx = nullptr;
+    int n = 0, N = 0, maxq = 0;
+    bool dbl = false;
+    std::vector<Plan*> plans;
+    std::vector<size_t> region;              // offset of each item's region
+    std::vector<const void*> x;
+    std::vector<void*> core, report;
+    std::vector<std::vector<void*>> factors;
+    size_t tables_cap = 0, ws_bytes = 0;
+    unsigned char* ws = nullptr;
+    std::vector<BatchLaunch> prog;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~rhosvd_batch() {
+        for (Plan* p : plans) delete p;
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+namespace {
+
+// Host image of the device tables, appended launch by launch.
+struct TableWriter {
+    std::vector<unsigned char> bytes;
+    template <typename J>
+    size_t put(const std::vector<J>& jobs) {
+        size_t off = (bytes.size() + 255) & ~static_cast<size_t>(255);
+        bytes.resize(off + jobs.size() * sizeof(J));
+        std::memcpy(bytes.data() + off, jobs.data(), jobs.size() * sizeof(J));
+        return off;
+    }
+};
+
+// The launch program of the whole batch (and its tables) for the bound
+// workspace, with the current tile parameters of every plan.
+void build_program(rhosvd_batch* B, TableWriter* tw) {
+    B->prog.clear();
+    const int n = B->n, N = B->N;
+    std::vector<Buffers> bufs(n);
+    for (int i = 0; i < n; ++i) carve(*B->plans[i], B->ws + B->region[i], &bufs[i]);
+    std::vector<const void*> cur(B->x.begin(), B->x.end());
+    auto add_stream = [&](int op, std::vector<rh::StreamJob>& jobs) {
+        if (jobs.empty()) return;
+        BatchLaunch L;
+        L.kind = BK_STREAM;
+        L.op = op;
+        L.njobs = static_cast<int>(jobs.size());
+        for (auto& j : jobs) {
+            L.sel = std::max(L.sel, j.units);
+            L.lds = std::max(L.lds, j.g.lds_bytes);
+        }
+        L.off = tw->put(jobs);
+        B->prog.push_back(L);
+    };
+    auto add_reduce = [&](std::vector<rh::ReduceJob>& jobs) {
+        if (jobs.empty()) return;
+        BatchLaunch L;
+        L.kind = BK_REDUCE;
+        L.njobs = static_cast<int>(jobs.size());
+        for (auto& j : jobs) L.sel = std::max(L.sel, j.I * j.K);
+        L.off = tw->put(jobs);
+        B->prog.push_back(L);
+    };
+    auto add_qr = [&](std::vector<rh::QrJob>& jobs) {
+        for (int ns = 1; ns <= 4; ++ns) {
+            std::vector<rh::QrJob> sub;
+            size_t lds = 0;
+            for (auto& j : jobs)
+                if ((j.K + 15) / 16 == ns) {
+                    sub.push_back(j);
+                    lds = std::max(lds, rh::hqr_lds_bytes(j.I, j.K));
+                }
+            if (sub.empty()) continue;
+            BatchLaunch L;
+            L.kind = BK_QR;
+            L.njobs = static_cast<int>(sub.size());
+            L.sel = ns;
+            L.lds = lds;
+            L.off = tw->put(sub);
+            B->prog.push_back(L);
+        }
+    };
+    // report initialisation
+    {
+        std::vector<rh::ReportJob> jobs(n);
+        for (int i = 0; i < n; ++i) {
+            jobs[i] = rh::ReportJob{};
+            jobs[i].rep = bufs[i].rep;
+            jobs[i].order = N;
+            for (int s = 0; s < N; ++s) {
+                const Step& st = B->plans[i]->st[s];
+                jobs[i].k_used[st.n] = st.capped ? -st.K : st.K;
+            }
+        }
+        BatchLaunch L;
+        L.kind = BK_INIT;
+        L.njobs = n;
+        L.off = tw->put(jobs);
+        B->prog.push_back(L);
+    }
+    for (int s = 0; s < N; ++s) {
+        // sketch, reduction, (norm of X), QR
+        std::vector<rh::StreamJob> sj;
+        std::vector<rh::ReduceJob> rj;
+        std::vector<rh::QrJob> qj;
+        std::vector<rh::SumJob> nj;
+        for (int i = 0; i < n; ++i) {
+            const Plan& pl = *B->plans[i];
+            const Step& st = pl.st[s];
+            const Buffers& b = bufs[i];
+            rh::StreamJob j{};
+            j.g = st.gs.sg;
+            j.units = st.gs.grid;
+            j.a.src = cur[i];
+            j.a.part_y = b.part;
+            j.a.part_ss = s == 0 ? b.part_ss : nullptr;
+            j.a.seed = pl.pr.seed;
+            j.a.mode = static_cast<uint32_t>(st.n);
+            j.a.tag = 2u;
+            sj.push_back(j);
+            rj.push_back(rh::ReduceJob{b.part, b.y, st.gs.grid, static_cast<int>(st.I), st.K,
+                                       st.gs.I_pad, st.gs.K_pad});
+            qj.push_back(rh::QrJob{b.y, b.q64, b.qT, static_cast<int>(st.I), st.K, B->dbl ? 1 : 0});
+            if (s == 0) nj.push_back(rh::SumJob{b.part_ss, b.rep, st.gs.grid});
+        }
+        add_stream(rh::OP_SKETCH, sj);
+        add_reduce(rj);
+        if (s == 0) {
+            BatchLaunch L;
+            L.kind = BK_NORMX;
+            L.njobs = n;
+            L.off = tw->put(nj);
+            B->prog.push_back(L);
+        }
+        add_qr(qj);
+        // power steps (items with more power steps than it)
+        for (int it = 0; it < B->maxq; ++it) {
+            std::vector<rh::StreamJob> pj;
+            std::vector<rh::ReduceJob> prj;
+            std::vector<rh::QrJob> pqj;
+            for (int i = 0; i < n; ++i) {
+                const Plan& pl = *B->plans[i];
+                if (pl.pr.q <= it) continue;
+                const Step& st = pl.st[s];
+                const Buffers& b = bufs[i];
+                rh::StreamJob j{};
+                j.g = st.gp.sg;
+                j.units = st.gp.grid;
+                j.a.src = cur[i];
+                j.a.mat = b.qT;
+                j.a.part_y = b.part;
+                pj.push_back(j);
+                prj.push_back(rh::ReduceJob{b.part, b.y, st.gp.grid, static_cast<int>(st.I), st.K,
+                                            st.gp.I_pad, st.gp.K_pad});
+                pqj.push_back(rh::QrJob{b.y, b.q64, b.qT, static_cast<int>(st.I), st.K,
+                                        B->dbl ? 1 : 0});
+            }
+            add_stream(rh::OP_POWER, pj);
+            add_reduce(prj);
+            add_qr(pqj);
+        }
+        // projection B = Q^T S_(n) with its Gram, the Gram reduction
+        std::vector<rh::StreamJob> tj;
+        std::vector<rh::ReduceJob> gj;
+        std::vector<rh::EvdJob> ej;
+        for (int i = 0; i < n; ++i) {
+            const Plan& pl = *B->plans[i];
+            const Step& st = pl.st[s];
+            const Buffers& b = bufs[i];
+            rh::StreamJob j{};
+            j.g = st.gt.sg;
+            j.units = st.gt.grid;
+            j.a.src = cur[i];
+            j.a.mat = b.qT;
+            j.a.out = b.B;
+            j.a.part_g = b.part;
+            tj.push_back(j);
+            gj.push_back(rh::ReduceJob{b.part, b.C, st.gt.grid, st.K, st.K, st.gt.K_pad,
+                                       st.gt.K_pad});
+            rh::EvdJob e{};
+            e.c = b.C;
+            e.flags = &b.rep->flags;
+            e.q = b.qT;
+            e.u_out = B->factors[i][st.n];
+            e.m_out = b.M;
+            e.sigma = &b.rep->sigma[st.n][0];
+            e.qwork = b.u64;
+            e.K = st.K;
+            e.I = static_cast<int>(st.I);
+            e.R = st.R;
+            e.use_v = 1;
+            e.staged = rh::evd_factor_staged(st.K, st.I) ? 1 : 0;
+            ej.push_back(e);
+        }
+        add_stream(rh::OP_TTM, tj);
+        add_reduce(gj);
+        for (int kb = 8; kb <= 64; kb += 8) {
+            std::vector<rh::EvdJob> sub;
+            size_t lds = 0;
+            for (auto& e : ej)
+                if (((e.K + 7) & ~7) == kb) {
+                    sub.push_back(e);
+                    lds = std::max(lds, rh::evd_factor_lds_bytes(e.K, e.I, e.staged != 0));
+                }
+            if (sub.empty()) continue;
+            BatchLaunch L;
+            L.kind = BK_EVD;
+            L.njobs = static_cast<int>(sub.size());
+            L.sel = kb;
+            L.lds = lds;
+            L.off = tw->put(sub);
+            B->prog.push_back(L);
+        }
+        // truncation S <- Ubar_R^T B, written rotated
+        std::vector<rh::StreamJob> rj2;
+        for (int i = 0; i < n; ++i) {
+            const Plan& pl = *B->plans[i];
+            const Step& st = pl.st[s];
+            const Buffers& b = bufs[i];
+            void* dst = (s == N - 1) ? B->core[i] : ((s % 2 == 0) ? b.ping : b.pong);
+            rh::StreamJob j{};
+            j.g = st.gtr.sg;
+            j.units = st.gtr.grid;
+            j.a.src = b.B;
+            j.a.mat = b.M;
+            j.a.out = dst;
+            j.a.out_t = 1;
+            rj2.push_back(j);
+            cur[i] = dst;
+        }
+        add_stream(rh::OP_TTM, rj2);
+    }
+    {
+        std::vector<rh::FinishJob> fj(n);
+        for (int i = 0; i < n; ++i)
+            fj[i] = rh::FinishJob{B->core[i], bufs[i].rep, B->report[i], B->plans[i]->core_elems};
+        BatchLaunch L;
+        L.kind = BK_FINISH;
+        L.njobs = n;
+        L.off = tw->put(fj);
+        B->prog.push_back(L);
+    }
+}
+
+hipError_t run_program(const rhosvd_batch* B, hipStream_t s) {
+    for (const BatchLaunch& L : B->prog) {
+        const void* t = B->ws + L.off;
+        hipError_t e = hipSuccess;
+        switch (L.kind) {
+            case BK_STREAM:
+                e = rh::launch_stream_batch(L.op, B->dbl, static_cast<const rh::StreamJob*>(t),
+                                            L.njobs, L.sel, L.lds, s);
+                break;
+            case BK_REDUCE:
+                e = rh::launch_reduce_parts_batch(B->dbl, static_cast<const rh::ReduceJob*>(t),
+                                                  L.njobs, L.sel, s);
+                break;
+            case BK_QR:
+                e = rh::launch_hqr_batch(static_cast<const rh::QrJob*>(t), L.njobs, L.sel, L.lds, s);
+                break;
+            case BK_EVD:
+                e = rh::launch_evd_factor_batch(B->dbl, static_cast<const rh::EvdJob*>(t), L.njobs,
+                                                L.sel, L.lds, s);
+                break;
+            case BK_INIT:
+                e = rh::launch_batch_report_init(static_cast<const rh::ReportJob*>(t), L.njobs, s);
+                break;
+            case BK_NORMX:
+                e = rh::launch_batch_norm_x(static_cast<const rh::SumJob*>(t), L.njobs, s);
+                break;
+            case BK_FINISH:
+                e = rh::launch_batch_finish(B->dbl, static_cast<const rh::FinishJob*>(t), L.njobs, s);
+                break;
+            default:
+                e = hipErrorInvalidValue;
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Upper bound of the tables: every launch holds at most one job per item.
+size_t tables_bound(int n, int N, int maxq) {
+    const size_t per_item_jobs = static_cast<size_t>(N) * (7 + 3 * maxq) + 3;
+    return (per_item_jobs * n * sizeof(rh::StreamJob) + 256 * (N * (12 + 8 * maxq) + 8) + 4095) &
+           ~static_cast<size_t>(4095);
+}
+
+// Mode-1 sketch of every item with the tile width cap `cmax` and `tpu` tiles
+// per workgroup: the time of the fastest of three launches (ms).
+int32_t time_candidate(rhosvd_batch* B, int cmax, int tpu, hipStream_t s, float* ms) {
+    std::vector<rh::StreamJob> jobs;
+    size_t lds = 0;
+    int maxu = 1;
+    for (int i = 0; i < B->n; ++i) {
+        Plan pl = *B->plans[i];
+        batch_geometry(&pl, cmax, tpu);
+        Buffers b;
+        carve(pl, B->ws + B->region[i], &b);
+        const Step& st = pl.st[0];
+        rh::StreamJob j{};
+        j.g = st.gs.sg;
+        j.units = st.gs.grid;
+        j.a.src = B->x[i];
+        j.a.part_y = b.part;
+        j.a.seed = pl.pr.seed;
+        j.a.mode = static_cast<uint32_t>(st.n);
+        j.a.tag = 2u;
+        jobs.push_back(j);
+        lds = std::max(lds, j.g.lds_bytes);
+        maxu = std::max(maxu, j.units);
+    }
+    RH_HIP(hipMemcpy(B->ws, jobs.data(), jobs.size() * sizeof(rh::StreamJob), hipMemcpyHostToDevice));
+    hipEvent_t e0, e1;
+    RH_HIP(hipEventCreate(&e0));
+    RH_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    for (int r = 0; r < 3; ++r) {
+        RH_HIP(hipEventRecord(e0, s));
+        RH_HIP(rh::launch_stream_batch(rh::OP_SKETCH, B->dbl,
+                                       reinterpret_cast<const rh::StreamJob*>(B->ws),
+                                       static_cast<int>(jobs.size()), maxu, lds, s));
+        RH_HIP(hipEventRecord(e1, s));
+        RH_HIP(hipEventSynchronize(e1));
+        float t = 0.0f;
+        RH_HIP(hipEventElapsedTime(&t, e0, e1));
+        if (r > 0 && t < best) best = t;     // the first launch warms up
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = best;
+    return RHOSVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t rhosvd_batch_create(rhosvd_ctx* ctx, int32_t count, const rhosvd_tensor* x,
+                            const rhosvd_params* p, const rhosvd_output* out,
+                            rhosvd_batch** batch, size_t* ws_bytes) {
+    if (!ctx || count < 1 || !x || !p || !out || !batch || !ws_bytes) return RHOSVD_EINVAL;
+    *batch = nullptr;
+    rhosvd_batch* B = new (std::nothrow) rhosvd_batch;
+    if (!B) return RHOSVD_ENOMEM;
+    B->ctx = ctx;
+    B->n = count;
+    int32_t rc = RHOSVD_OK;
+    size_t off = 0;
+    for (int i = 0; i < count && rc == RHOSVD_OK; ++i) {
+        Problem pr;
+        rc = validate(&x[i], &p[i], &pr, true);
+        if (rc != RHOSVD_OK) break;
+        if (pr.algo != RHOSVD_R_STHOSVD || (pr.explicit_error)) { rc = RHOSVD_EUNSUPPORTED; break; }
+        if (!out[i].core || !out[i].factors) { rc = RHOSVD_EINVAL; break; }
+        for (int nn = 0; nn < pr.N; ++nn)
+            if (!out[i].factors[nn]) rc = RHOSVD_EINVAL;
+        if (rc != RHOSVD_OK) break;
+        if (i == 0) {
+            B->N = pr.N;
+            B->dbl = pr.dbl;
+        } else if (pr.N != B->N || pr.dbl != B->dbl) {
+            rc = RHOSVD_EUNSUPPORTED;
+            break;
+        }
+        pr.kernels = RHOSVD_KERNELS_TILED;
+        Plan* pl = new (std::nothrow) Plan;
+        if (!pl) { rc = RHOSVD_ENOMEM; break; }
+        B->plans.push_back(pl);
+        rc = build_plan(pr, 256, pl);
+        if (rc != RHOSVD_OK) break;
+        if (!pl->rotated) { rc = RHOSVD_EUNSUPPORTED; break; }
+        for (int s = 0; s < pr.N; ++s)
+            if (pl->st[s].I > 256 || pl->st[s].K > 64) rc = RHOSVD_EUNSUPPORTED;
+        if (rc != RHOSVD_OK) break;
+        // the region holds the partials of up to kBatchUnits workgroups per pass
+        batch_geometry(pl, 64, 1);
+        pl->part_bytes = 0;
+        pl->max_grid = kBatchUnits;
+        for (int s = 0; s < pr.N; ++s) {
+            const Step& st = pl->st[s];
+            const Pass* ps[4] = {&st.gs, &st.gp, &st.gt, &st.gtr};
+            for (const Pass* q : ps) {
+                const size_t big = static_cast<size_t>(std::max(q->I_pad, q->K_pad));
+                const size_t b = static_cast<size_t>(kBatchUnits) * q->K_pad * big * pr.elem;
+                pl->part_bytes = std::max(pl->part_bytes, b);
+            }
+        }
+        B->maxq = std::max(B->maxq, pr.q);
+        B->x.push_back(x[i].data);
+        B->core.push_back(out[i].core);
+        B->report.push_back(out[i].report);
+        B->factors.emplace_back(out[i].factors, out[i].factors + pr.N);
+        Buffers b;
+        const size_t sz = (carve(*pl, nullptr, &b) + 4095) & ~static_cast<size_t>(4095);
+        B->region.push_back(off);
+        off += sz;
+    }
+    if (rc != RHOSVD_OK) {
+        delete B;
+        return rc;
+    }
+    B->tables_cap = tables_bound(count, B->N, B->maxq);
+    for (auto& r : B->region) r += B->tables_cap;
+    B->ws_bytes = B->tables_cap + off;
+    *ws_bytes = B->ws_bytes;
+    *batch = B;
+    return RHOSVD_OK;
+}
+
+int32_t rhosvd_batch_bind(rhosvd_batch* B, void* workspace, size_t ws_bytes, int32_t autotune,
+                          void* stream) {
+    if (!B || !workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return RHOSVD_EINVAL;
+    if (ws_bytes < B->ws_bytes) return RHOSVD_ENOMEM;
+    B->ws = static_cast<unsigned char*>(workspace);
+    if (B->exec) {
+        (void)hipGraphExecDestroy(B->exec);
+        B->exec = nullptr;
+    }
+    if (B->graph) {
+        (void)hipGraphDestroy(B->graph);
+        B->graph = nullptr;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rhosvd_ctx* ctx = B->ctx;
+    if (!ctx->tuned && autotune) {
+        // tile width cap x tiles per workgroup, timed on this batch's mode-1
+        // sketch; the choice is kept in the context so that every later batch
+        // (and a batch of one) computes with the same tiles
+        const int cm[3] = {64, 32, 16}, tp[4] = {1, 2, 4, 8};
+        float best = 1e30f;
+        int bc = 64, bt = 1;
+        for (int c : cm)
+            for (int t : tp) {
+                float ms = 0.0f;
+                const int32_t rc = time_candidate(B, c, t, s, &ms);
+                if (rc != RHOSVD_OK) return rc;
+                if (ms < best) {
+                    best = ms;
+                    bc = c;
+                    bt = t;
+                }
+            }
+        ctx->tuned = 1;
+        ctx->tune_cmax = bc;
+        ctx->tune_tpu = bt;
+        ctx->tune_ms = best;
+    }
+    const int cmax = ctx->tuned ? ctx->tune_cmax : 64;
+    const int tpu = ctx->tuned ? ctx->tune_tpu : 1;
+    for (Plan* pl : B->plans) batch_geometry(pl, cmax, tpu);
+    TableWriter tw;
+    build_program(B, &tw);
+    if (tw.bytes.size() > B->tables_cap) return RHOSVD_ENOMEM;
+    RH_HIP(hipMemcpy(B->ws, tw.bytes.data(), tw.bytes.size(), hipMemcpyHostToDevice));
+    return RHOSVD_OK;
+}
+
+int32_t rhosvd_batch_run(rhosvd_batch* B, int32_t use_graph, void* stream) {
+    if (!B || !B->ws) return RHOSVD_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = -1;
+    RH_HIP(hipGetDevice(&dev));
+    if (dev != B->ctx->device) RH_HIP(hipSetDevice(B->ctx->device));
+    hipError_t e = hipSuccess;
+    if (!use_graph || !s) {
+        e = run_program(B, s);
+    } else {
+        if (!B->exec) {
+            e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                const hipError_t er = run_program(B, s);
+                hipGraph_t g = nullptr;
+                e = hipStreamEndCapture(s, &g);
+                if (er != hipSuccess) e = er;
+                if (e == hipSuccess) {
+                    B->graph = g;
+                    e = hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0);
+                } else if (g) {
+                    (void)hipGraphDestroy(g);
+                }
+            }
+        }
+        if (e == hipSuccess) e = hipGraphLaunch(B->exec, s);
+    }
+    if (dev != B->ctx->device) (void)hipSetDevice(dev);
+    if (e != hipSuccess) return hip_fail(e);
+    return RHOSVD_OK;
+}
+
+void rhosvd_batch_destroy(rhosvd_batch* B) { delete B; }
+
+int32_t rhosvd_batch_launches(const rhosvd_batch* B) {
+    return B ? static_cast<int32_t>(B->prog.size()) : 0;
 }
 
 }  // extern "C"

@@ -133,3 +133,33 @@ def make_workload(name, scale_dims=None):
                                   factors=w["factors"], decay=w["decay"],
                                   noise=w["noise"], dtype=w["dtype"])
     return x, w
+
+
+def batch_specs(count=512, seed=1, dim_range=(32, 256), rank_range=(4, 32), order=3):
+    """Shapes of a batch of independent order-3 problems: every extent uniform
+    in dim_range and every exact rank uniform in rank_range, capped by the
+    extent and by the product of the other ranks (a multilinear rank cannot
+    exceed it), drawn from one generator seeded with [seed, 2]."""
+    rng = np.random.default_rng([int(seed), 2])
+    out = []
+    for _ in range(int(count)):
+        dims = tuple(int(v) for v in rng.integers(dim_range[0], dim_range[1] + 1, size=order))
+        ranks = [min(int(r), d) for r, d in
+                 zip(rng.integers(rank_range[0], rank_range[1] + 1, size=order), dims)]
+        changed = True
+        while changed:
+            changed = False
+            for n in range(order):
+                cap = int(np.prod([ranks[m] for m in range(order) if m != n]))
+                if ranks[n] > cap:
+                    ranks[n] = cap
+                    changed = True
+        out.append((dims, tuple(ranks)))
+    return out
+
+
+def batch_tensors(specs, *, seed=1, noise=1e-4, dtype=np.float32):
+    """One low-rank-plus-noise tensor per spec (orthonormal factors), item i
+    drawn with data seed 1000 seed + i."""
+    return [tucker_tensor(d, r, seed=1000 * int(seed) + i, noise=noise, dtype=dtype, workers=4)[0]
+            for i, (d, r) in enumerate(specs)]

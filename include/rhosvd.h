@@ -193,6 +193,95 @@ int32_t rhosvd_decompose_noalloc(rhosvd_ctx* ctx, const rhosvd_tensor* x,
                                  const rhosvd_params* p, const rhosvd_output* out,
                                  void* stream);
 
+/* ---- Batched decomposition: many small tensors in one graph launch ----
+ *
+ * R-STHOSVD (Algorithm 8 with Algorithm 1 per mode) of `count` independent
+ * tensors.  Every step of every item runs inside one launch per step for the
+ * whole batch (device tables of jobs; the QR and EVD launches are split by
+ * the kernel template their K needs), and rhosvd_batch_run captures that
+ * sequence into a HIP graph once and replays it.
+ * Limits (else RHOSVD_EUNSUPPORTED, nothing allocated): every item
+ * RHOSVD_R_STHOSVD in the natural mode order, without
+ * RHOSVD_OPT_EXPLICIT_ERROR; one order N and one dtype for the batch; every
+ * mode I_n <= 256 and K_n <= RHOSVD_MAX_SKETCH.  Dims, ranks, p, q, seed and
+ * precision may differ per item; the streaming passes run the workgroup-
+ * tiled FP32/FP64 kernels whatever the precision.  An item's result depends
+ * only on its own problem and on the context's tuned tile parameters, so it
+ * is bitwise the same alone (a batch of one) and in any mix.
+ *
+ * The context's tuner picks the tile width and the tiles per workgroup by
+ * timing the candidates on the first batch bound with autotune != 0; the
+ * choice is kept in the context for all later batches.
+ */
+typedef struct rhosvd_batch rhosvd_batch;
+
+/* Validate and plan the batch (host only).  x, p, out: arrays of `count`;
+ * the pointers in them (data, core, factors, report) are recorded and must
+ * stay valid while the batch is used.  *ws_bytes receives the workspace size. */
+int32_t rhosvd_batch_create(rhosvd_ctx* ctx, int32_t count, const rhosvd_tensor* x,
+                            const rhosvd_params* p, const rhosvd_output* out,
+                            rhosvd_batch** batch, size_t* ws_bytes);
+
+/* Bind the workspace (device, 256-byte aligned, at least *ws_bytes): runs
+ * the tuner on `stream` when asked and the context has no choice yet, then
+ * uploads the job tables into the workspace (a synchronous copy). */
+int32_t rhosvd_batch_bind(rhosvd_batch* batch, void* workspace, size_t ws_bytes,
+                          int32_t autotune, void* stream);
+
+/* Enqueue the whole batch on `stream`.  use_graph != 0 and a non-null
+ * stream: the first call captures the launch sequence into a HIP graph,
+ * every call launches that graph (one launch); otherwise the launches are
+ * enqueued directly.  Inputs and outputs are the recorded ones. */
+int32_t rhosvd_batch_run(rhosvd_batch* batch, int32_t use_graph, void* stream);
+
+/* Number of kernel launches in one run of the batch (0 before binding). */
+int32_t rhosvd_batch_launches(const rhosvd_batch* batch);
+
+void rhosvd_batch_destroy(rhosvd_batch* batch);
+
+/* ---- Serving: a continuous-batching request loop ----
+ *
+ * Decompositions submitted at any time queue in arrival order; a scheduler
+ * thread admits them while one of `max_slots` slots (HIP streams of default
+ * priority) is free and the request's workspace (rhosvd_workspace_size) fits
+ * in the free part of the caller's device pool (first fit; the oldest
+ * `lookahead` = 8 waiting requests are scanned for one that fits), enqueues
+ * the whole decomposition on the slot's stream and frees slot and memory as
+ * soon as it completes.  Requests that arrive while others run are admitted
+ * as slots and memory free up, and their kernels overlap on the device.  A
+ * request computes exactly what rhosvd_decompose computes for it alone.
+ * Inputs stay on the device: X and the outputs are the caller's buffers,
+ * which must stay valid until the request is done. */
+typedef struct rhosvd_server rhosvd_server;
+enum { RHOSVD_REQ_QUEUED = 0, RHOSVD_REQ_RUNNING = 1, RHOSVD_REQ_DONE = 2 };
+
+/* pool: device, 256-byte aligned, pool_bytes (the HBM budget of the
+ * workspaces); 1 <= max_slots <= 64.  Starts the scheduler thread. */
+int32_t rhosvd_server_create(rhosvd_ctx* ctx, int32_t device, void* pool, size_t pool_bytes,
+                             int32_t max_slots, rhosvd_server** server);
+
+/* Queue one decomposition (descriptors are copied; mode_order must be NULL).
+ * Validated at once: EINVAL / EUNSUPPORTED as rhosvd_decompose, ENOMEM when
+ * its workspace exceeds the whole pool.  *ticket identifies it. */
+int32_t rhosvd_server_submit(rhosvd_server* server, const rhosvd_tensor* x,
+                             const rhosvd_params* p, const rhosvd_output* out, uint64_t* ticket);
+
+/* State of a request (RHOSVD_REQ_*); times_ms (optional, 3 doubles): submit,
+ * start and completion times on the host's steady clock (ms).  Returns the
+ * request's status once it is done (RHOSVD_OK before), EINVAL for an
+ * unknown ticket. */
+int32_t rhosvd_server_poll(rhosvd_server* server, uint64_t ticket, int32_t* state,
+                           double* times_ms);
+
+/* Forget a completed request (its ticket becomes unknown). */
+int32_t rhosvd_server_release(rhosvd_server* server, uint64_t ticket);
+
+/* Block until no request is waiting or running. */
+int32_t rhosvd_server_drain(rhosvd_server* server);
+
+/* Finish every queued request, stop the thread, free the streams. */
+void rhosvd_server_destroy(rhosvd_server* server);
+
 /* Relative error E = ||X - Xhat|| / ||X|| (Section 8, eq. Relativeerror)
  * from a host copy of the report: sqrt(resid2 / ||X||^2) when the explicit
  * residual was computed (RHOSVD_FLAG_E_EXPLICIT), else the orthogonal-

@@ -22,6 +22,7 @@ PREC_F64, PREC_F32, PREC_BF16 = 0, 1, 2
 FLAG_K_CAPPED, FLAG_CQR_SHIFTED, FLAG_EVD_NOCONV, FLAG_QR_HOUSEHOLDER = 0x1, 0x2, 0x4, 0x8
 FLAG_E_EXPLICIT = 0x10
 OPT_EXPLICIT_ERROR = 0x1
+REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 OPTION_KERNELS = 1
 KERNELS_AUTO, KERNELS_TILED = 0, 1
 
@@ -70,6 +71,19 @@ _PROTOS = {
                                 ctypes.POINTER(Output), _P]),
     "rhosvd_decompose_noalloc": (_I32, [_P, ctypes.POINTER(Tensor), ctypes.POINTER(Params),
                                         ctypes.POINTER(Output), _P]),
+    "rhosvd_batch_create": (_I32, [_P, _I32, ctypes.POINTER(Tensor), ctypes.POINTER(Params),
+                                   ctypes.POINTER(Output), ctypes.POINTER(_P), ctypes.POINTER(_SZ)]),
+    "rhosvd_batch_bind": (_I32, [_P, _P, _SZ, _I32, _P]),
+    "rhosvd_batch_run": (_I32, [_P, _I32, _P]),
+    "rhosvd_batch_launches": (_I32, [_P]),
+    "rhosvd_batch_destroy": (None, [_P]),
+    "rhosvd_server_create": (_I32, [_P, _I32, _P, _SZ, _I32, ctypes.POINTER(_P)]),
+    "rhosvd_server_submit": (_I32, [_P, ctypes.POINTER(Tensor), ctypes.POINTER(Params),
+                                    ctypes.POINTER(Output), ctypes.POINTER(_U64)]),
+    "rhosvd_server_poll": (_I32, [_P, _U64, ctypes.POINTER(_I32), _DP]),
+    "rhosvd_server_release": (_I32, [_P, _U64]),
+    "rhosvd_server_drain": (_I32, [_P]),
+    "rhosvd_server_destroy": (None, [_P]),
     "rhosvd_report_rel_error": (ctypes.c_double, [ctypes.POINTER(Report)]),
     "rhosvd_omega_fill": (_I32, [_P, _U64, _I32, _I32, _I64, _I32, _I32, _P, _P]),
     "rhosvd_sketch": (_I32, [_P, _P, _I32, _I32, _I64, _I64, _I64, _I32, _U64, _I32, _I32, _P, _P,

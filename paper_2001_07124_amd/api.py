@@ -378,3 +378,147 @@ def sym_evd(c):
     L.check(lib.rhosvd_sym_evd(_context(dev.index or 0), _ptr(cc), K, _ptr(v), _ptr(lam),
                                _ptr(flags), _stream(None, dev)), "rhosvd_sym_evd")
     return v, lam, flags
+
+
+# ---- batched decomposition ----------------------------------------------------
+
+class Batch:
+    """R-STHOSVD of many small tensors, one launch per step for the whole
+    batch, replayed from a HIP graph (rhosvd_batch_*).
+
+    items: list of (x, ranks, p, q, seed, precision) with x a
+    first-index-fastest device tensor; outputs are allocated here."""
+
+    def __init__(self, items, autotune=True, stream=None):
+        self.lib = L.load()
+        if not items:
+            raise ValueError("empty batch")
+        dev = items[0][0].device
+        self.device = dev
+        self.ctx = _context(dev.index or 0)
+        n = len(items)
+        self._keep = []
+        tens = (L.Tensor * n)()
+        prms = (L.Params * n)()
+        outs = (L.Output * n)()
+        self.results = []
+        for i, (x, ranks, p, q, seed, prec) in enumerate(items):
+            dims = _check_fortran(x, None)
+            N = len(dims)
+            dims_c = (ctypes.c_int64 * N)(*dims)
+            ranks_c = (ctypes.c_int32 * N)(*[int(r) for r in ranks])
+            tens[i] = L.Tensor(N, dims_c, _dtype_code(x.dtype), x.data_ptr())
+            prms[i] = L.Params(L.R_STHOSVD, ranks_c, int(p), int(q), int(seed), None,
+                               _prec_code(prec, x.dtype), 0)
+            core = empty_fortran(tuple(int(r) for r in ranks), x.dtype, dev)
+            facs = [empty_colmajor(d, r, x.dtype, dev) for d, r in zip(dims, ranks)]
+            rep = torch.zeros(ctypes.sizeof(L.Report), dtype=torch.uint8, device=dev)
+            fac_c = (ctypes.c_void_p * N)(*[f.data_ptr() for f in facs])
+            outs[i] = L.Output(core.data_ptr(), fac_c, rep.data_ptr())
+            self._keep += [x, dims_c, ranks_c, fac_c]
+            self.results.append(Decomposition(core=core, factors=facs, report_buf=rep, order=N))
+        self._tens, self._prms, self._outs = tens, prms, outs
+        self.handle = ctypes.c_void_p()
+        ws = ctypes.c_size_t(0)
+        L.check(self.lib.rhosvd_batch_create(self.ctx, n, tens, prms, outs,
+                                             ctypes.byref(self.handle), ctypes.byref(ws)),
+                "rhosvd_batch_create")
+        self.ws_bytes = int(ws.value)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        L.check(self.lib.rhosvd_batch_bind(self.handle, ctypes.c_void_p(self.workspace.data_ptr()),
+                                           self.ws_bytes, 1 if autotune else 0,
+                                           _stream(stream, dev)), "rhosvd_batch_bind")
+
+    @property
+    def launches(self):
+        return int(self.lib.rhosvd_batch_launches(self.handle))
+
+    def run(self, stream=None, use_graph=True):
+        L.check(self.lib.rhosvd_batch_run(self.handle, 1 if use_graph else 0,
+                                          _stream(stream, self.device)), "rhosvd_batch_run")
+
+    def close(self):
+        if self.handle:
+            self.lib.rhosvd_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- serving --------------------------------------------------------------------
+
+class Server:
+    """Continuous-batching request loop (rhosvd_server_*): requests queue in
+    arrival order and run on `slots` streams as slots and pool memory free up.
+
+    pool_bytes of device memory are allocated here (torch) and handed to the
+    library as the workspace budget."""
+
+    def __init__(self, pool_bytes, slots=8, device=None):
+        self.lib = L.load()
+        self.device = torch.device(device) if device is not None else torch.device(
+            "cuda", torch.cuda.current_device())
+        idx = self.device.index if self.device.index is not None else 0
+        self.ctx = _context(idx)
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=self.device)
+        self.handle = ctypes.c_void_p()
+        L.check(self.lib.rhosvd_server_create(self.ctx, idx, ctypes.c_void_p(self.pool.data_ptr()),
+                                              int(pool_bytes), int(slots), ctypes.byref(self.handle)),
+                "rhosvd_server_create")
+        self._live = {}
+
+    def submit(self, x, ranks, *, algo="r_sthosvd", p=10, q=1, seed=0, precision=None,
+               explicit_error=False, outputs=None):
+        """Queue a decomposition of the device tensor x; returns (ticket,
+        Decomposition) whose buffers are filled when the ticket is done."""
+        dims = _check_fortran(x, None)
+        N = len(dims)
+        dims_c = (ctypes.c_int64 * N)(*dims)
+        ranks_c = (ctypes.c_int32 * N)(*[int(r) for r in ranks])
+        t = L.Tensor(N, dims_c, _dtype_code(x.dtype), x.data_ptr())
+        algo_code = {"r_sthosvd": L.R_STHOSVD, "rp_hosvd": L.RP_HOSVD}[algo]
+        prm = L.Params(algo_code, ranks_c, int(p), int(q), int(seed), None,
+                       _prec_code(precision, x.dtype), L.OPT_EXPLICIT_ERROR if explicit_error else 0)
+        if outputs is None:
+            core = empty_fortran(tuple(int(r) for r in ranks), x.dtype, self.device)
+            facs = [empty_colmajor(d, r, x.dtype, self.device) for d, r in zip(dims, ranks)]
+            rep = torch.zeros(ctypes.sizeof(L.Report), dtype=torch.uint8, device=self.device)
+            outputs = Decomposition(core=core, factors=facs, report_buf=rep, order=N)
+        fac_c = (ctypes.c_void_p * N)(*[f.data_ptr() for f in outputs.factors])
+        out = L.Output(outputs.core.data_ptr(), fac_c, outputs.report_buf.data_ptr())
+        ticket = ctypes.c_uint64(0)
+        L.check(self.lib.rhosvd_server_submit(self.handle, ctypes.byref(t), ctypes.byref(prm),
+                                              ctypes.byref(out), ctypes.byref(ticket)),
+                "rhosvd_server_submit")
+        self._live[int(ticket.value)] = (x, outputs)
+        return int(ticket.value), outputs
+
+    def poll(self, ticket):
+        """(state, (t_submit, t_start, t_done) in ms); state is L.REQ_*."""
+        st = ctypes.c_int32(0)
+        times = (ctypes.c_double * 3)()
+        L.check(self.lib.rhosvd_server_poll(self.handle, int(ticket), ctypes.byref(st), times),
+                "rhosvd_server_poll")
+        return int(st.value), (times[0], times[1], times[2])
+
+    def release(self, ticket):
+        L.check(self.lib.rhosvd_server_release(self.handle, int(ticket)), "rhosvd_server_release")
+        self._live.pop(int(ticket), None)
+
+    def drain(self):
+        L.check(self.lib.rhosvd_server_drain(self.handle), "rhosvd_server_drain")
+
+    def close(self):
+        if self.handle:
+            self.lib.rhosvd_server_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -27,6 +27,8 @@ SOURCES = {
     "kernels_small.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
     "kernels_resid.hip": [],
     "kernels_allmode.hip": [],
+    "kernels_batch.hip": [],
+    "server.hip": [],
     "noalloc.hip": [],
     "rhosvd_api.hip": [],
 }

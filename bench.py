@@ -55,13 +55,166 @@ def algorithmic_counts(dims, ranks, p, q, elem, order=None):
     return modes
 
 
-def expected_rel_error(dims, ranks, noise, core_norm2):
-    """Closed-form E when the subspaces capture the signal: the noise outside
-    the Tucker subspace over the total norm."""
-    M = float(np.prod(dims))
-    frac = 1.0 - float(np.prod([r / i for r, i in zip(ranks, dims)]))
-    n2 = noise ** 2 * M
-    return math.sqrt(n2 * frac / (core_norm2 + n2))
+GOLDEN = {"r_sthosvd_200x4_r25": os.path.join(ROOT, "tests", "golden", "r_sthosvd_200x4_r25_oracle.npz")}
+
+
+def oracle_rel_error(workload):
+    """E of the FP64 oracle on the full workload, from the stored oracle run
+    (tests/golden), or None when there is none for this workload."""
+    path = GOLDEN.get(workload)
+    if not path or not os.path.exists(path):
+        return None
+    return float(np.load(path, allow_pickle=False)["rel_error"])
+
+
+def bench_batched(dev, steps, seed=1, count=512):
+    """512 order-3 FP32 tensors (extents 32..256, exact ranks 4..32, noise
+    1e-4; R-STHOSVD at the true ranks, p = 5, q = 1): one graph launch per
+    batch, against the same tensors decomposed by 512 sequential calls."""
+    import torch
+    from paper_2001_07124_amd import api
+    from paper_2001_07124_amd.inputs import batch_specs, batch_tensors
+    specs = batch_specs(count=count, seed=seed)
+    t0 = time.perf_counter()
+    xs = batch_tensors(specs, seed=seed, noise=1e-4, dtype=np.float32)
+    xds = [api.to_device(x, dev) for x in xs]
+    torch.cuda.synchronize()
+    nbytes = float(sum(x.nbytes for x in xs))
+    log(f"[bench] batch: {count} tensors, {nbytes / 1e9:.2f} GB, generated in {time.perf_counter() - t0:.1f}s")
+    items = [(xd, r, 5, 1, i, "f32") for i, (xd, (d, r)) in enumerate(zip(xds, specs))]
+    s = torch.cuda.Stream(dev)
+    t0 = time.perf_counter()
+    b = api.Batch(items, autotune=True, stream=s)
+    t_plan = time.perf_counter() - t0
+    with torch.cuda.stream(s):
+        b.run(stream=s)                      # captures the graph
+        b.run(stream=s)
+    s.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(s):
+        e0.record(s)
+        for _ in range(steps):
+            b.run(stream=s)
+        e1.record(s)
+    s.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    errs = [r.rel_error for r in b.results]
+    # the same work as independent single decompositions, one after another
+    decs = [api.Decomposer(d, r, p=5, q=1, seed=i, dtype=torch.float32, precision="f32", device=dev)
+            for i, (d, r) in enumerate(specs)]
+    for dec, xd in zip(decs, xds):
+        dec.run(xd, stream=s)
+    s.synchronize()
+    e0.record(s)
+    for dec, xd in zip(decs, xds):
+        dec.run(xd, stream=s)
+    e1.record(s)
+    s.synchronize()
+    ms_seq = e0.elapsed_time(e1)
+    log(f"[bench] batch: {ms:.3f} ms per batch ({b.launches} launches, one graph), "
+        f"sequential {ms_seq:.3f} ms")
+    out = {"workload": f"batch_{count}_order3_32to256_r4to32", "tensors": count,
+           "tensor_GB": round(nbytes / 1e9, 3), "ms_per_batch": round(ms, 3),
+           "value": round(nbytes / (ms * 1e-3) / 1e9, 2), "unit": "GB/s",
+           "launches_per_batch": b.launches, "graph": True,
+           "sequential_ms": round(ms_seq, 3), "speedup_vs_sequential": round(ms_seq / ms, 2),
+           "rel_error_median": float(np.median(errs)), "rel_error_max": float(np.max(errs)),
+           "plan_and_tune_s": round(t_plan, 2)}
+    b.close()
+    return out
+
+
+# The streaming kernels keep a mode's I x K accumulators in registers: modes
+# of up to 256 rows take K <= 64, up to 512 rows K <= 32.  The serving mix is
+# drawn within those limits (extents up to 512 instead of 1024).
+MAX_SERVE_EXTENT = 512
+
+
+def serve_rank_cap(extent, p=10):
+    return (64 if extent <= 256 else 32) - p
+
+
+def serve_requests(count, seed=3, pool_tensors=24):
+    """Request mix of the serving workload: order 3 or 4, total size
+    log-uniform in [64^3, 1024 x 1024 x 256], extents around size^(1/N) with
+    a seeded jitter, clamped to [16, 512]; ranks uniform in 8..64 capped at
+    the extent and at 54 (so that K = R + 10 stays within the 64-column
+    limit, and by serve_rank_cap for taller modes); p = 10, q in {0, 1},
+    FP32 or BF16 path.  The tensors themselves
+    come from a pool of `pool_tensors` shapes drawn the same way."""
+    rng = np.random.default_rng([seed, 3])
+    shapes = []
+    for _ in range(pool_tensors):
+        N = int(rng.integers(3, 5))
+        size = float(np.exp(rng.uniform(np.log(64.0 ** 3), np.log(1024.0 * 1024 * 256))))
+        base = size ** (1.0 / N)
+        dims = [int(np.clip(round(base * np.exp(rng.uniform(-0.3, 0.3))), 16, MAX_SERVE_EXTENT))
+                for _ in range(N)]
+        shapes.append(tuple(dims))
+    reqs = []
+    for i in range(count):
+        k = int(rng.integers(0, pool_tensors))
+        dims = shapes[k]
+        ranks = tuple(int(min(rng.integers(8, 65), d, serve_rank_cap(d))) for d in dims)
+        reqs.append(dict(tensor=k, ranks=ranks, q=int(rng.integers(0, 2)),
+                         prec=("bf16" if rng.integers(0, 2) else "f32"), seed=i,
+                         gap=float(rng.exponential(1.0))))
+    return shapes, reqs
+
+
+def bench_serving(dev, rate=200.0, duration_s=2.0, slots=8, pool_gb=24.0):
+    """Poisson arrivals at `rate` requests/s for `duration_s`, every request a
+    decomposition of a tensor already in HBM; p50/p99 latency (completion -
+    arrival) and completed requests/s; then the same requests all at once
+    (saturation throughput)."""
+    import torch
+    from paper_2001_07124_amd import api
+    from paper_2001_07124_amd.inputs import tucker_tensor
+    count = int(rate * duration_s)
+    shapes, reqs = serve_requests(count)
+    t0 = time.perf_counter()
+    xds = []
+    for k, dims in enumerate(shapes):
+        r0 = tuple(min(16, d) for d in dims)
+        xds.append(api.to_device(tucker_tensor(dims, r0, seed=500 + k, noise=1e-3,
+                                               dtype=np.float32)[0], dev))
+    torch.cuda.synchronize()
+    log(f"[bench] serving: {len(shapes)} tensors ({sum(x.numel() for x in xds) * 4 / 1e9:.2f} GB) "
+        f"in {time.perf_counter() - t0:.1f}s, {count} requests at {rate:.0f}/s")
+    srv = api.Server(pool_bytes=int(pool_gb * (1 << 30)), slots=slots, device=dev)
+
+    def run(gap_scale):
+        tickets = []
+        t_start = time.perf_counter()
+        t_next = t_start
+        for r in reqs:
+            t_next += r["gap"] * gap_scale
+            while time.perf_counter() < t_next:
+                pass
+            tickets.append(srv.submit(xds[r["tensor"]], r["ranks"], p=10, q=r["q"], seed=r["seed"],
+                                      precision=r["prec"])[0])
+        srv.drain()
+        wall = time.perf_counter() - t_start
+        lat = []
+        for t in tickets:
+            st, (ts, tb, te) = srv.poll(t)
+            lat.append(te - ts)
+            srv.release(t)
+        return np.array(lat), wall
+
+    run(0.0)                                   # warm-up: every shape once
+    lat, wall = run(1.0 / rate)
+    lat_sat, wall_sat = run(0.0)
+    srv.close()
+    log(f"[bench] serving: p50 {np.percentile(lat, 50):.2f} ms, p99 {np.percentile(lat, 99):.2f} ms, "
+        f"{count / wall:.1f} req/s; saturation {count / wall_sat:.1f} req/s")
+    return {"workload": "serve_order3_4_64cubed_to_1024x1024x256", "rate_req_s": rate,
+            "requests": count, "slots": slots,
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "req_per_s": round(count / wall, 1),
+            "saturation_req_per_s": round(count / wall_sat, 1),
+            "saturation_p50_ms": round(float(np.percentile(lat_sat, 50)), 3)}
 
 
 def cpu_baseline(x, w):
@@ -129,6 +282,8 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=5)
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP32 comparison path")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-tensor batched line")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also copy 1 GiB device to device (counter calibration)")
     args = ap.parse_args()
@@ -244,8 +399,7 @@ def main():
         "config": {"workload": args.workload, "dims": list(dims), "ranks": list(ranks),
                    "p": w["p"], "q": w["q"], "precision": prec, "algo": w["algo"]},
         "rel_error": e_gpu,
-        "rel_error_expected": expected_rel_error(dims, w["ranks"], w["noise"],
-                                                 float(np.sum(core ** 2))),
+        "rel_error_oracle": oracle_rel_error(args.workload),
         "path": {"algorithmic_bytes": alg_bytes, "algorithmic_flops": alg_flops,
                  "algorithmic_GBps": round(alg_bytes / (ms * 1e-3) / 1e9, 1),
                  "hbm_roofline_ms": round(path_roof_ms, 4),
@@ -255,6 +409,12 @@ def main():
         "compare_path": compare,
         "wall_s_timed": round(t_wall, 3),
     }
+    if not args.no_batch:
+        log("[bench] batched workload")
+        out["batched"] = bench_batched(dev, max(3, args.steps // 2))
+    if not args.no_serve:
+        log("[bench] serving workload")
+        out["serving"] = bench_serving(dev)
     if args.copy_probe:
         copy_probe(dev)
     if not args.no_cpu_baseline:

@@ -73,11 +73,23 @@ typedef enum {
 #define RHOSVD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 
 enum { RHOSVD_F32 = 0, RHOSVD_F64 = 1 };                     /* tensor dtypes */
-enum { RHOSVD_RP_HOSVD = 0, RHOSVD_R_STHOSVD = 1 };          /* algorithms */
+/* Algorithms: RP-HOSVD (Algorithm 6), R-STHOSVD (Algorithm 8 with Algorithm
+ * 1 per mode) and RP-HOOI (Algorithm 7: Q_n from the orthonormalised
+ * Gaussian start (Omega stream tag 5, mode n, I_n x R_n), then
+ * params.power_iters sweeps of S = X x_{p != n} Q_p^T, W = S_(n) Omega
+ * (tag 6, counter mode word s N + n), Q_n = QR(W); oversample must be 0;
+ * the core X x_n Q_n^T with canonical factor signs). */
+enum { RHOSVD_RP_HOSVD = 0, RHOSVD_R_STHOSVD = 1, RHOSVD_RP_HOOI = 2 };
 /* Precision of the streaming contractions (inputs of the matrix cores);
  * accumulation is FP32 (FP64 for RHOSVD_PREC_F64); Gram matrices, Cholesky
- * and eigen-decompositions are always FP64. */
-enum { RHOSVD_PREC_F64 = 0, RHOSVD_PREC_F32 = 1, RHOSVD_PREC_BF16 = 2 };
+ * and eigen-decompositions are always FP64.
+ *   RHOSVD_PREC_BF16     sketch on bf16 inputs; power step, projection and
+ *                        truncation on split (hi + lo) bf16 operands
+ *   RHOSVD_PREC_FP8E4M3  the same, with the sketch of contiguous unfoldings
+ *                        on OCP e4m3 inputs (each 32-column block scaled by a
+ *                        power of two; strided unfoldings sketch in bf16);
+ *                        the split-bf16 power step wins the accuracy back */
+enum { RHOSVD_PREC_F64 = 0, RHOSVD_PREC_F32 = 1, RHOSVD_PREC_BF16 = 2, RHOSVD_PREC_FP8E4M3 = 3 };
 
 /* report.flags bits (warnings, set on the device) */
 #define RHOSVD_FLAG_K_CAPPED     0x1u  /* some K_n < R_n + p (capped by I_n or J_n) */
@@ -120,7 +132,7 @@ typedef struct {
     int32_t algo;             /* RHOSVD_RP_HOSVD or RHOSVD_R_STHOSVD */
     const int32_t* ranks;     /* host, N target ranks, 1 <= R_n <= I_n */
     int32_t oversample;       /* p >= 0; K_n = min(R_n + p, I_n, J_n) */
-    int32_t power_iters;      /* q, 0..8 */
+    int32_t power_iters;      /* q, 0..8 (RP-HOOI: the number of sweeps) */
     uint64_t seed;            /* Omega key */
     const int32_t* mode_order;/* host permutation of 0..N-1 or NULL (ascending); R-STHOSVD only */
     int32_t precision;        /* RHOSVD_PREC_*; F64 requires F64 data */

@@ -116,7 +116,8 @@ def _hooi_init(x, ranks, seed):
 def rp_hooi(x, ranks, sweeps, seed):
     """Algorithm 7: for each sweep and mode n, S = X x_{p != n} Q_p^T,
     W = S_(n) Omega (Omega: prod_{p != n} R_p x R_n Gaussian), Q_n = QR(W);
-    the core is X x_1 Q_1^T ... x_N Q_N^T at the end."""
+    the core is X x_1 Q_1^T ... x_N Q_N^T at the end (factor signs then
+    made canonical, the core carrying them)."""
     x = np.asarray(x, dtype=np.float64)
     N = x.ndim
     for d, r in zip(x.shape, ranks):
@@ -134,8 +135,15 @@ def rp_hooi(x, ranks, sweeps, seed):
     core = x
     for n in range(N):
         core = ttm(core, qs[n].T, n)
+    # as for the other algorithms: each factor's signs canonical, the core
+    # carrying them; sigma from the core's unfoldings
     sigma = [np.linalg.svd(unfold(core, n), compute_uv=False)[:ranks[n]] for n in range(N)]
-    return _finish(x, core, qs, sigma, list(ranks))
+    factors = []
+    for n in range(N):
+        sg = canonical_signs(qs[n])
+        factors.append(qs[n] * sg)
+        core = ttm(core, np.diag(sg), n)
+    return _finish(x, core, factors, sigma, list(ranks))
 
 
 def r_pet(x, ranks, p, seed):

@@ -17,8 +17,8 @@ MAX_K = 128
 OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EBUSY, EUNSUPPORTED, ESCRATCH = range(8)
 NOALLOC_SCRATCH_BYTES = 64 << 20
 F32, F64 = 0, 1
-RP_HOSVD, R_STHOSVD = 0, 1
-PREC_F64, PREC_F32, PREC_BF16 = 0, 1, 2
+RP_HOSVD, R_STHOSVD, RP_HOOI = 0, 1, 2
+PREC_F64, PREC_F32, PREC_BF16, PREC_FP8 = 0, 1, 2, 3
 FLAG_K_CAPPED, FLAG_CQR_SHIFTED, FLAG_EVD_NOCONV, FLAG_QR_HOUSEHOLDER = 0x1, 0x2, 0x4, 0x8
 FLAG_E_EXPLICIT = 0x10
 OPT_EXPLICIT_ERROR = 0x1

@@ -53,7 +53,7 @@ def _dtype_code(dt):
     raise TypeError("tensor dtype must be float32 or float64")
 
 
-_PREC = {"f64": L.PREC_F64, "f32": L.PREC_F32, "bf16": L.PREC_BF16}
+_PREC = {"f64": L.PREC_F64, "f32": L.PREC_F32, "bf16": L.PREC_BF16, "fp8": L.PREC_FP8}
 
 
 def _prec_code(precision, dt):
@@ -191,7 +191,7 @@ class Decomposer:
         self._ranks_c = (ctypes.c_int32 * self.N)(*self.ranks)
         self._order_c = None if mode_order is None else (ctypes.c_int32 * self.N)(*mode_order)
         self.tensor = L.Tensor(self.N, self._dims_c, _dtype_code(dtype), None)
-        algo_code = {"r_sthosvd": L.R_STHOSVD, "rp_hosvd": L.RP_HOSVD}[algo]
+        algo_code = {"r_sthosvd": L.R_STHOSVD, "rp_hosvd": L.RP_HOSVD, "rp_hooi": L.RP_HOOI}[algo]
         flags = L.OPT_EXPLICIT_ERROR if explicit_error else 0
         self.params = L.Params(algo_code, self._ranks_c, int(p), int(q), int(seed),
                                self._order_c, _prec_code(precision, dtype), flags)
@@ -256,6 +256,11 @@ def r_sthosvd(x, ranks, p=10, q=1, seed=0, **kw):
 def rp_hosvd(x, ranks, p=10, q=0, seed=0, **kw):
     """RP-HOSVD (Algorithm 6; the K-sized core is truncated by a small THOSVD)."""
     return decompose(x, ranks, algo="rp_hosvd", p=p, q=q, seed=seed, **kw)
+
+
+def rp_hooi(x, ranks, sweeps=2, seed=0, **kw):
+    """RP-HOOI (Algorithm 7) with `sweeps` sweeps from a Gaussian start."""
+    return decompose(x, ranks, algo="rp_hooi", p=0, q=sweeps, seed=seed, **kw)
 
 
 # ---- step-level calls (one hot-path step each) -------------------------------

@@ -59,7 +59,7 @@ hipError_t launch_stream_batch(int op, bool dbl, const StreamJob* jobs, int njob
                                size_t lds, hipStream_t s);
 
 // Matrix-core input precision of the wave-private FP32 kernels.
-enum CompType { CT_F32 = 0, CT_BF16 = 1, CT_BF16X3 = 2, CT_BF16X2 = 3 };
+enum CompType { CT_F32 = 0, CT_BF16 = 1, CT_BF16X3 = 2, CT_BF16X2 = 3, CT_FP8 = 4 };
 
 // Geometry of a wave-private pass (kernels_wave.hip): each wave owns blocks
 // of 16 unfolding columns; IB = ceil(I / 16) row blocks, NB = ceil(K / 16)
@@ -84,6 +84,7 @@ struct ColGeom {
     int64_t I, J;
     int K, nch, nb, variant, rowp;
     int split;            // the tensor split into hi + lo bf16 in Z = S^T M (CT_BF16X3)
+    int fp8;              // the sketch on e4m3 inputs (CT_FP8)
     int red3;             // LDS holds three waves' Y accumulators for the final reduction
     size_t mfr_bytes, lds_bytes;
     int64_t nblocks;

@@ -28,6 +28,15 @@
 // 1e-4.  The power step's Y += S Z takes the rounded tensor against split Z.
 // The Gram Z^T Z takes hi*hi + hi*lo + lo*hi.  Accumulation is FP32.
 //
+// FP8 sketch (VAR in the sketch): the block and Omega enter the
+// v_mfma_f32_16x16x32_fp8_fp8 matrix cores as OCP e4m3 (3 mantissa bits).
+// Each 32-column block is scaled by a power of two s that brings its largest
+// magnitude into [128, 256) (exact), the accumulators are multiplied by s
+// before the block's products and by 1/s after (both exact), so Y is the
+// unscaled sum; Omega (|z| < 6) needs no scale.  The bf16 tile of the block
+// holds one fp8 code per 16-bit slot so that the same transposing LDS read
+// serves both precisions.
+//
 // Outputs of the mode-n product are written with non-temporal stores: they
 // are read back only by the next pass, after far more traffic than the
 // caches hold, and streaming them past the caches costs the reads less.
@@ -94,6 +103,41 @@ __device__ __forceinline__ bf16x8 cat_bf(s16x4 a, s16x4 b) {
     v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
     v[4] = b[0]; v[5] = b[1]; v[6] = b[2]; v[7] = b[3];
     return __builtin_bit_cast(bf16x8, v);
+}
+
+__device__ __forceinline__ f32x4 mma32_fp8(long a, long b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+}
+
+// Eight floats as e4m3 codes, in order, packed into 64 bits.
+__device__ __forceinline__ long to_fp8x8(f32x4 a, f32x4 b) {
+    int lo = __builtin_amdgcn_cvt_pk_fp8_f32(a[0], a[1], 0, false);
+    lo = __builtin_amdgcn_cvt_pk_fp8_f32(a[2], a[3], lo, true);
+    int hi = __builtin_amdgcn_cvt_pk_fp8_f32(b[0], b[1], 0, false);
+    hi = __builtin_amdgcn_cvt_pk_fp8_f32(b[2], b[3], hi, true);
+    return static_cast<long>((static_cast<unsigned long>(static_cast<unsigned>(hi)) << 32) |
+                             static_cast<unsigned>(lo));
+}
+
+// Eight floats scaled by s as e4m3 codes, one per 16-bit slot (low byte).
+__device__ __forceinline__ bf16x8 to_fp8_slots(f32x4 a, f32x4 b, float s) {
+    const long c = to_fp8x8(a * s, b * s);
+    s16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = static_cast<short>((c >> (8 * e)) & 0xff);
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+// The low bytes of the eight 16-bit slots of a transposed tile read (the
+// same k order as cat_bf).
+__device__ __forceinline__ long cat_fp8(s16x4 a, s16x4 b) {
+    unsigned long v = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        v |= static_cast<unsigned long>(static_cast<unsigned short>(a[e]) & 0xff) << (8 * e);
+        v |= static_cast<unsigned long>(static_cast<unsigned short>(b[e]) & 0xff) << (8 * (e + 4));
+    }
+    return static_cast<long>(v);
 }
 
 // One 64-bit product a * b of 32-bit words as a single v_mad_u64_u32 (the
@@ -174,10 +218,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const float* src, i
 }
 
 // FLAG: the sum of squares (sketch) or the Gram Z^T Z (mode-n product).
-// SPLIT: the tensor also enters Z = S^T M split (hi*lo + lo*hi + hi*hi)
-// instead of rounded (hi*lo + hi*hi).
-template <int OP, int NCH, int NB, bool FLAG, bool SPLIT>
+// VAR: in the power step and the mode-n product (SPLIT), the tensor also
+// enters Z = S^T M split (hi*lo + lo*hi + hi*hi) instead of rounded (hi*lo +
+// hi*hi); in the sketch (FP8), e4m3 inputs instead of bf16.
+template <int OP, int NCH, int NB, bool FLAG, bool VAR>
 __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a) {
+    constexpr bool SPLIT = VAR && OP != OP_SKETCH;
+    constexpr bool FP8 = VAR && OP == OP_SKETCH;
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int RT = 2 * NCH;                 // 16-row tiles of Y
     constexpr bool SS = (OP == OP_SKETCH) && FLAG;
@@ -308,6 +355,27 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
             }
         }
 
+        // FP8: the power-of-two scale of the block (largest magnitude to [128, 256))
+        float fscale = 1.0f, finv = 1.0f;
+        if constexpr (FP8) {
+            float mx = 0.0f;
+#pragma unroll
+            for (int h = 0; h < NCH; ++h)
+#pragma unroll
+                for (int h2 = 0; h2 < 2; ++h2)
+#pragma unroll
+                    for (int q = 0; q < 2; ++q)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) mx = fmaxf(mx, fabsf(Fb[h][h2][q][e]));
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, kWave));
+            if (mx > 0.0f) {
+                int ex = 8 - __builtin_amdgcn_frexp_expf(mx);
+                ex = ex > 64 ? 64 : ex;
+                fscale = __builtin_amdgcn_ldexpf(1.0f, ex);
+                finv = __builtin_amdgcn_ldexpf(1.0f, -ex);
+            }
+        }
         // chunk by chunk: round to bf16, stage for the transpose, refill the
         // chunk's registers with the block 2 nw ahead, and Z = S^T M
 #pragma unroll
@@ -335,9 +403,12 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
                 }
             }
             bf16x8 D0, D1, L0, L1;
-            if (SPLIT && OP != OP_SKETCH) {
+            if constexpr (SPLIT) {
                 split8(Fb[h][0][0], Fb[h][0][1], D0, L0);
                 split8(Fb[h][1][0], Fb[h][1][1], D1, L1);
+            } else if constexpr (FP8) {
+                D0 = to_fp8_slots(Fb[h][0][0], Fb[h][0][1], fscale);
+                D1 = to_fp8_slots(Fb[h][1][0], Fb[h][1][1], fscale);
             } else {
                 D0 = to_bf16x8(Fb[h][0][0], Fb[h][0][1]);
                 D1 = to_bf16x8(Fb[h][1][0], Fb[h][1][1]);
@@ -394,7 +465,22 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
         if (SS) ss += static_cast<double>(part);
 
         // ---- Y += S_blk W, W = Omega (sketch) or Z (power step)
-        if (OP != OP_TTM) {
+        if constexpr (FP8) {
+            long W8[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const uint64_t e0 = eb[nb] + static_cast<uint64_t>(j0);
+                W8[nb] = to_fp8x8(omega4_w(e0, a.mode, a.tag, a.seed, jal),
+                                  omega4_w(e0 + 16, a.mode, a.tag, a.seed, jal));
+            }
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                const long A8 = cat_fp8(tile_tr(tile, rowp, 0, rt, lane), tile_tr(tile, rowp, 1, rt, lane));
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[rt][nb] = mma32_fp8(A8, W8[nb], acc[rt][nb] * fscale) * finv;
+            }
+        } else if (OP != OP_TTM) {
             bf16x8 Whi[NB], Wlo[NB];
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
@@ -584,8 +670,10 @@ constexpr int kNumColShapes = 8;
 
 bool plan_col(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu, ColGeom* g) {
     if (L != 1 || I < 1 || I > 256 || T < 1 || K < 1 || K > 64) return false;
-    if (op == OP_SKETCH ? ct != CT_BF16 : (ct != CT_BF16X2 && ct != CT_BF16X3)) return false;
+    if (op == OP_SKETCH ? (ct != CT_BF16 && ct != CT_FP8) : (ct != CT_BF16X2 && ct != CT_BF16X3))
+        return false;
     g->split = (op != OP_SKETCH && ct == CT_BF16X3) ? 1 : 0;
+    g->fp8 = (op == OP_SKETCH && ct == CT_FP8) ? 1 : 0;
     const int nch = static_cast<int>((I + 31) / 32), nb = (K + 15) / 16;
     int var = -1, best = 1 << 30;
     for (int v = 0; v < kNumColShapes; ++v) {
@@ -635,14 +723,14 @@ bool plan_col(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu
     return true;
 }
 
-template <int OP, int NCH, int NB, bool SPLIT>
+template <int OP, int NCH, int NB, bool VAR>
 static hipError_t launch_col_s(const ColGeom& g, const StreamArgs& a, hipStream_t s) {
     const bool flag = (OP == OP_SKETCH) ? a.part_ss != nullptr : (OP == OP_TTM && a.part_g != nullptr);
     if (flag)
-        hipLaunchKernelGGL((k_col<OP, NCH, NB, true, SPLIT>), dim3(g.grid), dim3(kColThreads),
+        hipLaunchKernelGGL((k_col<OP, NCH, NB, true, VAR>), dim3(g.grid), dim3(kColThreads),
                            g.lds_bytes, s, g, a);
     else
-        hipLaunchKernelGGL((k_col<OP, NCH, NB, false, SPLIT>), dim3(g.grid), dim3(kColThreads),
+        hipLaunchKernelGGL((k_col<OP, NCH, NB, false, VAR>), dim3(g.grid), dim3(kColThreads),
                            g.lds_bytes, s, g, a);
     return hipGetLastError();
 }
@@ -651,6 +739,8 @@ template <int OP, int NCH, int NB>
 static hipError_t launch_col_t(const ColGeom& g, const StreamArgs& a, hipStream_t s) {
     if constexpr (OP != OP_SKETCH) {
         if (g.split) return launch_col_s<OP, NCH, NB, true>(g, a, s);
+    } else {
+        if (g.fp8) return launch_col_s<OP, NCH, NB, true>(g, a, s);
     }
     return launch_col_s<OP, NCH, NB, false>(g, a, s);
 }

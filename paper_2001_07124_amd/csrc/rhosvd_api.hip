@@ -57,6 +57,8 @@ struct Carver {
 
 constexpr int kMaxSmallK = 64;    // the QR and EVD kernels keep K x K in LDS / registers
 constexpr int kSumsqBlocks = 256;
+// Omega streams of RP-HOOI (Algorithm 7): the Gaussian start and the sketches
+constexpr uint32_t kTagHooiInit = 5, kTagHooiSketch = 6;
 // The single-pass sketch of all modes regenerates Omega rows per tile: it is
 // used while that costs at most this many normals per element of X (beyond
 // it the per-mode passes, which generate each row once, are faster).
@@ -95,6 +97,8 @@ bool plan_pass(int op, bool dbl, int ct, int64_t L, int64_t I, int64_t T, int K,
         p->K_pad = p->cg.K_pad;
         return true;
     }
+    // the e4m3 sketch exists in the column kernel only; elsewhere bf16
+    if (ct == rh::CT_FP8) ct = rh::CT_BF16;
     if (!dbl && any && rh::plan_wave(op, ct, L, I, T, K, num_cu, &p->wg)) {
         p->kind = PASS_WAVE;
         p->grid = p->wg.grid;
@@ -152,6 +156,10 @@ struct Plan {
     // takes the shape and its Omega work stays small (see plan_allmode_use)
     bool use_allmode = false;
     rh::AllModeArgs am{};
+    // RP-HOOI: per mode n the chain X x_{p != n} Q_p^T (one mode-n product
+    // per p != n, natural order) and the sketch of its n-unfolding
+    Pass hchain[RHOSVD_MAX_ORDER][RHOSVD_MAX_ORDER];
+    Pass hsk[RHOSVD_MAX_ORDER];
     // R-STHOSVD in the natural mode order keeps the current tensor with its
     // next mode first: (I_n, ..., I_N, R_1, ..., R_{n-1}).  Every unfolding is
     // then contiguous (L = 1), its columns are in the cyclic order that
@@ -177,7 +185,9 @@ int32_t validate(const rhosvd_tensor* x, const rhosvd_params* p, Problem* pr, bo
     if (x->order < 2 || x->order > RHOSVD_MAX_ORDER || !x->dims) return RHOSVD_EINVAL;
     if (x->dtype != RHOSVD_F32 && x->dtype != RHOSVD_F64) return RHOSVD_EINVAL;
     if (need_data && !x->data) return RHOSVD_EINVAL;
-    if (p->algo != RHOSVD_RP_HOSVD && p->algo != RHOSVD_R_STHOSVD) return RHOSVD_EINVAL;
+    if (p->algo != RHOSVD_RP_HOSVD && p->algo != RHOSVD_R_STHOSVD && p->algo != RHOSVD_RP_HOOI)
+        return RHOSVD_EINVAL;
+    if (p->algo == RHOSVD_RP_HOOI && p->oversample != 0) return RHOSVD_EINVAL;
     if (!p->ranks || p->oversample < 0 || p->power_iters < 0 || p->power_iters > 8)
         return RHOSVD_EINVAL;
     if ((p->flags & ~static_cast<uint32_t>(RHOSVD_OPT_EXPLICIT_ERROR)) != 0) return RHOSVD_EINVAL;
@@ -215,9 +225,9 @@ int32_t validate(const rhosvd_tensor* x, const rhosvd_params* p, Problem* pr, bo
         if (!pr->dbl) return RHOSVD_EINVAL;
     } else if (p->precision == RHOSVD_PREC_F32) {
         if (pr->dbl) return RHOSVD_EINVAL;
-    } else if (p->precision == RHOSVD_PREC_BF16) {
+    } else if (p->precision == RHOSVD_PREC_BF16 || p->precision == RHOSVD_PREC_FP8E4M3) {
         if (pr->dbl) return RHOSVD_EINVAL;
-        pr->ct_sketch = rh::CT_BF16;
+        pr->ct_sketch = p->precision == RHOSVD_PREC_BF16 ? rh::CT_BF16 : rh::CT_FP8;
         pr->ct_power = rh::CT_BF16X3;
         pr->ct_ttm = rh::CT_BF16X3;
         pr->ct_trunc = rh::CT_BF16X3;
@@ -340,7 +350,30 @@ int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
         pl->qstore += IK;
         pl->mstore += static_cast<int64_t>(st.K) * st.R;
     }
-    {
+    if (pr.algo == RHOSVD_RP_HOOI) {
+        // chains X x_{p != n} Q_p^T and the sketches of their n-unfoldings
+        for (int n = 0; n < N; ++n) {
+            int64_t e[RHOSVD_MAX_ORDER];
+            for (int m = 0; m < N; ++m) e[m] = d[m];
+            for (int q = 0; q < N; ++q) {
+                if (q == n) continue;
+                if (!plan_pass(rh::OP_TTM, pr.dbl, pr.ct_ttm, prod(e, 0, q), e[q], prod(e, q + 1, N),
+                               pr.ranks[q], num_cu, &pl->hchain[n][q], pr.kernels))
+                    return RHOSVD_EUNSUPPORTED;
+                track_stream(pl, pl->hchain[n][q], false);
+                e[q] = pr.ranks[q];
+                const int64_t sz = prod(e, 0, N);
+                if (sz > pl->ping) pl->ping = sz;
+                if (sz > pl->pong) pl->pong = sz;
+            }
+            const int64_t Ln = prod(e, 0, n), Tn = prod(e, n + 1, N);
+            if (pr.ranks[n] > Ln * Tn) return RHOSVD_EINVAL;
+            if (!plan_pass(rh::OP_SKETCH, pr.dbl, pr.ct_sketch, Ln, e[n], Tn, pr.ranks[n], num_cu,
+                           &pl->hsk[n], pr.kernels))
+                return RHOSVD_EUNSUPPORTED;
+            track_stream(pl, pl->hsk[n], false);
+        }
+    } else {
         int Ks[RHOSVD_MAX_ORDER];
         for (int n = 0; n < N; ++n) Ks[n] = pl->st[n].K;
         if (pr.kernels == RHOSVD_KERNELS_AUTO &&
@@ -383,7 +416,8 @@ int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
         const int64_t sz = prod(d, 0, N);
         if (sz > buf) buf = sz;
     }
-    pl->ping = pl->pong = buf;
+    pl->ping = std::max(pl->ping, buf);
+    pl->pong = std::max(pl->pong, buf);
     pl->core_elems = prod(d, 0, N);
     size_resid(pl);
     return RHOSVD_OK;
@@ -533,7 +567,47 @@ int32_t run_rp_hosvd(const Plan& pl, const Buffers& b, const void* x, const rhos
         qo += pl.st[n].I * pl.st[n].K;
         mo += static_cast<int64_t>(pl.st[n].K) * pl.st[n].R;
     }
-    if (pl.use_allmode) {
+    if (pl.pr.algo == RHOSVD_RP_HOOI) {
+        // Algorithm 7: ||X||^2, the orthonormalised Gaussian start, then per
+        // sweep s and mode n: S = X x_{p != n} Q_p^T, W = S_(n) Omega (the
+        // stream of mode word s N + n), Q_n = QR(W)
+        RH_HIP(rh::launch_sumsq(dbl, x, prod(pl.pr.dims, 0, N), b.part_ss, kSumsqBlocks, s));
+        RH_HIP(rh::launch_reduce_ss(b.part_ss, kSumsqBlocks, &b.rep->norm_x2, s));
+        for (int n = 0; n < N; ++n) {
+            const Step& st = pl.st[n];
+            RH_HIP(rh::launch_omega_fill(true, pl.pr.seed, n, kTagHooiInit, st.I, st.K, b.y, s));
+            RH_HIP(rh::launch_cqr(b.y, st.I, st.K, dbl, at(b.qstore, qoff[n], e), b.q64,
+                                  &b.rep->flags, s));
+        }
+        void* hb[2] = {b.ping, b.pong};
+        for (int sw = 0; sw < pl.pr.q; ++sw) {
+            for (int n = 0; n < N; ++n) {
+                const void* cur = x;
+                int k = 0;
+                for (int q = 0; q < N; ++q) {
+                    if (q == n) continue;
+                    const int32_t rc = ttm(pl, pl.hchain[n][q], cur, at(b.qstore, qoff[q], e), hb[k & 1],
+                                           nullptr, s);
+                    if (rc != RHOSVD_OK) return rc;
+                    cur = hb[k & 1];
+                    ++k;
+                }
+                const Step& st = pl.st[n];
+                const Pass& gs = pl.hsk[n];
+                rh::StreamArgs a{};
+                a.src = cur;
+                a.part_y = b.part;
+                a.seed = pl.pr.seed;
+                a.mode = static_cast<uint32_t>(sw * N + n);
+                a.tag = kTagHooiSketch;
+                RH_HIP(launch_pass(gs, a, s));
+                RH_HIP(rh::launch_reduce_y(dbl, b.part, gs.grid, static_cast<int>(gs.I), gs.K,
+                                           gs.I_pad, gs.K_pad, b.y, s));
+                RH_HIP(rh::launch_cqr(b.y, st.I, st.K, dbl, at(b.qstore, qoff[n], e), b.q64,
+                                      &b.rep->flags, s));
+            }
+        }
+    } else if (pl.use_allmode) {
         // every Y_n from one read of X, then per mode the QR and power steps
         rh::AllModeArgs am = pl.am;
         am.x = x;
@@ -660,7 +734,7 @@ int32_t decompose_on(rhosvd_ctx* ctx, const rhosvd_tensor* x, const rhosvd_param
     if (he != hipSuccess) rc = hip_fail(he);
     if (rc == RHOSVD_OK)
         rc = (pr.algo == RHOSVD_R_STHOSVD) ? run_r_sthosvd(*pl, b, x->data, out, s)
-                                            : run_rp_hosvd(*pl, b, x->data, out, s);
+                                            : run_rp_hosvd(*pl, b, x->data, out, s);   // RP-HOSVD, RP-HOOI
     if (rc == RHOSVD_OK) {
         he = rh::launch_sumsq(pr.dbl, out->core, pl->core_elems, b.part_ss, kSumsqBlocks, s);
         if (he == hipSuccess) he = rh::launch_reduce_ss(b.part_ss, kSumsqBlocks, &b.rep->norm_core2, s);
@@ -814,8 +888,8 @@ int32_t rhosvd_omega_fill(rhosvd_ctx* ctx, uint64_t seed, int32_t mode, int32_t 
 }
 
 static void step_cts(int32_t precision, int* s, int* p, int* t) {
-    if (precision == RHOSVD_PREC_BF16) {
-        *s = rh::CT_BF16;
+    if (precision == RHOSVD_PREC_BF16 || precision == RHOSVD_PREC_FP8E4M3) {
+        *s = precision == RHOSVD_PREC_BF16 ? rh::CT_BF16 : rh::CT_FP8;
         *p = rh::CT_BF16X3;
         *t = rh::CT_BF16X3;
     } else {
@@ -828,7 +902,8 @@ static int32_t check_view(int32_t dtype, int32_t precision, int64_t L, int64_t I
     if (dtype != RHOSVD_F32 && dtype != RHOSVD_F64) return RHOSVD_EINVAL;
     if (L < 1 || I < 1 || T < 1 || K < 1 || K > RHOSVD_MAX_K) return RHOSVD_EINVAL;
     if (dtype == RHOSVD_F64 && precision != RHOSVD_PREC_F64) return RHOSVD_EINVAL;
-    if (dtype == RHOSVD_F32 && precision != RHOSVD_PREC_F32 && precision != RHOSVD_PREC_BF16)
+    if (dtype == RHOSVD_F32 && precision != RHOSVD_PREC_F32 && precision != RHOSVD_PREC_BF16 &&
+        precision != RHOSVD_PREC_FP8E4M3)
         return RHOSVD_EINVAL;
     return RHOSVD_OK;
 }

@@ -233,3 +233,53 @@ def test_capped_sketch_is_deterministic_hosvd(algo, dtype, tol):
         np.testing.assert_allclose(res.sigma(n), det.sigma[n], rtol=tol, atol=tol * det.sigma[n][0])
         u, v = facs[n], det.factors[n]
         assert np.linalg.norm(u @ u.T - v @ v.T, 2) <= 100 * tol
+
+
+# The e4m3 sketch only starts the power iteration: its ~3% perturbation of Y
+# is damped by each split-bf16 power step by the gap ratio of the spectrum,
+# and the factors and core come from the split-bf16 projection and
+# truncation.  Bound: the 5e-3 stated for the reduced-precision paths; with
+# q = 0 the sketch's rounding reaches Q directly, so that case is held to
+# the same 5e-3 only.
+@pytest.mark.parametrize("dims,ranks,p,q", CASES)
+def test_fp8_path_matches_oracle(dims, ranks, p, q):
+    x, _, _ = tucker_tensor(dims, ranks, seed=36, noise=0.05, dtype=np.float32)
+    res, core, facs = _run("r_sthosvd", x, ranks, p, q, seed=3, precision="fp8")
+    ref = o_rst(x.astype(np.float64), ranks, p, q, seed=3)
+    d = abs(res.rel_error - ref.rel_error)
+    print(f"[fp8] {dims} q={q}: E {res.rel_error:.8f} oracle {ref.rel_error:.8f} |dE| {d:.2e}", flush=True)
+    assert d <= 5e-3
+    for u in facs:
+        assert np.linalg.norm(u.T @ u - np.eye(u.shape[1]), 2) <= 1e-5
+
+
+# ---- RP-HOOI (Algorithm 7) ---------------------------------------------------
+
+from oracle.variants import rp_hooi as o_hooi  # noqa: E402
+
+HOOI_CASES = [((30, 26, 21), (4, 5, 3), 2), ((14, 12, 11, 9), (3, 3, 2, 3), 1), ((40, 33, 27), (6, 4, 5), 0)]
+
+
+@pytest.mark.parametrize("dims,ranks,sweeps", HOOI_CASES)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_rp_hooi_matches_oracle(dims, ranks, sweeps, dtype):
+    x, _, _ = tucker_tensor(dims, ranks, seed=43, noise=0.05, dtype=dtype)
+    xd = api.to_device(x)
+    res = api.rp_hooi(xd, ranks, sweeps=sweeps, seed=4)
+    ref = o_hooi(x.astype(np.float64), ranks, sweeps, seed=4)
+    core = api.to_numpy_fortran(res.core).astype(np.float64)
+    facs = [f.cpu().numpy().astype(np.float64) for f in res.factors]
+    if dtype == np.float64:
+        _compare(res, core, facs, ref, 1e-10, 1e-9, 1e-8)
+        for u, v in zip(facs, ref.factors):
+            np.testing.assert_allclose(u, v, atol=1e-8)
+        np.testing.assert_allclose(core, ref.core, atol=1e-8 * np.max(np.abs(ref.core)))
+    else:
+        _compare(res, core, facs, ref, 1e-5, 1e-5, 1e-4)
+
+
+def test_rp_hooi_exact_recovery():
+    dims, ranks = (36, 30, 24), (5, 4, 3)
+    x, _, _ = tucker_tensor(dims, ranks, seed=44, factors="gaussian", dtype=np.float64)
+    res = api.rp_hooi(api.to_device(x), ranks, sweeps=1, seed=2)
+    assert res.explicit and res.rel_error <= 1e-12

@@ -139,14 +139,15 @@ def _explicit_rel_error(x, x2, core, facs):
 # small FP32 cases (E 1e-5, sigma 1e-5 relative, projectors 1e-4); bf16: the
 # target of this workload, E within 1e-3 of the oracle's, with sigma and the
 # projectors within 1e-3.
-DEC_TOL = {"f32": dict(e=1e-5, s=1e-5, u=1e-4), "bf16": dict(e=1e-3, s=1e-3, u=1e-3)}
+DEC_TOL = {"f32": dict(e=1e-5, s=1e-5, u=1e-4), "bf16": dict(e=1e-3, s=1e-3, u=1e-3),
+           "fp8": dict(e=1e-3, s=1e-3, u=1e-2)}
 
 
 def test_fullsize_decomposition(data):
     x, gold = data["x"], data["gold"]
     e_ref = float(gold["rel_error"])
     errs = {}
-    for prec in ("bf16", "f32"):
+    for prec in ("bf16", "f32", "fp8"):
         dec = api.Decomposer(DIMS, W["target"], algo=W["algo"], p=W["p"], q=W["q"], seed=W["seed"],
                              dtype=torch.float32, precision=prec)
         dec.run(data["xd"])
@@ -179,3 +180,4 @@ def test_fullsize_decomposition(data):
         assert abs(e_exp - res.rel_error) <= (1e-5 if prec == "f32" else 1e-4)
         errs[prec] = res.rel_error
     assert abs(errs["bf16"] - errs["f32"]) <= 1e-4
+    assert abs(errs["fp8"] - errs["f32"]) <= 1e-3

@@ -257,3 +257,31 @@ def _tiled_kernels_fp32(dims):
         y = api.power(src, view, torch.from_numpy(q).cuda()).cpu().numpy()
         a = unfold(x64, n)
         _close_cols(y, a @ (a.T @ q.astype(np.float64)), 3e-5)
+
+
+# e4m3 sketch: every product x w is formed from e4m3 inputs (unit roundoff
+# u = 2^-4 for both operands, the tensor scaled by a power of two per
+# 32-column block, which is exact), so |dY_ik| <= (2u + u^2) (|X| |Omega|)_ik
+# plus the subnormal floors: 2^-10 absolute for Omega entries below 2^-6 and
+# 2^-10 / 128 of the block's largest magnitude for the scaled tensor, and
+# FP32 accumulation (2^-20 of the same sum at these lengths).
+@pytest.mark.parametrize("dims", DIMS)
+def test_fp8_sketch_within_rounding_bound(dims):
+    x, _, _ = tucker_tensor(dims, tuple(min(3, d) for d in dims), seed=26, noise=0.3, dtype=np.float32)
+    src = _flat(x, np.float32)
+    x64 = x.astype(np.float64)
+    n, view = _views(dims)[0]                   # contiguous: the e4m3 column kernel
+    K = min(11, dims[0], view[2])
+    y, _ = api.sketch(src, view, K, seed=5, mode=n, tag=2, precision="fp8")
+    a = unfold(x64, n)
+    om = philox.omega_unfolding(5, n, 2, x64.shape, K)
+    want = a @ om
+    u = 2.0 ** -4
+    bound = ((2 * u + u * u + 2.0 ** -20) * (np.abs(a) @ np.abs(om))
+             + 2.0 ** -10 * (np.abs(a) @ np.ones_like(om))
+             + 2.0 ** -17 * np.max(np.abs(a)) * (np.ones_like(a) @ np.abs(om)))
+    got = y.cpu().numpy()
+    assert np.all(np.abs(got - want) <= bound)
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print(f"[fp8] sketch {dims}: relative error {rel:.3e}", flush=True)
+    assert rel <= 0.05                          # about u / sqrt(3) for random-sign rounding

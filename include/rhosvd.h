@@ -74,12 +74,20 @@ typedef enum {
 
 enum { RHOSVD_F32 = 0, RHOSVD_F64 = 1 };                     /* tensor dtypes */
 /* Algorithms: RP-HOSVD (Algorithm 6), R-STHOSVD (Algorithm 8 with Algorithm
- * 1 per mode) and RP-HOOI (Algorithm 7: Q_n from the orthonormalised
+ * 1 per mode), RP-HOOI (Algorithm 7: Q_n from the orthonormalised
  * Gaussian start (Omega stream tag 5, mode n, I_n x R_n), then
  * params.power_iters sweeps of S = X x_{p != n} Q_p^T, W = S_(n) Omega
  * (tag 6, counter mode word s N + n), Q_n = QR(W); oversample must be 0;
- * the core X x_n Q_n^T with canonical factor signs). */
-enum { RHOSVD_RP_HOSVD = 0, RHOSVD_R_STHOSVD = 1, RHOSVD_RP_HOOI = 2 };
+ * the core X x_n Q_n^T with canonical factor signs) and R-PET (Algorithm 9:
+ * the factor sketches Y_n = X_(n) Omega_n of RP-HOSVD (tag 1) with
+ * Q_n = QR(Y_n), the core sketch H = X x_1 Omt_1^T ... x_N Omt_N^T with
+ * Omt_n Gaussian I_n x S_n, S_n = min(2 K_n + 1, I_n) (tag 3, mode n), the
+ * core recovered as H x_n pinv(Omt_n^T Q_n) for every n (eq. Onepass2) and
+ * truncated to R_n by a small THOSVD as in RP-HOSVD; power_iters must be 0).
+ * R-PET reads X twice (once for all Y_n, once for the first product of H)
+ * and, as its core is not X x_n U_n^T, always reports the explicit residual
+ * (RHOSVD_FLAG_E_EXPLICIT), one more pass. */
+enum { RHOSVD_RP_HOSVD = 0, RHOSVD_R_STHOSVD = 1, RHOSVD_RP_HOOI = 2, RHOSVD_R_PET = 3 };
 /* Precision of the streaming contractions (inputs of the matrix cores);
  * accumulation is FP32 (FP64 for RHOSVD_PREC_F64); Gram matrices, Cholesky
  * and eigen-decompositions are always FP64.
@@ -112,6 +120,17 @@ enum { RHOSVD_PREC_F64 = 0, RHOSVD_PREC_F32 = 1, RHOSVD_PREC_BF16 = 2, RHOSVD_PR
  * catastrophically for small errors (FP64 resolves it only down to ~1e-8).
  * The decision is taken on the device; the workspace always has room. */
 #define RHOSVD_OPT_EXPLICIT_ERROR 0x1u
+/* Sketch with the structured test matrix of Section 5.1 instead of the dense
+ * Gaussian one (the memory-efficient form W = X x_{q != n} Omega_q): the
+ * Khatri-Rao form that keeps the width K_n, column k of Omega_n being the
+ * Kronecker product of the k-th columns of small Gaussian tables Gamma_q
+ * (extent of mode q x K_n, q != n; stream (seed, counter mode word n N + q,
+ * tag 4)), i.e. the entry for the other modes' indices i_q is
+ * prod_q Gamma_q(i_q, k).  sum_q I_q K_n normals per mode instead of J_n K_n.
+ * R-STHOSVD and RP-HOSVD (EINVAL with the other algorithms); also in
+ * rhosvd_decompose_adaptive.  RP-HOSVD then sketches mode by mode (the
+ * single-pass sketch of every mode generates the Gaussian stream only). */
+#define RHOSVD_OPT_KR_SKETCH 0x2u
 
 /* Context options (rhosvd_set_option). */
 #define RHOSVD_OPTION_KERNELS 1   /* which streaming-kernel families may run: */
@@ -205,6 +224,50 @@ int32_t rhosvd_decompose_noalloc(rhosvd_ctx* ctx, const rhosvd_tensor* x,
                                  const rhosvd_params* p, const rhosvd_output* out,
                                  void* stream);
 
+/* ---- Fixed-precision R-STHOSVD (Section 5.1 with the per-mode split of the
+ * tolerance of Algorithm 4; problem DT1 of Section 4) ----
+ *
+ * The ranks come from a tolerance eps instead of being given.  Modes run in
+ * ascending order; mode n sketches the current tensor S with
+ * K_n = min(kmax, I_n, J_n) columns (Omega tag 2, as R-STHOSVD), applies q
+ * power steps, forms B = Q^T S_(n) and the eigenpairs of B B^T, and keeps the
+ * smallest R_n whose residual ||S||^2 - sum_{i <= R_n} sigma_i^2 (the part of
+ * S outside span(Q) plus the discarded spectrum of B) is at most
+ * eps^2 ||X||^2 / N; when no R <= K_n reaches it, R_n = K_n and the mode is
+ * reported unmet.  Then S <- S x_n U_n^T with U_n = Q Ubar[:, :R_n].
+ * ||S||^2 is accumulated in FP64 in the sketch pass and the sigma_i come from
+ * the FP64 eigen-decomposition of the Gram, so the residual carries the
+ * Gram's accumulation error (about 1e-7 ||S||^2 with FP32 inputs, 1e-5 with
+ * split-bf16 operands): tolerances well above it are decided reliably.
+ *
+ * The rank choice reads the eigenvalues on the host: the call synchronises
+ * `stream` once per mode and returns when the whole decomposition is done.
+ * Capacities: out->factors[n] holds I_n x min(kmax, I_n) elements and
+ * out->core prod_n min(kmax, I_n); on return ranks_out[n] (host, N entries)
+ * = R_n, U_n is the leading I_n x R_n column-major block of factors[n] and
+ * the core the leading R_1 x ... x R_N elements (first-index-fastest).
+ * met_out[n] (host, optional) = 1 when mode n met its share.  The report
+ * holds sigma[n][0 .. R_n), k_used = K_n and, as rhosvd_decompose, the norms
+ * and the explicit residual when requested or when E < 1e-2.
+ * Errors as rhosvd_decompose; EINVAL also for eps <= 0 or kmax outside
+ * 1..RHOSVD_MAX_SKETCH. */
+typedef struct {
+    double eps;               /* target relative error, > 0 */
+    int32_t kmax;             /* largest sketch width per mode, 1..RHOSVD_MAX_SKETCH */
+    int32_t power_iters;      /* q, 0..8 */
+    uint64_t seed;            /* Omega key */
+    int32_t precision;        /* RHOSVD_PREC_*; F64 requires F64 data */
+    uint32_t flags;           /* RHOSVD_OPT_* bits */
+} rhosvd_adaptive_params;
+
+/* Workspace bytes of rhosvd_decompose_adaptive (every R_n = K_n bounds it). */
+int32_t rhosvd_adaptive_workspace_size(const rhosvd_tensor* x, const rhosvd_adaptive_params* p,
+                                       size_t* bytes);
+int32_t rhosvd_decompose_adaptive(rhosvd_ctx* ctx, const rhosvd_tensor* x,
+                                  const rhosvd_adaptive_params* p, void* workspace,
+                                  size_t ws_bytes, const rhosvd_output* out, int32_t* ranks_out,
+                                  int32_t* met_out, void* stream);
+
 /* ---- Batched decomposition: many small tensors in one graph launch ----
  *
  * R-STHOSVD (Algorithm 8 with Algorithm 1 per mode) of `count` independent
@@ -219,7 +282,9 @@ int32_t rhosvd_decompose_noalloc(rhosvd_ctx* ctx, const rhosvd_tensor* x,
  * precision may differ per item; the streaming passes run the workgroup-
  * tiled FP32/FP64 kernels whatever the precision.  An item's result depends
  * only on its own problem and on the context's tuned tile parameters, so it
- * is bitwise the same alone (a batch of one) and in any mix.
+ * is bitwise the same alone (a batch of one) and in any mix.  The reports
+ * hold the identity-based E of Section 5.1 only (no explicit residual pass):
+ * with FP32 data it cannot resolve errors below about 1e-3.
  *
  * The context's tuner picks the tile width and the tiles per workgroup by
  * timing the candidates on the first batch bound with autotune != 0; the
@@ -319,6 +384,16 @@ int32_t rhosvd_sketch(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t p
                       int64_t L, int64_t I, int64_t T, int32_t K, uint64_t seed,
                       int32_t mode, int32_t tag, double* y, double* norm2,
                       void* workspace, size_t ws_bytes, void* stream);
+
+/* The same sketch with the structured test matrix of RHOSVD_OPT_KR_SKETCH
+ * (Section 5.1): the view's column j = l + L t split in mixed radix over
+ * ext[0 .. nq) (fastest first), Omega(j, k) = prod_q tabs[q](i_q, k), each
+ * tabs[q] a device ext[q] x K column-major table in src's dtype; prod ext = J
+ * (else EINVAL), 1 <= nq <= 15.  Test entry of the structured kernels. */
+int32_t rhosvd_sketch_kr(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t precision,
+                         int64_t L, int64_t I, int64_t T, int32_t K, const void* const* tabs,
+                         const int64_t* ext, int32_t nq, double* y, double* norm2,
+                         void* workspace, size_t ws_bytes, void* stream);
 
 /* Sketch of every mode from one read of X (Algorithm 6 step 3; Section 5.1:
  * no unfolding is formed): Y_n = X_(n) Omega_n for n = 0..N-1, Omega_n the

@@ -103,7 +103,7 @@ def sthosvd(x, ranks, mode_order=None):
     return _finish(x, s_t, factors, sigma, list(ranks))
 
 
-def r_sthosvd(x, ranks, p, q, seed, mode_order=None, keep_trace=False):
+def r_sthosvd(x, ranks, p, q, seed, mode_order=None, keep_trace=False, omega_fn=None):
     """Algorithm 8: randomized sequentially truncated HOSVD.
 
     S starts as the whole tensor X (the first step of the printed algorithm
@@ -112,6 +112,8 @@ def r_sthosvd(x, ranks, p, q, seed, mode_order=None, keep_trace=False):
     target rank R_n, oversampling p and q power steps, using the test matrix
     Omega(seed, mode=n, tag=2) of the current S (rows in the paper's order,
     see oracle.philox); then S <- S x_n Q_n^T with the rank-R_n factor.
+    omega_fn(n, shape, K), when given, supplies the test matrix of mode n for
+    the current tensor's shape instead (the structured sketch).
     """
     x = np.asarray(x, dtype=np.float64)
     _check_ranks(x.shape, ranks)
@@ -125,8 +127,11 @@ def r_sthosvd(x, ranks, p, q, seed, mode_order=None, keep_trace=False):
         a = unfold(s_t, n)
         if ranks[n] > a.shape[1]:
             raise ValueError("R_n exceeds the column count of the current unfolding")
-        res = brsvd(a, ranks[n], p, q,
-                    lambda J, K, n=n, sh=s_t.shape: omega_unfolding(seed, n, TAG_R_STHOSVD, sh, K))
+        if omega_fn is None:
+            om_fn = lambda J, K, n=n, sh=s_t.shape: omega_unfolding(seed, n, TAG_R_STHOSVD, sh, K)
+        else:
+            om_fn = lambda J, K, n=n, sh=s_t.shape: omega_fn(n, sh, K)
+        res = brsvd(a, ranks[n], p, q, om_fn)
         u = res.U * canonical_signs(res.U)
         factors[n], sigma[n], k_used[n] = u, res.s, res.K
         if keep_trace:
@@ -135,7 +140,7 @@ def r_sthosvd(x, ranks, p, q, seed, mode_order=None, keep_trace=False):
     return _finish(x, s_t, factors, sigma, k_used, trace)
 
 
-def rp_hosvd(x, ranks, p, q, seed):
+def rp_hosvd(x, ranks, p, q, seed, omega_fn=None):
     """Algorithm 6: random-projection HOSVD.
 
     For every mode n independently: K_n = min(R_n + p, I_n, J_n),
@@ -155,7 +160,9 @@ def rp_hosvd(x, ranks, p, q, seed):
         K = min(ranks[n] + p, I, J)
         if ranks[n] > J:
             raise ValueError("R_n exceeds the column count of the unfolding")
-        y = a @ omega_unfolding(seed, n, TAG_RP_HOSVD, x.shape, K)
+        om = (omega_unfolding(seed, n, TAG_RP_HOSVD, x.shape, K) if omega_fn is None
+              else omega_fn(n, x.shape, K))
+        y = a @ om
         qm = qr_pos(y)
         for _ in range(q):
             qz = qr_pos(a.T @ qm)

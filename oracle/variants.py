@@ -11,6 +11,10 @@ TEST INFRASTRUCTURE ONLY, like the rest of this package.
   r_pet               the pass-efficient randomized Tucker algorithm R-PET,
                       Algorithm 9 (factor sketches and a core sketch from one
                       pass over X, core recovered by least squares).
+  omega_kr            the memory-efficient structured test matrix of Section
+                      5.1 (a Khatri-Rao product of small Gaussian matrices,
+                      one per other mode), and r_sthosvd_kr / rp_hosvd_kr,
+                      Algorithms 8 and 6 sketching with it.
 
 Readings where the paper is silent or garbled (listed with the others in the
 design notes):
@@ -30,6 +34,17 @@ design notes):
   (tag 1), the core sketch matrices Omega~_n (S_n x I_n) the tag 3 stream
   (generator rows = i_n, columns = s); the truncation of the recovered K-sized
   core to rank R is the small THOSVD used for oversampled RP-HOSVD.
+* Structured sketch: the paper writes W = Z x_{p != n} Omega_p^(n) and calls
+  the unfolding of W a product with the Kronecker product of the Omega_p^(n)
+  (the dimensions it prints are garbled); a Kronecker product would make the
+  sketch width the product of the per-mode widths, so the Khatri-Rao form of
+  its footnote is taken, which keeps the width K_n of Algorithm 1: column k
+  of Omega_n is the Kronecker product of the k-th columns of Gaussian
+  Gamma_q (extent of mode q x K_n), q != n, i.e. the entry for the other
+  modes' indices (i_q) is prod_q Gamma_q(i_q, k).  Gamma_q of mode n is the
+  stream (seed, counter mode word n N + q, tag 4) over the current extent of
+  mode q; no cyclic reordering is needed since the tables are indexed by the
+  mode indices themselves.
 """
 from dataclasses import dataclass
 from typing import List
@@ -39,9 +54,10 @@ import numpy as np
 from .philox import TAG_RP_HOSVD, TAG_R_STHOSVD, cyclic_position, omega, omega_unfolding
 from .rsvd import canonical_signs, qr_pos
 from .tensor_ops import frob2, ttm, unfold
-from .tucker import TuckerResult, _finish
+from .tucker import TuckerResult, _finish, r_sthosvd, rp_hosvd
 
 TAG_RPET_CORE = 3
+TAG_KR = 4
 TAG_HOOI_INIT = 5
 TAG_HOOI_SKETCH = 6
 
@@ -184,3 +200,36 @@ def r_pet(x, ranks, p, seed):
         sigma.append(s[:ranks[n]])
         g = ttm(g, (w * sg).T, n)
     return _finish(x, g, factors, sigma, ks)
+
+
+def kr_tables(seed, n, shape, K):
+    """The Gaussian tables Gamma_q (shape[q] x K) of mode n's structured
+    sketch, q != n (stream word n N + q, tag 4)."""
+    N = len(shape)
+    return {q: omega(seed, n * N + q, TAG_KR, int(shape[q]), int(K)) for q in range(N) if q != n}
+
+
+def omega_kr(seed, n, shape, K):
+    """Structured test matrix for the n-unfolding of a tensor of `shape`, rows
+    in the paper's column order j = l + L t (the other modes' indices in
+    storage order, first fastest): Omega(j, k) = prod_{q != n} Gamma_q(i_q(j), k)."""
+    shape = tuple(int(d) for d in shape)
+    tabs = kr_tables(seed, n, shape, K)
+    other = [q for q in range(len(shape)) if q != n]
+    J = int(np.prod([shape[q] for q in other], dtype=np.int64))
+    idx = np.unravel_index(np.arange(J), [shape[q] for q in other], order="F")
+    om = np.ones((J, int(K)))
+    for pos, q in enumerate(other):
+        om *= tabs[q][idx[pos], :]
+    return om
+
+
+def r_sthosvd_kr(x, ranks, p, q, seed):
+    """Algorithm 8 in the natural mode order with Algorithm 1 sketching by
+    omega_kr of the current tensor."""
+    return r_sthosvd(x, ranks, p, q, seed, omega_fn=lambda n, sh, K: omega_kr(seed, n, sh, K))
+
+
+def rp_hosvd_kr(x, ranks, p, q, seed):
+    """Algorithm 6 with every sketch W = X_(n) omega_kr(seed, n, X.shape, K_n)."""
+    return rp_hosvd(x, ranks, p, q, seed, omega_fn=lambda n, sh, K: omega_kr(seed, n, sh, K))

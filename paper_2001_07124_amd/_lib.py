@@ -17,11 +17,12 @@ MAX_K = 128
 OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EBUSY, EUNSUPPORTED, ESCRATCH = range(8)
 NOALLOC_SCRATCH_BYTES = 64 << 20
 F32, F64 = 0, 1
-RP_HOSVD, R_STHOSVD, RP_HOOI = 0, 1, 2
+RP_HOSVD, R_STHOSVD, RP_HOOI, R_PET = 0, 1, 2, 3
 PREC_F64, PREC_F32, PREC_BF16, PREC_FP8 = 0, 1, 2, 3
 FLAG_K_CAPPED, FLAG_CQR_SHIFTED, FLAG_EVD_NOCONV, FLAG_QR_HOUSEHOLDER = 0x1, 0x2, 0x4, 0x8
 FLAG_E_EXPLICIT = 0x10
 OPT_EXPLICIT_ERROR = 0x1
+OPT_KR_SKETCH = 0x2
 REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 OPTION_KERNELS = 1
 KERNELS_AUTO, KERNELS_TILED = 0, 1
@@ -37,6 +38,11 @@ class Params(ctypes.Structure):
                 ("oversample", ctypes.c_int32), ("power_iters", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("mode_order", ctypes.POINTER(ctypes.c_int32)),
                 ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class AdaptiveParams(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("kmax", ctypes.c_int32), ("power_iters", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
 class Report(ctypes.Structure):
@@ -71,6 +77,11 @@ _PROTOS = {
                                 ctypes.POINTER(Output), _P]),
     "rhosvd_decompose_noalloc": (_I32, [_P, ctypes.POINTER(Tensor), ctypes.POINTER(Params),
                                         ctypes.POINTER(Output), _P]),
+    "rhosvd_adaptive_workspace_size": (_I32, [ctypes.POINTER(Tensor), ctypes.POINTER(AdaptiveParams),
+                                              ctypes.POINTER(_SZ)]),
+    "rhosvd_decompose_adaptive": (_I32, [_P, ctypes.POINTER(Tensor), ctypes.POINTER(AdaptiveParams),
+                                         _P, _SZ, ctypes.POINTER(Output), ctypes.POINTER(_I32),
+                                         ctypes.POINTER(_I32), _P]),
     "rhosvd_batch_create": (_I32, [_P, _I32, ctypes.POINTER(Tensor), ctypes.POINTER(Params),
                                    ctypes.POINTER(Output), ctypes.POINTER(_P), ctypes.POINTER(_SZ)]),
     "rhosvd_batch_bind": (_I32, [_P, _P, _SZ, _I32, _P]),
@@ -88,6 +99,8 @@ _PROTOS = {
     "rhosvd_omega_fill": (_I32, [_P, _U64, _I32, _I32, _I64, _I32, _I32, _P, _P]),
     "rhosvd_sketch": (_I32, [_P, _P, _I32, _I32, _I64, _I64, _I64, _I32, _U64, _I32, _I32, _P, _P,
                              _P, _SZ, _P]),
+    "rhosvd_sketch_kr": (_I32, [_P, _P, _I32, _I32, _I64, _I64, _I64, _I32, _P, _P, _I32, _P, _P,
+                                _P, _SZ, _P]),
     "rhosvd_sketch_all": (_I32, [_P, _P, _I32, _I32, _P, _P, _U64, _I32, _P, _P, _P, _SZ, _P]),
     "rhosvd_sketch_all_workspace_size": (_SZ, [_I32, _P, _P, _I32]),
     "rhosvd_power": (_I32, [_P, _P, _I32, _I32, _I64, _I64, _I64, _I32, _P, _P, _P, _SZ, _P]),

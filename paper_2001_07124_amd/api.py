@@ -177,7 +177,7 @@ class Decomposer:
 
     def __init__(self, dims, ranks, *, algo="r_sthosvd", p=10, q=1, seed=0,
                  dtype=torch.float32, precision=None, mode_order=None, device=None,
-                 explicit_error=False):
+                 explicit_error=False, kr_sketch=False):
         self.lib = L.load()
         self.device = torch.device(device) if device is not None else torch.device(
             "cuda", torch.cuda.current_device())
@@ -191,8 +191,9 @@ class Decomposer:
         self._ranks_c = (ctypes.c_int32 * self.N)(*self.ranks)
         self._order_c = None if mode_order is None else (ctypes.c_int32 * self.N)(*mode_order)
         self.tensor = L.Tensor(self.N, self._dims_c, _dtype_code(dtype), None)
-        algo_code = {"r_sthosvd": L.R_STHOSVD, "rp_hosvd": L.RP_HOSVD, "rp_hooi": L.RP_HOOI}[algo]
-        flags = L.OPT_EXPLICIT_ERROR if explicit_error else 0
+        algo_code = {"r_sthosvd": L.R_STHOSVD, "rp_hosvd": L.RP_HOSVD, "rp_hooi": L.RP_HOOI,
+                     "r_pet": L.R_PET}[algo]
+        flags = (L.OPT_EXPLICIT_ERROR if explicit_error else 0) | (L.OPT_KR_SKETCH if kr_sketch else 0)
         self.params = L.Params(algo_code, self._ranks_c, int(p), int(q), int(seed),
                                self._order_c, _prec_code(precision, dtype), flags)
         ws = ctypes.c_size_t(0)
@@ -238,12 +239,13 @@ class Decomposer:
 
 
 def decompose(x, ranks, *, algo="r_sthosvd", p=10, q=1, seed=0, precision=None,
-              mode_order=None, dims=None, stream=None, explicit_error=False):
-    """One decomposition of x (device tensor, first-index-fastest)."""
+              mode_order=None, dims=None, stream=None, explicit_error=False, kr_sketch=False):
+    """One decomposition of x (device tensor, first-index-fastest);
+    kr_sketch selects the structured (Khatri-Rao) test matrix of Section 5.1."""
     dims = _check_fortran(x, dims)
     d = Decomposer(dims, ranks, algo=algo, p=p, q=q, seed=seed, dtype=x.dtype,
                    precision=precision, mode_order=mode_order, device=x.device,
-                   explicit_error=explicit_error)
+                   explicit_error=explicit_error, kr_sketch=kr_sketch)
     d.run(x, stream)
     return d.result()
 
@@ -258,9 +260,62 @@ def rp_hosvd(x, ranks, p=10, q=0, seed=0, **kw):
     return decompose(x, ranks, algo="rp_hosvd", p=p, q=q, seed=seed, **kw)
 
 
+def r_pet(x, ranks, p=10, seed=0, **kw):
+    """R-PET (Algorithm 9): factor sketches and a core sketch of width
+    S_n = min(2 K_n + 1, I_n), the core recovered by least squares."""
+    return decompose(x, ranks, algo="r_pet", p=p, q=0, seed=seed, **kw)
+
+
 def rp_hooi(x, ranks, sweeps=2, seed=0, **kw):
     """RP-HOOI (Algorithm 7) with `sweeps` sweeps from a Gaussian start."""
     return decompose(x, ranks, algo="rp_hooi", p=0, q=sweeps, seed=seed, **kw)
+
+
+@dataclass
+class AdaptiveDecomposition(Decomposition):
+    ranks: tuple = ()
+    met: tuple = ()
+
+
+def decompose_adaptive(x, eps, *, kmax=32, q=1, seed=0, precision=None, dims=None, stream=None,
+                       explicit_error=False, kr_sketch=False):
+    """Fixed-precision R-STHOSVD: the ranks from the tolerance eps (Section
+    5.1 with Algorithm 4's per-mode share eps^2 ||X||^2 / N), each mode
+    sketched with K_n = min(kmax, I_n, J_n) columns.  Returns the core and
+    factors at the chosen ranks plus `ranks` and `met` (per mode, whether its
+    share of the tolerance was reached).  Synchronises the stream once per
+    mode (the rank choice reads the eigenvalues on the host)."""
+    lib = L.load()
+    dims = _check_fortran(x, dims)
+    dev = x.device
+    N = len(dims)
+    dims_c = (ctypes.c_int64 * N)(*dims)
+    tensor = L.Tensor(N, dims_c, _dtype_code(x.dtype), x.data_ptr())
+    flags = (L.OPT_EXPLICIT_ERROR if explicit_error else 0) | (L.OPT_KR_SKETCH if kr_sketch else 0)
+    prm = L.AdaptiveParams(float(eps), int(kmax), int(q), int(seed), _prec_code(precision, x.dtype),
+                           flags)
+    ws = ctypes.c_size_t(0)
+    L.check(lib.rhosvd_adaptive_workspace_size(ctypes.byref(tensor), ctypes.byref(prm),
+                                               ctypes.byref(ws)), "rhosvd_adaptive_workspace_size")
+    workspace = torch.empty(int(ws.value), dtype=torch.uint8, device=dev)
+    caps = [min(int(kmax), d) for d in dims]
+    fac_bufs = [torch.empty(d * c, dtype=x.dtype, device=dev) for d, c in zip(dims, caps)]
+    core_buf = torch.empty(int(np.prod(caps)), dtype=x.dtype, device=dev)
+    report_buf = torch.zeros(ctypes.sizeof(L.Report), dtype=torch.uint8, device=dev)
+    fac_c = (ctypes.c_void_p * N)(*[f.data_ptr() for f in fac_bufs])
+    out = L.Output(core_buf.data_ptr(), fac_c, report_buf.data_ptr())
+    ranks_c = (ctypes.c_int32 * N)()
+    met_c = (ctypes.c_int32 * N)()
+    L.check(lib.rhosvd_decompose_adaptive(_context(dev.index or 0), ctypes.byref(tensor),
+                                          ctypes.byref(prm), ctypes.c_void_p(workspace.data_ptr()),
+                                          int(ws.value), ctypes.byref(out), ranks_c, met_c,
+                                          _stream(stream, dev)),
+            "rhosvd_decompose_adaptive")
+    ranks = tuple(int(r) for r in ranks_c)
+    factors = [f[: d * r].as_strided((d, r), (1, d)) for f, d, r in zip(fac_bufs, dims, ranks)]
+    core = core_buf[: int(np.prod(ranks))].as_strided(ranks, fortran_strides(ranks))
+    return AdaptiveDecomposition(core=core, factors=factors, report_buf=report_buf, order=N,
+                                 ranks=ranks, met=tuple(bool(m) for m in met_c))
 
 
 # ---- step-level calls (one hot-path step each) -------------------------------
@@ -296,6 +351,26 @@ def sketch(src, view, K, seed, mode, tag, want_norm=False, precision=None):
                               _prec_code(precision, src.dtype), Lv, I, T, int(K), int(seed), int(mode),
                               int(tag), _ptr(y), _ptr(nrm), _ptr(ws), nb, _stream(None, dev)),
             "rhosvd_sketch")
+    return y, nrm
+
+
+def sketch_kr(src, view, K, tables, ext, want_norm=False, precision=None):
+    """Y = S_(n) Omega with the structured test matrix: the view's column
+    index split over ext (fastest first), Omega(j, k) = prod_q tables[q](i_q, k)
+    with tables[q] device ext[q] x K column-major in src's dtype."""
+    lib = L.load()
+    Lv, I, T = (int(v) for v in view)
+    dev = src.device
+    y = empty_colmajor(I, K, torch.float64, dev)
+    nrm = torch.zeros(1, dtype=torch.float64, device=dev) if want_norm else None
+    ws, nb = _step_ws(I, K, Lv * T, dev)
+    nq = len(tables)
+    tabs_c = (ctypes.c_void_p * nq)(*[t.data_ptr() for t in tables])
+    ext_c = (ctypes.c_int64 * nq)(*[int(e) for e in ext])
+    L.check(lib.rhosvd_sketch_kr(_context(dev.index or 0), _ptr(src), _dtype_code(src.dtype),
+                                 _prec_code(precision, src.dtype), Lv, I, T, int(K), tabs_c, ext_c,
+                                 nq, _ptr(y), _ptr(nrm), _ptr(ws), nb, _stream(None, dev)),
+            "rhosvd_sketch_kr")
     return y, nrm
 
 
@@ -485,7 +560,8 @@ class Server:
         dims_c = (ctypes.c_int64 * N)(*dims)
         ranks_c = (ctypes.c_int32 * N)(*[int(r) for r in ranks])
         t = L.Tensor(N, dims_c, _dtype_code(x.dtype), x.data_ptr())
-        algo_code = {"r_sthosvd": L.R_STHOSVD, "rp_hosvd": L.RP_HOSVD}[algo]
+        algo_code = {"r_sthosvd": L.R_STHOSVD, "rp_hosvd": L.RP_HOSVD, "rp_hooi": L.RP_HOOI,
+                     "r_pet": L.R_PET}[algo]
         prm = L.Params(algo_code, ranks_c, int(p), int(q), int(seed), None,
                        _prec_code(precision, x.dtype), L.OPT_EXPLICIT_ERROR if explicit_error else 0)
         if outputs is None:

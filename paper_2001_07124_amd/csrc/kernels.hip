@@ -9,6 +9,8 @@
 // factor + sign canonicalisation (steps 6-7), fixed-order reductions.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "householder.hpp"
 #include "kernels.hpp"
@@ -107,11 +109,13 @@ __device__ __forceinline__ void stream_body(const StreamGeom& g, const StreamArg
         }
 
         // ---- Omega tile: entries (j0 + c, k) for c < Cv, k < K
-        if (OP == OP_SKETCH && g.L > 1) {
+        if (OP == OP_SKETCH && (g.L > 1 || a.kr.nq)) {
             // generator rows are not consecutive along the tile's columns
+            // (or the structured matrix): entry by entry
             for (int it = tid; it < K * Cv; it += kBlock) {
                 const int k = it / Cv, c = it - k * Cv;
-                sW[c * KW + k] = omega_entry<T>(a.seed, a.mode, a.tag, j0 + c, k, g.L, g.T, J);
+                sW[c * KW + k] = a.kr.nq ? kr_entry<T>(a.kr, j0 + c, k)
+                                         : omega_entry<T>(a.seed, a.mode, a.tag, j0 + c, k, g.L, g.T, J);
             }
         } else if (OP == OP_SKETCH) {
             const int QPK = C / 4 + 2;
@@ -658,6 +662,39 @@ hipError_t launch_omega_fill(bool dbl, uint64_t seed, int mode, int tag, int64_t
     return hipGetLastError();
 }
 
+// Several J x K Gaussian tables in one launch (the structured sketch's
+// tables): table y = blockIdx.y holds the stream (seed, word, tag) as
+// launch_omega_fill writes it.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_kr_fill(KrFill f) {
+    const KrFill::Table& t = f.t[blockIdx.y];
+    const int64_t total = t.J * static_cast<int64_t>(t.K);
+    T* out = static_cast<T*>(t.out);
+    for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; 4 * q < total;
+         q += static_cast<int64_t>(gridDim.x) * kBlock) {
+        T z[4];
+        normals4<T>(static_cast<uint64_t>(q), t.word, f.tag, f.seed, z);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int64_t e = 4 * q + w;
+            if (e < total) out[e] = z[w];
+        }
+    }
+}
+
+hipError_t launch_kr_fill(bool dbl, const KrFill& f, hipStream_t s) {
+    if (f.count < 1 || f.count > KrFill::kMax) return hipErrorInvalidValue;
+    int64_t most = 1;
+    for (int i = 0; i < f.count; ++i) most = std::max<int64_t>(most, f.t[i].J * f.t[i].K);
+    int64_t blocks = (most / 4 + kBlock) / kBlock;
+    if (blocks > 256) blocks = 256;
+    if (dbl)
+        hipLaunchKernelGGL(k_kr_fill<double>, dim3(blocks, f.count), dim3(kBlock), 0, s, f);
+    else
+        hipLaunchKernelGGL(k_kr_fill<float>, dim3(blocks, f.count), dim3(kBlock), 0, s, f);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Report bookkeeping.
 // ---------------------------------------------------------------------------
@@ -673,6 +710,20 @@ __global__ void k_report_init(rhosvd_report* rep, ReportInit ri, uint32_t init_f
         for (int n = 0; n < RHOSVD_MAX_ORDER; ++n) rep->k_used[n] = ri.k_used[n];
         rep->flags = init_flags;
     }
+}
+
+__global__ void k_report_mode(rhosvd_report* rep, int n, int k, int r) {
+    for (int e = r + static_cast<int>(threadIdx.x); e < RHOSVD_MAX_K; e += blockDim.x) rep->sigma[n][e] = 0.0;
+    if (threadIdx.x == 0) {
+        rep->k_used[n] = k < 0 ? -k : k;
+        if (k < 0) rep->flags |= RHOSVD_FLAG_K_CAPPED;
+    }
+}
+
+hipError_t launch_report_mode(void* rep, int n, int k, int r, hipStream_t s) {
+    hipLaunchKernelGGL(k_report_mode, dim3(1), dim3(kWave), 0, s, static_cast<rhosvd_report*>(rep),
+                       n, k, r);
+    return hipGetLastError();
 }
 
 hipError_t launch_report_init(void* rep, ReportInit ri, hipStream_t s) {

@@ -25,6 +25,59 @@ struct StreamGeom {
     size_t lds_bytes;
 };
 
+// Structured test matrix of Section 5.1 (the Khatri-Rao form): the
+// unfolding column j, split in mixed radix over ext[0 .. nq) (fastest first:
+// the other modes in the order they are stored), gives
+// Omega(j, k) = prod_q tab_q(i_q, k), each tab_q ext[q] x K column-major in
+// the tensor's dtype.  nq = 0 selects the Gaussian stream.  Rows past J and
+// columns past K (the padding of the kernels' tiles) read as row J - 1 and
+// column K - 1 so that no table is read out of range; their products meet
+// zero data or land in dropped outputs.
+struct KrArgs {
+    const void* tab[RHOSVD_MAX_ORDER - 1];
+    int ext[RHOSVD_MAX_ORDER - 1];
+    int nq;
+    int K;
+    int64_t J;
+};
+
+template <typename V>
+__device__ __forceinline__ V kr_entry(const KrArgs& kr, int64_t j, int k) {
+    uint32_t jj = static_cast<uint32_t>(j < kr.J ? j : kr.J - 1);
+    const size_t kk = static_cast<size_t>(k < kr.K ? k : kr.K - 1);
+    V w = V(1);
+    for (int q = 0; q < kr.nq; ++q) {
+        const uint32_t e = static_cast<uint32_t>(kr.ext[q]);
+        const uint32_t nx = jj / e;
+        w *= static_cast<const V*>(kr.tab[q])[(jj - nx * e) + kk * e];
+        jj = nx;
+    }
+    return w;
+}
+
+// Rows j0 .. j0 + 3 of column k: the slower digits' product once, the
+// fastest digit per row (the full product where it wraps).
+template <typename V>
+__device__ __forceinline__ void kr_entry4(const KrArgs& kr, int64_t j0, int k, V (&w)[4]) {
+    const int64_t jl = kr.J - 1;
+    const uint32_t e0 = static_cast<uint32_t>(kr.ext[0]);
+    const size_t kk = static_cast<size_t>(k < kr.K ? k : kr.K - 1);
+    const uint32_t jj = static_cast<uint32_t>(j0 < jl ? j0 : jl);
+    uint32_t r = jj / e0;
+    const uint32_t i0 = jj - r * e0;
+    V rest = V(1);
+    for (int q = 1; q < kr.nq; ++q) {
+        const uint32_t e = static_cast<uint32_t>(kr.ext[q]);
+        const uint32_t nx = r / e;
+        rest *= static_cast<const V*>(kr.tab[q])[(r - nx * e) + kk * e];
+        r = nx;
+    }
+    const V* t0 = static_cast<const V*>(kr.tab[0]) + kk * e0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        w[e] = (i0 + e < e0 && j0 + e <= jl) ? rest * t0[i0 + e] : kr_entry<V>(kr, j0 + e, k);
+}
+
 struct StreamArgs {
     const void* src;
     const void* mat;      // POWER: Q (I x K); TTM: M (I x Kout); column-major
@@ -35,6 +88,7 @@ struct StreamArgs {
     uint64_t seed;
     uint32_t mode, tag;
     int out_t;            // TTM with L == 1: write out[r * J + j] (modes rotated) instead of out[j * K + r]
+    KrArgs kr;            // SKETCH: the structured test matrix when kr.nq > 0
 };
 
 // Plan the geometry of a pass; returns false if the shape exceeds the
@@ -71,6 +125,9 @@ struct WGeom {
     int64_t nblocks;
     int grid;
     int vec4;             // L == 1 and I % 4 == 0: 16-byte row loads
+    int rs;               // waves sharing a column block (1, or 4 for tall modes)
+    int IBW;              // row blocks per wave when rs > 1
+    size_t xr_off;        // rs > 1: offset of the cross-wave exchange of Z
 };
 
 bool plan_wave(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu, WGeom* g);
@@ -110,6 +167,10 @@ hipError_t launch_cqr_lds(const double* y, int64_t I, int K, bool dbl, void* q_o
 hipError_t launch_cqr_global(const double* y, int64_t I, int K, bool dbl, void* q_out,
                              double* q64, uint32_t* flags, hipStream_t s);
 size_t cqr_lds_bytes(int64_t I, int K);
+// R-PET core recovery operator: pt = (pinv(Omt^T Q))^T (S x K column-major)
+// for Omt (I x S) and Q (I x K), in FP64 arithmetic (kernels_small.hip).
+hipError_t launch_lsq_pinv(bool dbl, const void* omt, const void* q, int I, int S, int K, void* pt,
+                           uint32_t* flags, hipStream_t s);
 
 // Symmetric EVD of the K x K Gram C (FP64, sorted descending) followed, in
 // the same launch, by the factor step: U = Q V[:, :R] (identity V when
@@ -131,6 +192,22 @@ hipError_t launch_sumsq(bool dbl, const void* x, int64_t n, double* part, int G,
 
 hipError_t launch_omega_fill(bool dbl, uint64_t seed, int mode, int tag, int64_t J, int K,
                              void* out, hipStream_t s);
+
+// Up to kMax Gaussian tables (stream (seed, word, tag), J x K column-major
+// each, as launch_omega_fill) in one launch.
+struct KrFill {
+    static constexpr int kMax = 48;
+    struct Table {
+        void* out;
+        int64_t J;
+        int K;
+        uint32_t word;
+    } t[kMax];
+    int count;
+    uint32_t tag;
+    uint64_t seed;
+};
+hipError_t launch_kr_fill(bool dbl, const KrFill& f, hipStream_t s);
 
 hipError_t launch_gram_reduce(bool dbl, const void* part, int G, int K, int K_pad, double* c,
                               hipStream_t s);
@@ -231,6 +308,9 @@ struct ReportInit {
     int32_t k_used[16];
 };
 hipError_t launch_report_init(void* rep, ReportInit ri, hipStream_t s);
+// After mode n of the fixed-precision path: k_used[n] = |k| (k < 0 marks a
+// capped sketch width, which also sets the flag) and sigma[n][r ..] = 0.
+hipError_t launch_report_mode(void* rep, int n, int k, int r, hipStream_t s);
 hipError_t launch_copy_bytes(const void* src, void* dst, size_t n, hipStream_t s);
 
 }  // namespace rh

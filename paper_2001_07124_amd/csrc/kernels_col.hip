@@ -337,6 +337,23 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
     // mode-n product output staging (TTM): 32 x 16 NB floats per wave
     float* stage = reinterpret_cast<float*>(smem + g.mfr_bytes) + static_cast<size_t>(wave) * 32 * 16 * NB;
 
+    // Omega rows j .. j + 3 and j + 16 .. j + 19 of column k (linear index e0
+    // of the first): the Gaussian stream, or the structured matrix
+    auto omega8 = [&](uint64_t e0, int64_t j, int k, f32x4& w0, f32x4& w1) {
+        if (a.kr.nq) {
+            float t0[4], t1[4];
+            kr_entry4<float>(a.kr, j, k, t0);
+            kr_entry4<float>(a.kr, j + 16, k, t1);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                w0[e] = t0[e];
+                w1[e] = t1[e];
+            }
+        } else {
+            w0 = omega4_w(e0, a.mode, a.tag, a.seed, jal);
+            w1 = omega4_w(e0 + 16, a.mode, a.tag, a.seed, jal);
+        }
+    };
     auto body = [&](f32x4 (&Fb)[NCH][2][2], int64_t blk) {
         const int64_t j0 = blk * 32;
         const __amdgpu_buffer_rsrc_t rn = block_rsrc(src, blk + PD * nw, g.nblocks, I, J);
@@ -470,8 +487,9 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const uint64_t e0 = eb[nb] + static_cast<uint64_t>(j0);
-                W8[nb] = to_fp8x8(omega4_w(e0, a.mode, a.tag, a.seed, jal),
-                                  omega4_w(e0 + 16, a.mode, a.tag, a.seed, jal));
+                f32x4 w0, w1;
+                omega8(e0, j0 + 4 * grp, 16 * nb + c16, w0, w1);
+                W8[nb] = to_fp8x8(w0, w1);
             }
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) {
@@ -486,8 +504,8 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
             for (int nb = 0; nb < NB; ++nb) {
                 if (OP == OP_SKETCH) {
                     const uint64_t e0 = eb[nb] + static_cast<uint64_t>(j0);
-                    const f32x4 w0 = omega4_w(e0, a.mode, a.tag, a.seed, jal);
-                    const f32x4 w1 = omega4_w(e0 + 16, a.mode, a.tag, a.seed, jal);
+                    f32x4 w0, w1;
+                    omega8(e0, j0 + 4 * grp, 16 * nb + c16, w0, w1);
                     Whi[nb] = to_bf16x8(w0, w1);
                 } else {
                     split8(Z[0][nb], Z[1][nb], Whi[nb], Wlo[nb]);

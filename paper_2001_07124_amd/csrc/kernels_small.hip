@@ -595,6 +595,141 @@ hipError_t launch_cqr_lds(const double* y, int64_t I, int K, bool dbl, void* q_o
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Least-squares operator of the single-pass core recovery (R-PET, Algorithm 9;
+// the second sketch of eqs. Onepass / Onepass2, Section 3.1): for
+// A = Omt^T Q (S x K, Omt: I x S, Q: I x K, both column-major, S >= K),
+// P^T = (pinv(A))^T = A (A^T A)^{-1} (S x K column-major), in FP64 from the
+// normal equations: A is a Gaussian sketch of an orthonormal basis, so
+// cond(A) is a small constant (about (sqrt(S) + sqrt(K)) / (sqrt(S) - sqrt(K))
+// for S = 2K + 1) and squaring it costs nothing.  One workgroup:
+//   A = Omt^T Q                 all threads, fixed-order sums over I
+//   G = A^T A                   all threads
+//   G = L L^T, X = L^{-1}       wave 0 (as CholeskyQR); a breakdown retries
+//                               with the shift of Fukaya et al. and sets
+//                               RHOSVD_FLAG_CQR_SHIFTED
+//   B = A X^T, P^T = B X        one row of A per thread, in place
+// LDS: A (S rows of pitch K | 1), then G and X (KP16 rows of pitch KP16 + 1).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline size_t lsq_lds_doubles(int S, int K) {
+    const int KP = K | 1, KP16 = (K + 15) & ~15;
+    return static_cast<size_t>(S) * KP + 2 * static_cast<size_t>(KP16) * (KP16 + 1) + 2 * KP16 + 2;
+}
+
+template <int KB, typename T>
+__global__ __launch_bounds__(kBlock) void k_lsq_pinv(const T* __restrict__ omt,
+                                                     const T* __restrict__ q, int I, int S, int K,
+                                                     T* __restrict__ pt, uint32_t* flags) {
+    extern __shared__ __align__(16) double shd[];
+    __shared__ double diag0[RHOSVD_MAX_K];
+    __shared__ double shift_sh;
+    __shared__ int ok_sh;
+    const int KP = K | 1, KP16 = (K + 15) & ~15, GP = KP16 + 1;
+    double* A = shd;
+    double* G = A + ((static_cast<size_t>(S) * KP + 1) & ~static_cast<size_t>(1));
+    double* X = G + static_cast<size_t>(KP16) * GP;
+    const int tid = threadIdx.x, wave = wave_id();
+    for (int e = tid; e < S * K; e += kBlock) {
+        const int r = e / K, k = e - r * K;
+        const T* oc = omt + static_cast<size_t>(r) * I;
+        const T* qc = q + static_cast<size_t>(k) * I;
+        double acc = 0.0;
+        for (int i = 0; i < I; ++i) acc = fma(static_cast<double>(oc[i]), static_cast<double>(qc[i]), acc);
+        A[r * KP + k] = acc;
+    }
+    __syncthreads();
+    for (int round = 0; round < 2; ++round) {
+        for (int e = tid; e < K * K; e += kBlock) {
+            const int k1 = e / K, k2 = e - k1 * K;
+            double acc = 0.0;
+            for (int r = 0; r < S; ++r) acc = fma(A[r * KP + k1], A[r * KP + k2], acc);
+            G[k1 * GP + k2] = acc;
+            if (k1 == k2) diag0[k1] = acc;
+        }
+        __syncthreads();
+        if (round == 1) {
+            // shift s = 11 (S K + K (K + 1)) u trace(G) on the diagonal
+            if (tid == 0) {
+                double tr = 0.0;
+                for (int k = 0; k < K; ++k) tr += diag0[k];
+                shift_sh = 11.0 * (static_cast<double>(S) * K + static_cast<double>(K) * (K + 1)) *
+                           1.1102230246251565e-16 * tr;
+            }
+            __syncthreads();
+            if (tid < K) {
+                G[tid * GP + tid] += shift_sh;
+                diag0[tid] += shift_sh;
+            }
+            __syncthreads();
+        }
+        if (wave == 0) {
+            const bool okw = wave_chol_inv<KB>(G, diag0, G, X, K, GP, KP16);
+            if (threadIdx.x == 0) ok_sh = okw;
+        }
+        __syncthreads();
+        if (ok_sh) break;
+        if (round == 1) {
+            // still singular: Q is rank deficient; report and leave P^T zero
+            if (tid == 0 && flags) atomicOr(flags, RHOSVD_FLAG_CQR_SHIFTED | RHOSVD_FLAG_EVD_NOCONV);
+            for (int e = tid; e < S * K; e += kBlock) pt[e] = static_cast<T>(0);
+            return;
+        }
+        if (tid == 0 && flags) atomicOr(flags, RHOSVD_FLAG_CQR_SHIFTED);
+    }
+    // row r of A: B = A X^T (descending k: B(r, k) needs A(r, m <= k)), then
+    // P^T = B X (ascending k: needs B(r, m >= k)); X is lower triangular
+    for (int r = tid; r < S; r += kBlock) {
+        double* ar = A + static_cast<size_t>(r) * KP;
+        for (int k = K - 1; k >= 0; --k) {
+            double acc = 0.0;
+            for (int m = 0; m <= k; ++m) acc = fma(ar[m], X[k * GP + m], acc);
+            ar[k] = acc;
+        }
+        for (int k = 0; k < K; ++k) {
+            double acc = 0.0;
+            for (int m = k; m < K; ++m) acc = fma(ar[m], X[m * GP + k], acc);
+            ar[k] = acc;
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < S * K; e += kBlock) {
+        const int k = e / S, r = e - k * S;
+        pt[e] = static_cast<T>(A[r * KP + k]);
+    }
+}
+
+hipError_t launch_lsq_pinv(bool dbl, const void* omt, const void* q, int I, int S, int K, void* pt,
+                           uint32_t* flags, hipStream_t s) {
+    if (K < 1 || K > 64 || S < K || I < 1) return hipErrorInvalidValue;
+    const size_t lds = lsq_lds_doubles(S, K) * sizeof(double);
+    if (lds + kStaticLdsMargin > kLdsLimit) return hipErrorInvalidValue;
+#define RH_LSQ_CASE(KBV)                                                                         \
+    case KBV:                                                                                    \
+        if (dbl)                                                                                 \
+            hipLaunchKernelGGL((k_lsq_pinv<KBV, double>), dim3(1), dim3(kBlock), lds, s,          \
+                               static_cast<const double*>(omt), static_cast<const double*>(q), I, \
+                               S, K, static_cast<double*>(pt), flags);                           \
+        else                                                                                     \
+            hipLaunchKernelGGL((k_lsq_pinv<KBV, float>), dim3(1), dim3(kBlock), lds, s,           \
+                               static_cast<const float*>(omt), static_cast<const float*>(q), I,   \
+                               S, K, static_cast<float*>(pt), flags);                            \
+        break;
+    switch ((K + 7) & ~7) {
+        RH_LSQ_CASE(8)
+        RH_LSQ_CASE(16)
+        RH_LSQ_CASE(24)
+        RH_LSQ_CASE(32)
+        RH_LSQ_CASE(40)
+        RH_LSQ_CASE(48)
+        RH_LSQ_CASE(56)
+        RH_LSQ_CASE(64)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef RH_LSQ_CASE
+    return hipGetLastError();
+}
+
 // 1 / x and 1 / sqrt(x) from the hardware estimates with one Newton step.
 __device__ __forceinline__ double rcp_nr(double x) {
     const double y = __builtin_amdgcn_rcp(x);
@@ -624,22 +759,27 @@ __device__ __forceinline__ double rsq_nr(double x) {
 //      points with at most j eigenvalues below, and the group keeps the
 //      eighth that holds lambda_j; 18 steps take the Gershgorin interval to
 //      about 1e-16 of norm(T).
-//   3. wave 0, lane j = eigenvalue j: two steps of inverse iteration from a
-//      fixed pseudo-random start, each a solve with T - lambda_j I factored
-//      by Gaussian elimination with row interchanges (the factor kept in LDS,
-//      the vector in registers), normalised, then Gram-Schmidt against the
-//      earlier vectors of its cluster (eigenvalues closer than 1e-3 norm(T),
-//      as in dstein).
+//   3. wave 0, lane j = eigenvalue j: inverse iteration from a fixed
+//      pseudo-random unit start, each step a solve with T - lambda_j I
+//      factored by Gaussian elimination with row interchanges (the factor
+//      kept in LDS, the vector in registers), normalised, then Gram-Schmidt
+//      against the earlier vectors of its cluster; a second (third) step only
+//      while some vector grew by less than 1e11 / norm(T), i.e. its residual
+//      is above 1e-11 norm(T).  With the shift accurate to rounding one solve
+//      leaves the other directions at about eps norm(T) / gap, so only
+//      eigenvalues closer than 1e-4 norm(T) form a cluster (dstein's 1e-3
+//      would also sweep in well separated ones).
 //   4. wave 0: z <- H_0 ... H_{K-3} z.
-//   5. convergence check on T: the residual norm(T z - lambda z) and the
-//      orthogonality of the vectors against 1e-10 norm(T) and 1e-10; a miss
-//      sets RHOSVD_FLAG_EVD_NOCONV.
+//   5. convergence check on T: the residual norm(T z - lambda z) against
+//      1e-10 norm(T), and the orthogonality of each vector to its neighbours
+//      and its cluster against 1e-10; a miss sets RHOSVD_FLAG_EVD_NOCONV.
 // Outputs: v (K x K column-major, column r the eigenvector of the r-th largest
 // eigenvalue) and lambda (descending), or with FACTOR the factor step on them
 // in the same launch.  LDS: evd_tri_lds_doubles(K), then the eigenpairs.
 // ---------------------------------------------------------------------------
-constexpr int kTriIters = 2;   // each step shrinks the error by about eps norm(T) / gap
-constexpr int kBisectSteps = 18;
+constexpr int kTriMaxIters = 3;    // solves of inverse iteration, while some vector grows too little
+constexpr int kBisectSteps = 18;   // the Gershgorin interval to ~1e-16 norm(T)
+constexpr double kClusterGap = 1e-4;  // Gram-Schmidt within gaps below this, relative to norm(T)
 constexpr int kTriP = RHOSVD_MAX_K / 2;   // row pitch of the LDS vectors (64 >= K)
 
 __host__ __device__ inline size_t evd_tri_lds_doubles(int K) {
@@ -739,12 +879,13 @@ __device__ __forceinline__ void hqr_body(const double* __restrict__ y, int I, in
             if (j >= K) break;
             const int ow = jc & 3, og = jc >> 2;
             if (wave == ow) {
-                double s2 = 0.0;
+                double s4[4] = {0.0, 0.0, 0.0, 0.0};     // four independent chains
 #pragma unroll
                 for (int r = 0; r < RPL; ++r) {
                     const double x = t + 16 * r >= j ? a[m][r] : 0.0;
-                    s2 = fma(x, x, s2);
+                    s4[r & 3] = fma(x, x, s4[r & 3]);
                 }
+                const double s2 = (s4[0] + s4[1]) + (s4[2] + s4[3]);
                 const double n2 = readlane_d(row16_total(s2), 16 * og);
                 const double ajj = readlane_d(a[m][m], 16 * og + jc);   // row j: t = jc, r = m
                 const double alpha = (ajj > 0.0 ? -1.0 : 1.0) * sqrt(n2);
@@ -772,10 +913,10 @@ __device__ __forceinline__ void hqr_body(const double* __restrict__ y, int I, in
             // after jc (columns past K are zero and stay zero)
 #pragma unroll
             for (int mm = m; mm < NS; ++mm) {
-                double d = 0.0;
+                double d4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int r = 0; r < RPL; ++r) d = fma(v[r], a[mm][r], d);
-                d = row16_total(d) * tau;
+                for (int r = 0; r < RPL; ++r) d4[r & 3] = fma(v[r], a[mm][r], d4[r & 3]);
+                double d = row16_total((d4[0] + d4[1]) + (d4[2] + d4[3])) * tau;
                 if (mm == m) d = cw > jc ? d : 0.0;
 #pragma unroll
                 for (int r = 0; r < RPL; ++r) a[mm][r] = fma(-d, v[r], a[mm][r]);
@@ -804,10 +945,10 @@ __device__ __forceinline__ void hqr_body(const double* __restrict__ y, int I, in
             for (int r = 0; r < RPL; ++r) v[r] = V[j * VP + t + 16 * r];
 #pragma unroll
             for (int mm = m; mm < NS; ++mm) {
-                double d = 0.0;
+                double d4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int r = 0; r < RPL; ++r) d = fma(v[r], q[mm][r], d);
-                d = row16_total(d) * tau;
+                for (int r = 0; r < RPL; ++r) d4[r & 3] = fma(v[r], q[mm][r], d4[r & 3]);
+                double d = row16_total((d4[0] + d4[1]) + (d4[2] + d4[3])) * tau;
                 if (mm == m) d = cw >= jc ? d : 0.0;
 #pragma unroll
                 for (int r = 0; r < RPL; ++r) q[mm][r] = fma(-d, v[r], q[mm][r]);
@@ -900,23 +1041,23 @@ __device__ void factor_step(int K, int K16, int I, int I16, int R, int use_v, co
     __shared__ double sgn[RHOSVD_MAX_K];
     const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
     // the padding first, then Q in its own column-major order (coalesced),
-    // eight loads in flight per thread
+    // 32 loads in flight per thread (one round up to 8192 elements)
     for (int e = tid; e < I16 * K16; e += kBlock) {
         const int i = e / K16, k = e - i * K16;
         if (i >= I || k >= K) Qs[e] = 0.0;
     }
     const int n = I * K;
-    for (int e0 = tid; e0 < n; e0 += 8 * kBlock) {
-        T v[8];
+    for (int e0 = tid; e0 < n; e0 += 32 * kBlock) {
+        T v[32];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 32; ++u) {
             const int e = e0 + u * kBlock;
             v[u] = q[e < n ? e : n - 1];
         }
         int k = e0 / I, i = e0 - k * I;
         const int dk = kBlock / I, di = kBlock - dk * I;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 32; ++u) {
             if (e0 + u * kBlock < n) Qs[i * K16 + k] = static_cast<double>(v[u]);
             i += di;
             k += dk;
@@ -1167,13 +1308,9 @@ __device__ __forceinline__ void evd_tri_body(const double* __restrict__ cin, int
             d[i] = i < K ? dd[i] : 1e300;
             e2[i] = ee[i] * ee[i];                 // ee is zero past K - 2
         }
+        auto multisect = [&](double& lo, double& hi, int j, int steps) {
 #pragma unroll 1
-        for (int jb = 0; jb < K; jb += 9 * (kBlock / kWave)) {
-            const int j = jb + 9 * wave + grpq;
-            double lo = -tn - 4.0 * pivmin - 2.2e-16 * 4.0 * K * tn - 1e-300;
-            double hi = tn + 4.0 * pivmin + 2.2e-16 * 4.0 * K * tn + 1e-300;
-#pragma unroll 1
-            for (int st = 0; st < kBisectSteps; ++st) {
+            for (int st = 0; st < steps; ++st) {
                 // point sub + 1 of the 8-way split (point 8 is hi itself)
                 const double h = (hi - lo) * 0.125;
                 const double xa = lo + (sub + 1) * h;
@@ -1193,7 +1330,18 @@ __device__ __forceinline__ void evd_tri_body(const double* __restrict__ cin, int
                 hi = nle == 7 ? hi : lo + (nle + 1) * h;
                 lo = nlo;
             }
-            if (sub == 0 && grpq < 9 && j < K) lam[j] = 0.5 * (lo + hi);
+        };
+        // eigenvalue j of round r: jb = 36 r (K <= 64: two rounds at most)
+        constexpr int kPerRound = 9 * (kBlock / kWave);
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int j = kPerRound * r + 9 * wave + grpq;
+            double lo = -tn - 4.0 * pivmin - 2.2e-16 * 4.0 * K * tn - 1e-300;
+            double hi = tn + 4.0 * pivmin + 2.2e-16 * 4.0 * K * tn + 1e-300;
+            if (kPerRound * r < K) {
+                multisect(lo, hi, j, kBisectSteps);
+                if (sub == 0 && grpq < 9 && j < K) lam[j] = 0.5 * (lo + hi);
+            }
         }
     }
     __syncthreads();
@@ -1202,7 +1350,7 @@ __device__ __forceinline__ void evd_tri_body(const double* __restrict__ cin, int
     if (wave == 0) {
         const double tn = stats[0];
         const double tiny = 2.2e-16 * fmax(tn, 1e-300);      // pivot floor of T - lambda I
-        const double ctol = 1e-3 * tn;                         // cluster distance
+        const double ctol = kClusterGap * tn;                  // cluster distance
         const int jl = lane < K ? lane : K - 1;
         const double lj = lam[jl];
         // cluster id: the number of gaps above ctol below this eigenvalue;
@@ -1215,10 +1363,23 @@ __device__ __forceinline__ void evd_tri_body(const double* __restrict__ cin, int
         double* u2 = lu + K * kWave;
         double* u3 = lu + 2 * K * kWave;
         double z[KB];
+        {
+            double s2 = 0.0;
 #pragma unroll
-        for (int i = 0; i < KB; ++i) z[i] = i < K ? start_entry(i, jl) : 0.0;
+            for (int i = 0; i < KB; ++i) {
+                z[i] = i < K ? start_entry(i, jl) : 0.0;
+                s2 = fma(z[i], z[i], s2);
+            }
+            const double r = rsq_nr(s2);
+#pragma unroll
+            for (int i = 0; i < KB; ++i) z[i] *= r;
+        }
+        // a solve of (T - lambda I) x = z with norm(z) = 1 leaves z' = x / norm(x)
+        // with residual norm(T z' - lambda z') = 1 / norm(x): the vector has
+        // converged when norm(x) >= 1e11 / norm(T)
+        const double grow2 = 1e22 / fmax(tn * tn, 1e-300);
 #pragma unroll 1
-        for (int it = 0; it < kTriIters; ++it) {
+        for (int it = 0; it < kTriMaxIters; ++it) {
             // forward: elimination with row interchanges (branch-free), the
             // same operations applied to z; rows past K are left alone
             double ca = dd[0] - lj, cb = ee[0], cd = 0.0;
@@ -1265,6 +1426,7 @@ __device__ __forceinline__ void evd_tri_body(const double* __restrict__ cin, int
             double nn = 0.0;
 #pragma unroll
             for (int i = 0; i < KB; ++i) nn = fma(z[i], z[i], nn);
+            const bool conv = !(lane < K) || nn >= grow2;
             double inv = rsq_nr(nn);
 #pragma unroll
             for (int i = 0; i < KB; ++i) z[i] *= inv;
@@ -1285,9 +1447,10 @@ __device__ __forceinline__ void evd_tri_body(const double* __restrict__ cin, int
                     }
                 }
                 const bool mate = lane > m && lane < K && cid == __builtin_amdgcn_readlane(cid, m);
-                double dot = 0.0;
+                double d4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int i = 0; i < KB; ++i) dot = fma(zs[m * kTriP + i], z[i], dot);
+                for (int i = 0; i < KB; ++i) d4[i & 3] = fma(zs[m * kTriP + i], z[i], d4[i & 3]);
+                const double dot = (d4[0] + d4[1]) + (d4[2] + d4[3]);
                 if (mate) {
 #pragma unroll
                     for (int i = 0; i < KB; ++i) z[i] = fma(-dot, zs[m * kTriP + i], z[i]);
@@ -1299,28 +1462,40 @@ __device__ __forceinline__ void evd_tri_body(const double* __restrict__ cin, int
             inv = rsq_nr(nn);
 #pragma unroll
             for (int i = 0; i < KB; ++i) z[i] *= inv;
+            if (__ballot(!conv) == 0ull) break;           // wave-uniform
         }
-        // convergence: residual of T z - lambda z and orthogonality of the
-        // vectors, both against norm(T) (about 1e-16 when the iteration
-        // succeeded; the back-transformation below is orthogonal)
+        // convergence check: residual norm(T z - lambda z) against norm(T),
+        // and orthogonality to the neighbouring vectors and to the cluster's
+        // (vectors of eigenvalues further apart than the cluster distance
+        // are orthogonal to about eps norm(T) / gap by construction)
         {
-            double res = 0.0;
+            double tz[KB];
 #pragma unroll
             for (int i = 0; i < KB; ++i) {
+                double t = 0.0;
                 if (i < K) {
-                    double t = fma(dd[i] - lj, z[i], 0.0);
+                    t = dd[i] * z[i];
                     if (i > 0) t = fma(ee[i - 1], z[i - 1], t);
                     if (i + 1 < KB && i + 1 < K) t = fma(ee[i], z[i + 1], t);
-                    res = fmax(res, fabs(t));
                 }
+                tz[i] = t;
             }
+            double res = 0.0;
+#pragma unroll
+            for (int i = 0; i < KB; ++i) res = fmax(res, fabs(fma(-lj, z[i], tz[i])));
             if (lane < K) {
 #pragma unroll
                 for (int i = 0; i < KB; ++i) zs[lane * kTriP + i] = z[i];
             }
+            // cluster of this eigenvalue: [cs, ce] from the mates mask
+            int cs = jl, ce = jl;
+            while (cs > 0 && ((mates >> (cs - 1)) & 1ull)) --cs;
+            while (ce + 1 < K && ((mates >> ce) & 1ull)) ++ce;
+            const int mlo = cs < jl - 1 ? cs : (jl > 0 ? jl - 1 : 0);
+            const int mhi = ce > jl + 1 ? ce : (jl + 1 < K ? jl + 1 : K - 1);
             double orth = 0.0;
 #pragma unroll 1
-            for (int m = 0; m < K; ++m) {
+            for (int m = mlo; m <= mhi; ++m) {
                 double dq[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int i = 0; i < KB; i += 2) {
@@ -1329,7 +1504,7 @@ __device__ __forceinline__ void evd_tri_body(const double* __restrict__ cin, int
                     dq[(i + 1) & 3] = fma(c2.y, z[i + 1], dq[(i + 1) & 3]);
                 }
                 const double dot = (dq[0] + dq[1]) + (dq[2] + dq[3]);
-                orth = fmax(orth, fabs(dot - (m == lane ? 1.0 : 0.0)));
+                orth = fmax(orth, fabs(dot - (m == jl ? 1.0 : 0.0)));
             }
             if (lane >= K) res = orth = 0.0;
 #pragma unroll

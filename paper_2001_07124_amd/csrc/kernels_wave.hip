@@ -15,6 +15,15 @@
 // Workgroups are 4 independent waves; the only barriers are at the start
 // (M fragments) and at the end (cross-wave reduction of the partials).
 //
+// Tall modes (RS = 4, 256 < I <= 64 IBT): the four waves of a workgroup
+// share each block, wave w holding the row blocks w IBW .. (w + 1) IBW - 1.
+// The sketch needs no exchange (each wave accumulates its own rows of Y);
+// in the power step and the mode-n product the waves' partial Z = S_w^T M_w
+// are summed through LDS in wave order, one barrier per block (two exchange
+// buffers alternate, so a wave never overwrites a buffer another still
+// reads), and every wave continues with the same Z.  Wave 0 writes the
+// mode-n product and forms its Gram.
+//
 // Matrix-core precision (CompType):
 //   CT_F32     four v_mfma_f32_16x16x4_f32 per 16x16x16 step
 //   CT_BF16    one v_mfma_f32_16x16x16_bf16 (inputs rounded to bf16)
@@ -224,8 +233,9 @@ __device__ __forceinline__ f32x4 omega4(uint64_t e0, uint32_t mode, uint32_t tag
 // S(16 f + 4 g + e, j0 + c), zero outside the tensor.
 template <int MAXIB>
 __device__ __forceinline__ void load_block(const WGeom& g, const float* __restrict__ src,
-                                           int64_t blk, int l16, int quad, f32x4 (&sf)[MAXIB]) {
-    const int IB = g.IB, I = static_cast<int>(g.I);
+                                           int64_t blk, int l16, int quad, f32x4 (&sf)[MAXIB],
+                                           int fb0, int IB) {
+    const int I = static_cast<int>(g.I);
     const int64_t L = g.L, J = g.J;
     const int64_t j0 = blk * 16;
     const bool cok = j0 + l16 < J;
@@ -234,7 +244,7 @@ __device__ __forceinline__ void load_block(const WGeom& g, const float* __restri
 #pragma unroll
         for (int f = 0; f < MAXIB; ++f) {
             if (f < IB) {
-                const int i0 = 16 * f + 4 * quad;
+                const int i0 = 16 * (fb0 + f) + 4 * quad;
                 if (cok && i0 < I)
                     sf[f] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(colp + i0));
                 else
@@ -253,7 +263,7 @@ __device__ __forceinline__ void load_block(const WGeom& g, const float* __restri
             if (f < IB) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int i = 16 * f + 4 * quad + e;
+                    const int i = 16 * (fb0 + f) + 4 * quad + e;
                     sf[f][e] = (cok && i < I) ? src[colbase + L * i] : 0.0f;
                 }
             }
@@ -264,7 +274,7 @@ __device__ __forceinline__ void load_block(const WGeom& g, const float* __restri
 // IBT / NBT bound the row blocks of the block and the 16-column blocks of
 // the K-wide operand; EXACT variants fix IB = IBT and NB = NBT at compile
 // time (no masks, no spare accumulators).
-template <int OP, int CT, int IBT, int NBT, bool EXACT>
+template <int OP, int CT, int IBT, int NBT, bool EXACT, int RS>
 __global__ __launch_bounds__(kBlock, 1) void k_wave(WGeom g, StreamArgs a, int want_ss,
                                                     int want_gram) {
     constexpr int DCT = Sides<CT>::data;    // streamed tensor
@@ -276,14 +286,18 @@ __global__ __launch_bounds__(kBlock, 1) void k_wave(WGeom g, StreamArgs a, int w
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l16 = lane & 15, quad = lane >> 4;
-    const int IB = EXACT ? IBT : g.IB;
+    // IB: row blocks of the mode; this wave holds nf of them from fb0 on
+    const int IB = EXACT ? IBT * RS : g.IB;
     const int NB = EXACT ? NBT : g.NB;
+    const int IBW = RS == 1 ? IB : (EXACT ? IBT : g.IBW);
+    const int fb0 = RS == 1 ? 0 : wave * IBW;
+    const int nf = RS == 1 ? IB : (IB - fb0 < IBW ? (IB - fb0 > 0 ? IB - fb0 : 0) : IBW);
     const int K = g.K, I = static_cast<int>(g.I);
     const int64_t L = g.L, J = g.J;
 
     FO* qfr = reinterpret_cast<FO*>(smem);
     unsigned char* scr = smem + g.q_bytes + static_cast<size_t>(wave) * g.scr_bytes;
-    const int plane_elems = IB * 256;
+    const int plane_elems = IBW * 256;
 
     // M fragments (B operand of P2): fragment (f, nb), lane (r, g) holds
     // M(16 f + 4 g + e, 16 nb + r).
@@ -322,25 +336,30 @@ __global__ __launch_bounds__(kBlock, 1) void k_wave(WGeom g, StreamArgs a, int w
     double ss = 0.0;
 
     const float* __restrict__ src = static_cast<const float*>(a.src);
-    const int64_t wid = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + wave;
-    const int64_t nw = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
+    // RS = 1: one block per wave; RS = 4: one block per workgroup
+    const int64_t wid = RS == 1 ? static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + wave
+                                : static_cast<int64_t>(blockIdx.x);
+    const int64_t nw = RS == 1 ? static_cast<int64_t>(gridDim.x) * (kBlock / kWave)
+                               : static_cast<int64_t>(gridDim.x);
     const bool jal = (J & 3) == 0;
+    f32x4* xr = reinterpret_cast<f32x4*>(smem + g.xr_off);   // [2][RS][NBT][64] when RS > 1
+    int par = 0;
 
     // software pipeline: the next block's loads are in flight while this
     // block is processed (one wave per SIMD, so the wave hides its own latency)
     f32x4 sf[IBT], sfn[IBT];
-    if (wid < g.nblocks) load_block<IBT>(g, src, wid, l16, quad, sf);
+    if (wid < g.nblocks) load_block<IBT>(g, src, wid, l16, quad, sf, fb0, nf);
     for (int64_t blk = wid; blk < g.nblocks; blk += nw) {
         const int64_t j0 = blk * 16;
         const int cv = static_cast<int>(J - j0 < 16 ? J - j0 : 16);
         const bool cok = l16 < cv;
-        if (blk + nw < g.nblocks) load_block<IBT>(g, src, blk + nw, l16, quad, sfn);
+        if (blk + nw < g.nblocks) load_block<IBT>(g, src, blk + nw, l16, quad, sfn, fb0, nf);
 
         if (want_ss) {
             float part = 0.0f;
 #pragma unroll
             for (int f = 0; f < IBT; ++f)
-                if (f < IB)
+                if (f < nf)
 #pragma unroll
                     for (int e = 0; e < 4; ++e) part = fmaf(sf[f][e], sf[f][e], part);
             ss += static_cast<double>(part);
@@ -352,15 +371,37 @@ __global__ __launch_bounds__(kBlock, 1) void k_wave(WGeom g, StreamArgs a, int w
         for (int nb = 0; nb < NBT; ++nb) z[nb] = zero4<f32x4>();
 #pragma unroll
         for (int f = 0; f < IBT; ++f) {
-            if (f < IB) {
+            if (f < nf) {
                 const F sbf = make_frag<DCT>(sf[f]);
                 if (OP != OP_SKETCH) {
 #pragma unroll
                     for (int nb = 0; nb < NBT; ++nb)
-                        if (nb < NB) z[nb] = mma(sbf, qfr[(f * NB + nb) * 64 + lane], z[nb]);
+                        if (nb < NB) z[nb] = mma(sbf, qfr[((fb0 + f) * NB + nb) * 64 + lane], z[nb]);
                 }
                 if (OP != OP_TTM) scr_put_frag<DCT>(scr, plane_elems, f, quad, l16, sbf);
             }
+        }
+        if constexpr (RS > 1 && OP != OP_SKETCH) {
+            // Z = sum over the waves' rows, in wave order
+            f32x4* xb = xr + static_cast<size_t>(par) * RS * NBT * 64;
+#pragma unroll
+            for (int nb = 0; nb < NBT; ++nb)
+                if (nb < NB) xb[(wave * NBT + nb) * 64 + lane] = z[nb];
+            __syncthreads();
+#pragma unroll
+            for (int nb = 0; nb < NBT; ++nb) {
+                if (nb < NB) {
+                    f32x4 t = xb[nb * 64 + lane];
+#pragma unroll
+                    for (int w = 1; w < RS; ++w) {
+                        const f32x4 o = xb[(w * NBT + nb) * 64 + lane];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) t[e] += o[e];
+                    }
+                    z[nb] = t;
+                }
+            }
+            par ^= 1;
         }
 
         // ---- P1: Y += S_blk W with W = Omega (sketch) or Z (power step)
@@ -377,13 +418,21 @@ __global__ __launch_bounds__(kBlock, 1) void k_wave(WGeom g, StreamArgs a, int w
 #pragma unroll
                             for (int e = 0; e < 4; ++e) {
                                 const int64_t j = j0 + 4 * quad + e;
-                                w[e] = j < J ? omega_entry<float>(a.seed, a.mode, a.tag, j, r, L, g.T, J)
-                                             : 0.0f;
+                                w[e] = j >= J ? 0.0f
+                                       : a.kr.nq ? kr_entry<float>(a.kr, j, r)
+                                                 : omega_entry<float>(a.seed, a.mode, a.tag, j, r, L, g.T, J);
                             }
                         } else if (r < K) {
                             const uint64_t e0 = static_cast<uint64_t>(r) * static_cast<uint64_t>(J) +
                                                 static_cast<uint64_t>(j0 + 4 * quad);
-                            w = omega4(e0, a.mode, a.tag, a.seed, jal);
+                            if (a.kr.nq) {
+                                float t4[4];
+                                kr_entry4<float>(a.kr, j0 + 4 * quad, r, t4);
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) w[e] = t4[e];
+                            } else {
+                                w = omega4(e0, a.mode, a.tag, a.seed, jal);
+                            }
 #pragma unroll
                             for (int e = 0; e < 4; ++e)
                                 if (4 * quad + e >= cv) w[e] = 0.0f;
@@ -397,7 +446,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_wave(WGeom g, StreamArgs a, int w
             wave_lds_sync();
 #pragma unroll
             for (int f = 0; f < IBT; ++f) {
-                if (f < IB) {
+                if (f < nf) {
                     const F t = scr_get_frag<DCT>(scr, plane_elems, f, quad, l16);
 #pragma unroll
                     for (int nb = 0; nb < NBT; ++nb)
@@ -408,7 +457,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_wave(WGeom g, StreamArgs a, int w
         }
 
         // ---- mode-n product output (folded) and its Gram
-        if (OP == OP_TTM) {
+        if (OP == OP_TTM && (RS == 1 || wave == 0)) {
             if (want_gram) {
                 FG zg[NBT];
 #pragma unroll
@@ -472,7 +521,20 @@ __global__ __launch_bounds__(kBlock, 1) void k_wave(WGeom g, StreamArgs a, int w
     float* red = reinterpret_cast<float*>(smem);
     const size_t gidx = blockIdx.x;
     const int I_pad = IB * 16, K_pad = NB * 16;
-    if (OP != OP_TTM) {
+    if (OP != OP_TTM && RS > 1) {
+        // the waves hold disjoint rows: each writes its own
+#pragma unroll
+        for (int f = 0; f < AI; ++f)
+#pragma unroll
+            for (int nb = 0; nb < AN; ++nb)
+                if (f < nf && nb < NB)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        red[(16 * nb + l16) * I_pad + 16 * (fb0 + f) + 4 * quad + e] = acc[f][nb][e];
+        __syncthreads();
+        float* __restrict__ py = static_cast<float*>(a.part_y) + gidx * K_pad * I_pad;
+        for (int e = tid; e < K_pad * I_pad; e += kBlock) py[e] = red[e];
+    } else if (OP != OP_TTM) {
         for (int w = 0; w < kBlock / kWave; ++w) {
             if (wave == w) {
 #pragma unroll
@@ -532,6 +594,15 @@ __global__ __launch_bounds__(kBlock, 1) void k_wave(WGeom g, StreamArgs a, int w
 static const int kExact[][2] = {{13, 3}, {3, 2}, {13, 2}, {7, 1}};
 static const int kGeneric[][2] = {{4, 4}, {8, 4}, {16, 2}, {16, 4}};
 constexpr int kNumExact = 4, kNumGeneric = 4;
+// Tall modes, four waves per block (row blocks per wave, operand blocks):
+// an exact 500-row case (IB = 32, NB = 2), then bounded generic ones.
+static const int kTall[][3] = {{8, 2, 1}, {8, 2, 0}, {6, 3, 0}};
+constexpr int kNumTall = 3;
+constexpr int kTallRS = 4;
+constexpr int kTallVariant0 = 8;    // variant index of kTall[0]
+
+static bool plan_wave_tall(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu,
+                           WGeom* g);
 
 bool plan_wave(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu, WGeom* g) {
     if (L < 1 || I < 1 || T < 1 || K < 1) return false;
@@ -545,7 +616,10 @@ bool plan_wave(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_c
                 var = kNumExact + v;
                 break;
             }
-    if (var < 0) return false;
+    if (var < 0) return plan_wave_tall(op, ct, L, I, T, K, num_cu, g);
+    g->rs = 1;
+    g->IBW = IB;
+    g->xr_off = 0;
     g->L = L;
     g->I = I;
     g->T = T;
@@ -578,11 +652,59 @@ bool plan_wave(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_c
     return true;
 }
 
-template <int OP, int CT, int MI, int MN, bool EX>
+static bool plan_wave_tall(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu,
+                           WGeom* g) {
+    const int IB = static_cast<int>((I + 15) / 16), NB = (K + 15) / 16;
+    const int ibw = (IB + kTallRS - 1) / kTallRS;
+    const size_t frag = (ct == CT_BF16) ? 8 : 16;
+    const size_t comp = (ct == CT_F32) ? 4 : 2;
+    const size_t planes = (ct == CT_BF16X3) ? 2 : 1;
+    for (int v = 0; v < kNumTall; ++v) {
+        const int ibt = kTall[v][0], nbt = kTall[v][1];
+        const bool exact = kTall[v][2] != 0;
+        if (exact ? (IB != kTallRS * ibt || NB != nbt) : (ibw > ibt || NB > nbt)) continue;
+        const size_t q_bytes = (op != OP_SKETCH) ? static_cast<size_t>(IB) * NB * 64 * frag : 0;
+        size_t scr = 0;
+        if (op != OP_TTM) scr = static_cast<size_t>(ibw) * 256 * comp * planes;
+        else if (L > 1) scr = static_cast<size_t>(NB) * 16 * 17 * 4;
+        const size_t scr_bytes = (scr + 15) / 16 * 16;
+        const size_t xr_off = q_bytes + 4 * scr_bytes;
+        const size_t xr = (op != OP_SKETCH) ? static_cast<size_t>(2) * kTallRS * nbt * 64 * 16 : 0;
+        size_t lds = xr_off + xr;
+        size_t red = static_cast<size_t>(IB) * 16 * NB * 16 * 4;
+        const size_t redg = static_cast<size_t>(NB) * 16 * NB * 16 * 4;
+        if (redg > red) red = redg;
+        if (red > lds) lds = red;
+        if (lds + kStaticLdsMargin > kLdsLimit) continue;
+        g->L = L;
+        g->I = I;
+        g->T = T;
+        g->J = L * T;
+        g->K = K;
+        g->IB = IB;
+        g->NB = NB;
+        g->ct = ct;
+        g->variant = kTallVariant0 + v;
+        g->q_bytes = q_bytes;
+        g->scr_bytes = scr_bytes;
+        g->lds_bytes = lds;
+        g->rs = kTallRS;
+        g->IBW = exact ? ibt : ibw;
+        g->xr_off = xr_off;
+        g->nblocks = (g->J + 15) / 16;
+        const int64_t cap = num_cu > 0 ? num_cu : 256;
+        g->grid = static_cast<int>(g->nblocks < cap ? g->nblocks : cap);
+        g->vec4 = (L == 1 && I % 4 == 0) ? 1 : 0;
+        return true;
+    }
+    return false;
+}
+
+template <int OP, int CT, int MI, int MN, bool EX, int RS = 1>
 static hipError_t launch_wave_t(const WGeom& g, const StreamArgs& a, hipStream_t s) {
     const int want_ss = a.part_ss != nullptr;
     const int want_gram = a.part_g != nullptr;
-    auto fn = k_wave<OP, CT, MI, MN, EX>;
+    auto fn = k_wave<OP, CT, MI, MN, EX, RS>;
     hipLaunchKernelGGL(fn, dim3(g.grid), dim3(kBlock), g.lds_bytes, s, g, a, want_ss, want_gram);
     return hipGetLastError();
 }
@@ -597,7 +719,10 @@ static hipError_t launch_wave_ct(const WGeom& g, const StreamArgs& a, hipStream_
         case 4: return launch_wave_t<OP, CT, 4, 4, false>(g, a, s);
         case 5: return launch_wave_t<OP, CT, 8, 4, false>(g, a, s);
         case 6: return launch_wave_t<OP, CT, 16, 2, false>(g, a, s);
-        default: return launch_wave_t<OP, CT, 16, 4, false>(g, a, s);
+        case 7: return launch_wave_t<OP, CT, 16, 4, false>(g, a, s);
+        case kTallVariant0 + 0: return launch_wave_t<OP, CT, 8, 2, true, kTallRS>(g, a, s);
+        case kTallVariant0 + 1: return launch_wave_t<OP, CT, 8, 2, false, kTallRS>(g, a, s);
+        default: return launch_wave_t<OP, CT, 6, 3, false, kTallRS>(g, a, s);
     }
 }
 

@@ -58,7 +58,7 @@ struct Carver {
 constexpr int kMaxSmallK = 64;    // the QR and EVD kernels keep K x K in LDS / registers
 constexpr int kSumsqBlocks = 256;
 // Omega streams of RP-HOOI (Algorithm 7): the Gaussian start and the sketches
-constexpr uint32_t kTagHooiInit = 5, kTagHooiSketch = 6;
+constexpr uint32_t kTagHooiInit = 5, kTagHooiSketch = 6, kTagRpetCore = 3, kTagKr = 4;
 // The single-pass sketch of all modes regenerates Omega rows per tile: it is
 // used while that costs at most this many normals per element of X (beyond
 // it the per-mode passes, which generate each row once, are faster).
@@ -134,6 +134,7 @@ struct Problem {
     int ct_sketch = 0, ct_power = 0, ct_ttm = 0, ct_trunc = 0;
     int kernels = RHOSVD_KERNELS_AUTO;
     bool explicit_error = false;
+    bool kr = false;             // structured (Khatri-Rao) sketch
 };
 
 struct Step {
@@ -160,6 +161,19 @@ struct Plan {
     // per p != n, natural order) and the sketch of its n-unfolding
     Pass hchain[RHOSVD_MAX_ORDER][RHOSVD_MAX_ORDER];
     Pass hsk[RHOSVD_MAX_ORDER];
+    // R-PET: the core sketch X x_n Omt_n^T (widths S_n) and the recovery
+    // H x_n pinv(Omt_n^T Q_n), each a chain of mode-n products
+    int Sn[RHOSVD_MAX_ORDER] = {};
+    Pass gp0[RHOSVD_MAX_ORDER];
+    Pass gp1[RHOSVD_MAX_ORDER];
+    int64_t omt = 0, pst = 0;
+    // structured sketch: per step the tables of the other modes in the
+    // digit order of the sketched view (its storage order), at offsets
+    // kr_off (elements) into one region of kr_elems
+    int64_t kr_elems = 0;
+    int kr_mode[RHOSVD_MAX_ORDER][RHOSVD_MAX_ORDER - 1] = {};
+    int64_t kr_ext[RHOSVD_MAX_ORDER][RHOSVD_MAX_ORDER - 1] = {};
+    int64_t kr_off[RHOSVD_MAX_ORDER][RHOSVD_MAX_ORDER - 1] = {};
     // R-STHOSVD in the natural mode order keeps the current tensor with its
     // next mode first: (I_n, ..., I_N, R_1, ..., R_{n-1}).  Every unfolding is
     // then contiguous (L = 1), its columns are in the cyclic order that
@@ -185,13 +199,20 @@ int32_t validate(const rhosvd_tensor* x, const rhosvd_params* p, Problem* pr, bo
     if (x->order < 2 || x->order > RHOSVD_MAX_ORDER || !x->dims) return RHOSVD_EINVAL;
     if (x->dtype != RHOSVD_F32 && x->dtype != RHOSVD_F64) return RHOSVD_EINVAL;
     if (need_data && !x->data) return RHOSVD_EINVAL;
-    if (p->algo != RHOSVD_RP_HOSVD && p->algo != RHOSVD_R_STHOSVD && p->algo != RHOSVD_RP_HOOI)
+    if (p->algo != RHOSVD_RP_HOSVD && p->algo != RHOSVD_R_STHOSVD && p->algo != RHOSVD_RP_HOOI &&
+        p->algo != RHOSVD_R_PET)
         return RHOSVD_EINVAL;
     if (p->algo == RHOSVD_RP_HOOI && p->oversample != 0) return RHOSVD_EINVAL;
+    if (p->algo == RHOSVD_R_PET && p->power_iters != 0) return RHOSVD_EINVAL;
     if (!p->ranks || p->oversample < 0 || p->power_iters < 0 || p->power_iters > 8)
         return RHOSVD_EINVAL;
-    if ((p->flags & ~static_cast<uint32_t>(RHOSVD_OPT_EXPLICIT_ERROR)) != 0) return RHOSVD_EINVAL;
-    pr->explicit_error = (p->flags & RHOSVD_OPT_EXPLICIT_ERROR) != 0;
+    if ((p->flags & ~static_cast<uint32_t>(RHOSVD_OPT_EXPLICIT_ERROR | RHOSVD_OPT_KR_SKETCH)) != 0)
+        return RHOSVD_EINVAL;
+    pr->kr = (p->flags & RHOSVD_OPT_KR_SKETCH) != 0;
+    if (pr->kr && p->algo != RHOSVD_R_STHOSVD && p->algo != RHOSVD_RP_HOSVD) return RHOSVD_EINVAL;
+    // R-PET's core is recovered from a sketch, not X x_n U_n^T, so the
+    // identity E of Section 5.1 does not hold for it: always the explicit one
+    pr->explicit_error = (p->flags & RHOSVD_OPT_EXPLICIT_ERROR) != 0 || p->algo == RHOSVD_R_PET;
     pr->N = x->order;
     pr->dbl = x->dtype == RHOSVD_F64;
     pr->elem = pr->dbl ? sizeof(double) : sizeof(float);
@@ -260,6 +281,22 @@ void size_resid(Plan* pl) {
     }
 }
 
+// Tables of the structured sketch of step s (mode n) for the current
+// extents d: the other modes in the order their indices vary along the
+// sketched view's columns (the view's storage order).
+void plan_kr(Plan* pl, int s, int n, const int64_t* d, bool rotated, int K) {
+    const int N = pl->pr.N;
+    int q = 0;
+    for (int t = 1; t < N; ++t) {
+        const int m = rotated ? (n + t) % N : (t <= n ? t - 1 : t);
+        pl->kr_mode[s][q] = m;
+        pl->kr_ext[s][q] = d[m];
+        pl->kr_off[s][q] = pl->kr_elems;
+        pl->kr_elems += d[m] * K;
+        ++q;
+    }
+}
+
 int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
     pl->pr = pr;
     const int N = pr.N;
@@ -305,6 +342,7 @@ int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
             if (qw > pl->maxQW) pl->maxQW = qw;
         }
             if (st.K * st.J > pl->maxB) pl->maxB = st.K * st.J;
+            if (pr.kr) plan_kr(pl, s, n, d, pl->rotated, st.K);
             d[n] = st.R;
             if (s < N - 1) {
                 const int64_t sz = prod(d, 0, N);
@@ -349,6 +387,7 @@ int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
         }
         pl->qstore += IK;
         pl->mstore += static_cast<int64_t>(st.K) * st.R;
+        if (pr.kr) plan_kr(pl, n, n, d, false, st.K);
     }
     if (pr.algo == RHOSVD_RP_HOOI) {
         // chains X x_{p != n} Q_p^T and the sketches of their n-unfoldings
@@ -376,7 +415,7 @@ int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
     } else {
         int Ks[RHOSVD_MAX_ORDER];
         for (int n = 0; n < N; ++n) Ks[n] = pl->st[n].K;
-        if (pr.kernels == RHOSVD_KERNELS_AUTO &&
+        if (pr.kernels == RHOSVD_KERNELS_AUTO && !pr.kr &&
             rh::plan_allmode(N, pr.dims, Ks, num_cu, elem, &pl->am)) {
             // Omega normals generated per element of X: sum_n K_n / b_n
             double per_elem = 0.0;
@@ -390,9 +429,37 @@ int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
             }
         }
     }
-    // core chain H = X x_1 Q_1^T ... x_N Q_N^T, then G = H x_n M_n^T
+    // core chain H = X x_1 Q_1^T ... x_N Q_N^T (R-PET: the core sketch and
+    // its recovery), then G = H x_n M_n^T
     int64_t buf = 1;
-    for (int n = 0; n < N; ++n) {
+    if (pr.algo == RHOSVD_R_PET) {
+        for (int n = 0; n < N; ++n) {
+            const Step& st = pl->st[n];
+            pl->Sn[n] = static_cast<int>(std::min<int64_t>(2 * static_cast<int64_t>(st.K) + 1, st.I));
+            if (pl->Sn[n] < st.K) return RHOSVD_EUNSUPPORTED;
+            pl->omt += st.I * pl->Sn[n];
+            pl->pst += static_cast<int64_t>(pl->Sn[n]) * st.K;
+        }
+        for (int n = 0; n < N; ++n) {
+            const int64_t L = prod(d, 0, n), T = prod(d, n + 1, N);
+            if (!plan_pass(rh::OP_TTM, pr.dbl, pr.ct_ttm, L, d[n], T, pl->Sn[n], num_cu, &pl->gp0[n], pr.kernels))
+                return RHOSVD_EUNSUPPORTED;
+            track_stream(pl, pl->gp0[n], false);
+            d[n] = pl->Sn[n];
+            const int64_t sz = prod(d, 0, N);
+            if (sz > buf) buf = sz;
+        }
+        for (int n = 0; n < N; ++n) {
+            const int64_t L = prod(d, 0, n), T = prod(d, n + 1, N);
+            if (!plan_pass(rh::OP_TTM, pr.dbl, pr.ct_ttm, L, d[n], T, pl->st[n].K, num_cu, &pl->gp1[n], pr.kernels))
+                return RHOSVD_EUNSUPPORTED;
+            track_stream(pl, pl->gp1[n], false);
+            d[n] = pl->st[n].K;
+            const int64_t sz = prod(d, 0, N);
+            if (sz > buf) buf = sz;
+        }
+    }
+    for (int n = 0; n < N && pr.algo != RHOSVD_R_PET; ++n) {
         const int64_t L = prod(d, 0, n), T = prod(d, n + 1, N);
         if (!plan_pass(rh::OP_TTM, pr.dbl, pr.ct_ttm, L, d[n], T, pl->st[n].K, num_cu, &pl->gh[n], pr.kernels))
             return RHOSVD_EUNSUPPORTED;
@@ -441,6 +508,9 @@ struct Buffers {
     double* ystore;
     int* gate;
     double* part_resid;
+    void* omt;     // R-PET: Omt_n, I_n x S_n each
+    void* pst;     // R-PET: pinv(Omt_n^T Q_n)^T, S_n x K_n each
+    void* krtab;   // structured sketch tables
 };
 
 size_t carve(const Plan& pl, void* ws, Buffers* b) {
@@ -471,11 +541,54 @@ size_t carve(const Plan& pl, void* ws, Buffers* b) {
     b->pong = cv.take<void>(pl.pong * e);
     b->gate = cv.take<int>(sizeof(int));
     b->part_resid = cv.take<double>(rh::kResidGrid * sizeof(double));
+    b->omt = pl.omt ? cv.take<void>(pl.omt * e) : nullptr;
+    b->pst = pl.pst ? cv.take<void>(pl.pst * e) : nullptr;
+    b->krtab = pl.kr_elems ? cv.take<void>(pl.kr_elems * e) : nullptr;
     return cv.off + 256;
 }
 
 void* at(void* base, int64_t elems, size_t elem) {
     return static_cast<unsigned char*>(base) + static_cast<size_t>(elems) * elem;
+}
+
+// The structured sketch's arguments for step s (nq = 0: Gaussian stream).
+rh::KrArgs kr_args(const Plan& pl, const Buffers& b, int s, int K, int64_t J) {
+    rh::KrArgs k{};
+    if (!pl.pr.kr) return k;
+    k.nq = pl.pr.N - 1;
+    k.K = K;
+    k.J = J;
+    for (int q = 0; q < k.nq; ++q) {
+        k.tab[q] = at(b.krtab, pl.kr_off[s][q], pl.pr.elem);
+        k.ext[q] = static_cast<int>(pl.kr_ext[s][q]);
+    }
+    return k;
+}
+
+// Fill the tables of steps [s0, s1) (mode of step s: modes[s]), chunked by
+// the launch's descriptor limit.
+int32_t fill_kr(const Plan& pl, const Buffers& b, int s0, int s1, const int* modes, const int* Ks,
+                hipStream_t s) {
+    if (!pl.pr.kr) return RHOSVD_OK;
+    const int N = pl.pr.N;
+    rh::KrFill f{};
+    f.seed = pl.pr.seed;
+    f.tag = kTagKr;
+    for (int st = s0; st < s1; ++st) {
+        for (int q = 0; q < N - 1; ++q) {
+            rh::KrFill::Table& t = f.t[f.count++];
+            t.out = at(b.krtab, pl.kr_off[st][q], pl.pr.elem);
+            t.J = pl.kr_ext[st][q];
+            t.K = Ks[st];
+            t.word = static_cast<uint32_t>(modes[st] * N + pl.kr_mode[st][q]);
+            if (f.count == rh::KrFill::kMax) {
+                RH_HIP(rh::launch_kr_fill(pl.pr.dbl, f, s));
+                f.count = 0;
+            }
+        }
+    }
+    if (f.count) RH_HIP(rh::launch_kr_fill(pl.pr.dbl, f, s));
+    return RHOSVD_OK;
 }
 
 // q fused power steps Y = S_(n) (S_(n)^T Q), each followed by the QR
@@ -499,7 +612,9 @@ int32_t power_steps(const Plan& pl, const Buffers& b, const void* src, const Pas
 // Y = S_(n) Omega, then Q and the power steps.
 int32_t sketch_and_orthonormalize(const Plan& pl, const Buffers& b, const void* src,
                                   const Pass& gs, const Pass& gp, int mode,
-                                  uint32_t tag, bool want_norm, void* q_out, hipStream_t s) {
+                                  uint32_t tag, double* norm_dst, void* q_out, hipStream_t s,
+                                  const rh::KrArgs& kr = rh::KrArgs{}) {
+    const bool want_norm = norm_dst != nullptr;
     const bool dbl = pl.pr.dbl;
     rh::StreamArgs a{};
     a.src = src;
@@ -508,10 +623,11 @@ int32_t sketch_and_orthonormalize(const Plan& pl, const Buffers& b, const void* 
     a.seed = pl.pr.seed;
     a.mode = static_cast<uint32_t>(mode);
     a.tag = tag;
+    a.kr = kr;
     RH_HIP(launch_pass(gs, a, s));
     RH_HIP(rh::launch_reduce_y(dbl, b.part, gs.grid, static_cast<int>(gs.I), gs.K, gs.I_pad,
                                gs.K_pad, b.y, s));
-    if (want_norm) RH_HIP(rh::launch_reduce_ss(b.part_ss, gs.grid, &b.rep->norm_x2, s));
+    if (want_norm) RH_HIP(rh::launch_reduce_ss(b.part_ss, gs.grid, norm_dst, s));
     RH_HIP(rh::launch_cqr(b.y, gs.I, gs.K, dbl, q_out, b.q64, &b.rep->flags, s));
     return power_steps(pl, b, src, gp, q_out, s);
 }
@@ -535,9 +651,20 @@ int32_t run_r_sthosvd(const Plan& pl, const Buffers& b, const void* x, const rho
     const size_t e = pl.pr.elem;
     const int N = pl.pr.N;
     const void* src = x;
+    if (pl.pr.kr) {
+        int modes[RHOSVD_MAX_ORDER], Ks[RHOSVD_MAX_ORDER];
+        for (int si = 0; si < N; ++si) {
+            modes[si] = pl.st[si].n;
+            Ks[si] = pl.st[si].K;
+        }
+        const int32_t rc = fill_kr(pl, b, 0, N, modes, Ks, s);
+        if (rc != RHOSVD_OK) return rc;
+    }
     for (int si = 0; si < N; ++si) {
         const Step& st = pl.st[si];
-        int32_t rc = sketch_and_orthonormalize(pl, b, src, st.gs, st.gp, st.n, 2u, si == 0, b.qT, s);
+        int32_t rc = sketch_and_orthonormalize(pl, b, src, st.gs, st.gp, st.n, 2u,
+                                               si == 0 ? &b.rep->norm_x2 : nullptr, b.qT, s,
+                                               kr_args(pl, b, si, st.K, st.J));
         if (rc != RHOSVD_OK) return rc;
         // B = Q^T S_(n), folded, and C = B B^T
         rc = ttm(pl, st.gt, src, b.qT, b.B, b.part, s);
@@ -626,22 +753,63 @@ int32_t run_rp_hosvd(const Plan& pl, const Buffers& b, const void* x, const rhos
             if (rc != RHOSVD_OK) return rc;
         }
     } else {
+        if (pl.pr.kr) {
+            int modes[RHOSVD_MAX_ORDER], Ks[RHOSVD_MAX_ORDER];
+            for (int n = 0; n < N; ++n) {
+                modes[n] = n;
+                Ks[n] = pl.st[n].K;
+            }
+            const int32_t rc = fill_kr(pl, b, 0, N, modes, Ks, s);
+            if (rc != RHOSVD_OK) return rc;
+        }
         for (int n = 0; n < N; ++n) {
             const Step& st = pl.st[n];
-            const int32_t rc = sketch_and_orthonormalize(pl, b, x, st.gs, st.gp, n, 1u, n == 0,
-                                                         at(b.qstore, qoff[n], e), s);
+            const int32_t rc = sketch_and_orthonormalize(pl, b, x, st.gs, st.gp, n, 1u,
+                                                         n == 0 ? &b.rep->norm_x2 : nullptr,
+                                                         at(b.qstore, qoff[n], e), s,
+                                                         kr_args(pl, b, n, st.K, st.J));
             if (rc != RHOSVD_OK) return rc;
         }
     }
-    // H = X x_1 Q_1^T ... x_N Q_N^T
+    // H = X x_1 Q_1^T ... x_N Q_N^T; R-PET: the core sketch
+    // X x_1 Omt_1^T ... x_N Omt_N^T, then H x_n pinv(Omt_n^T Q_n) for all n
     const void* src = x;
     void* bufs[2] = {b.ping, b.pong};
     int cur = 0;
-    for (int n = 0; n < N; ++n) {
-        const int32_t rc = ttm(pl, pl.gh[n], src, at(b.qstore, qoff[n], e), bufs[cur], nullptr, s);
-        if (rc != RHOSVD_OK) return rc;
-        src = bufs[cur];
-        cur ^= 1;
+    if (pl.pr.algo == RHOSVD_R_PET) {
+        int64_t oo = 0, po = 0;
+        int64_t ooff[RHOSVD_MAX_ORDER], poff[RHOSVD_MAX_ORDER];
+        for (int n = 0; n < N; ++n) {
+            const Step& st = pl.st[n];
+            ooff[n] = oo;
+            poff[n] = po;
+            oo += st.I * pl.Sn[n];
+            po += static_cast<int64_t>(pl.Sn[n]) * st.K;
+            RH_HIP(rh::launch_omega_fill(dbl, pl.pr.seed, n, kTagRpetCore, st.I, pl.Sn[n],
+                                         at(b.omt, ooff[n], e), s));
+            RH_HIP(rh::launch_lsq_pinv(dbl, at(b.omt, ooff[n], e), at(b.qstore, qoff[n], e),
+                                       static_cast<int>(st.I), pl.Sn[n], st.K, at(b.pst, poff[n], e),
+                                       &b.rep->flags, s));
+        }
+        for (int n = 0; n < N; ++n) {
+            const int32_t rc = ttm(pl, pl.gp0[n], src, at(b.omt, ooff[n], e), bufs[cur], nullptr, s);
+            if (rc != RHOSVD_OK) return rc;
+            src = bufs[cur];
+            cur ^= 1;
+        }
+        for (int n = 0; n < N; ++n) {
+            const int32_t rc = ttm(pl, pl.gp1[n], src, at(b.pst, poff[n], e), bufs[cur], nullptr, s);
+            if (rc != RHOSVD_OK) return rc;
+            src = bufs[cur];
+            cur ^= 1;
+        }
+    } else {
+        for (int n = 0; n < N; ++n) {
+            const int32_t rc = ttm(pl, pl.gh[n], src, at(b.qstore, qoff[n], e), bufs[cur], nullptr, s);
+            if (rc != RHOSVD_OK) return rc;
+            src = bufs[cur];
+            cur ^= 1;
+        }
     }
     const void* H = src;
     void* scratch = bufs[cur];
@@ -734,7 +902,7 @@ int32_t decompose_on(rhosvd_ctx* ctx, const rhosvd_tensor* x, const rhosvd_param
     if (he != hipSuccess) rc = hip_fail(he);
     if (rc == RHOSVD_OK)
         rc = (pr.algo == RHOSVD_R_STHOSVD) ? run_r_sthosvd(*pl, b, x->data, out, s)
-                                            : run_rp_hosvd(*pl, b, x->data, out, s);   // RP-HOSVD, RP-HOOI
+                                            : run_rp_hosvd(*pl, b, x->data, out, s);   // RP-HOSVD, RP-HOOI, R-PET
     if (rc == RHOSVD_OK) {
         he = rh::launch_sumsq(pr.dbl, out->core, pl->core_elems, b.part_ss, kSumsqBlocks, s);
         if (he == hipSuccess) he = rh::launch_reduce_ss(b.part_ss, kSumsqBlocks, &b.rep->norm_core2, s);
@@ -743,6 +911,183 @@ int32_t decompose_on(rhosvd_ctx* ctx, const rhosvd_tensor* x, const rhosvd_param
     if (rc == RHOSVD_OK) rc = run_residual(*pl, b, x->data, out, s);
     if (rc == RHOSVD_OK && out->report) {
         he = rh::launch_copy_bytes(b.rep, out->report, sizeof(rhosvd_report), s);
+        if (he != hipSuccess) rc = hip_fail(he);
+    }
+    if (dev != ctx->device) (void)hipSetDevice(dev);
+    return rc;
+}
+
+// ---- fixed-precision R-STHOSVD (Section 5.1, the tolerance split of
+// Algorithm 4) -----------------------------------------------------------
+
+// The problem with every R_n = K_n = min(kmax, I_n, J_n): the largest tensors
+// (and workspace) the adaptive path can meet.  ks receives the K_n.
+int32_t adaptive_problem(const rhosvd_tensor* x, const rhosvd_adaptive_params* ap, int32_t* ks,
+                         rhosvd_params* p) {
+    if (!x || !ap || !x->dims) return RHOSVD_EINVAL;
+    if (!(ap->eps > 0.0) || ap->kmax < 1 || ap->kmax > RHOSVD_MAX_SKETCH) return RHOSVD_EINVAL;
+    if (x->order < 2 || x->order > RHOSVD_MAX_ORDER) return RHOSVD_EINVAL;
+    const int N = x->order;
+    int64_t d[RHOSVD_MAX_ORDER];
+    for (int n = 0; n < N; ++n) {
+        if (x->dims[n] < 1) return RHOSVD_EINVAL;
+        d[n] = x->dims[n];
+    }
+    for (int n = 0; n < N; ++n) {
+        const int64_t J = prod(d, 0, n) * prod(d, n + 1, N);
+        const int64_t K = std::min<int64_t>(std::min<int64_t>(ap->kmax, d[n]), J);
+        ks[n] = static_cast<int32_t>(K);
+        d[n] = K;
+    }
+    *p = rhosvd_params{};
+    p->algo = RHOSVD_R_STHOSVD;
+    p->ranks = ks;
+    p->oversample = 0;
+    p->power_iters = ap->power_iters;
+    p->seed = ap->seed;
+    p->mode_order = nullptr;
+    p->precision = ap->precision;
+    p->flags = ap->flags;
+    return RHOSVD_OK;
+}
+
+// The partials of pass g fit the buffers carved for the worst-case plan.
+bool partials_fit(const Plan& pl, const Pass& g, bool gram) {
+    const size_t y = static_cast<size_t>(g.grid) * g.K_pad * g.I_pad * pl.pr.elem;
+    const size_t gg = gram ? static_cast<size_t>(g.grid) * g.K_pad * g.K_pad * pl.pr.elem : 0;
+    return y <= pl.part_bytes && gg <= pl.part_bytes && g.grid <= pl.max_grid;
+}
+
+// Mode by mode: sketch, power steps, B and its Gram, all K eigenpairs and
+// U = Q Ubar (K columns); the eigenvalues come to the host, which keeps the
+// smallest R whose residual ||S||^2 - sum_{i <= R} sigma_i^2 is within the
+// mode's share eps^2 ||X||^2 / N, and the truncation keeps R rows.
+int32_t run_adaptive(rhosvd_ctx* ctx, Plan* pl, const Buffers& b, const rhosvd_tensor* x,
+                     const rhosvd_adaptive_params* ap, const rhosvd_output* out,
+                     int32_t* ranks_out, int32_t* met_out, hipStream_t s) {
+    const Problem& pr = pl->pr;
+    const bool dbl = pr.dbl;
+    const int N = pr.N;
+    const int cu = planning_cu(nullptr);
+    int64_t d[RHOSVD_MAX_ORDER];
+    for (int n = 0; n < N; ++n) d[n] = pr.dims[n];
+    const void* src = x->data;
+    double budget = 0.0;
+    (void)ctx;
+    for (int n = 0; n < N; ++n) {
+        const int64_t I = d[n], T = prod(d, 0, N) / d[n];
+        const int K = static_cast<int>(std::min<int64_t>(std::min<int64_t>(ap->kmax, I), T));
+        const bool capped = K < ap->kmax;
+        Pass gs, gp, gt, gtr;
+        if (!plan_pass(rh::OP_SKETCH, dbl, pr.ct_sketch, 1, I, T, K, cu, &gs, pr.kernels) ||
+            !plan_pass(rh::OP_POWER, dbl, pr.ct_power, 1, I, T, K, cu, &gp, pr.kernels) ||
+            !plan_pass(rh::OP_TTM, dbl, pr.ct_ttm, 1, I, T, K, cu, &gt, pr.kernels))
+            return RHOSVD_EUNSUPPORTED;
+        if (!partials_fit(*pl, gs, false) || (pr.q > 0 && !partials_fit(*pl, gp, false)) ||
+            !partials_fit(*pl, gt, true) || I * K > pl->maxIK || static_cast<int64_t>(K) * T > pl->maxB ||
+            static_cast<int64_t>(K) * K > pl->maxKR || static_cast<int64_t>(K) * K > pl->maxKK ||
+            static_cast<int64_t>(rh::evd_qwork_doubles(K, I)) > pl->maxQW)
+            return RHOSVD_EUNSUPPORTED;
+        double* nrm = n == 0 ? &b.rep->norm_x2 : b.part_resid;
+        rh::KrArgs kr{};
+        if (pr.kr) {
+            // this mode's tables at the current extents (within the room the
+            // worst case, every earlier R = K, reserved)
+            for (int q = 0; q < N - 1; ++q) pl->kr_ext[n][q] = d[pl->kr_mode[n][q]];
+            int modes[RHOSVD_MAX_ORDER], Ks[RHOSVD_MAX_ORDER];
+            modes[n] = n;
+            Ks[n] = K;
+            const int32_t rf = fill_kr(*pl, b, n, n + 1, modes, Ks, s);
+            if (rf != RHOSVD_OK) return rf;
+            kr = kr_args(*pl, b, n, K, T);
+        }
+        int32_t rc = sketch_and_orthonormalize(*pl, b, src, gs, gp, n, 2u, nrm, b.qT, s, kr);
+        if (rc != RHOSVD_OK) return rc;
+        rc = ttm(*pl, gt, src, b.qT, b.B, b.part, s);
+        if (rc != RHOSVD_OK) return rc;
+        RH_HIP(rh::launch_gram_reduce(dbl, b.part, gt.grid, K, gt.K_pad, b.C, s));
+        RH_HIP(rh::launch_evd_factor(dbl, b.C, K, &b.rep->flags, b.qT, I, K, 1, out->factors[n], b.M,
+                                     &b.rep->sigma[n][0], b.u64, s));
+        double sig[RHOSVD_MAX_K], nrm_h = 0.0;
+        RH_HIP(hipStreamSynchronize(s));
+        RH_HIP(hipMemcpy(sig, &b.rep->sigma[n][0], sizeof(double) * K, hipMemcpyDeviceToHost));
+        RH_HIP(hipMemcpy(&nrm_h, nrm, sizeof(double), hipMemcpyDeviceToHost));
+        if (n == 0) budget = ap->eps * ap->eps * nrm_h / N;
+        int R = K;
+        bool met = false;
+        double kept = 0.0;
+        for (int r = 1; r <= K; ++r) {
+            kept += sig[r - 1] * sig[r - 1];
+            if (nrm_h - kept <= budget) {
+                R = r;
+                met = true;
+                break;
+            }
+        }
+        ranks_out[n] = R;
+        if (met_out) met_out[n] = met ? 1 : 0;
+        RH_HIP(rh::launch_report_mode(b.rep, n, capped ? -K : K, R, s));
+        if (!plan_pass(rh::OP_TTM, dbl, pr.ct_trunc, 1, K, T, R, cu, &gtr, pr.kernels))
+            return RHOSVD_EUNSUPPORTED;
+        void* dst = (n == N - 1) ? out->core : ((n % 2 == 0) ? b.ping : b.pong);
+        if (n < N - 1 && R * T > ((n % 2 == 0) ? pl->ping : pl->pong)) return RHOSVD_EUNSUPPORTED;
+        rc = ttm(*pl, gtr, b.B, b.M, dst, nullptr, s, 1);
+        if (rc != RHOSVD_OK) return rc;
+        src = dst;
+        d[n] = R;
+    }
+    // the chosen ranks are the problem's ranks from here on (core norm,
+    // residual)
+    pl->core_elems = prod(d, 0, N);
+    for (int n = 0; n < N; ++n) pl->pr.ranks[n] = ranks_out[n];
+    return RHOSVD_OK;
+}
+
+int32_t decompose_adaptive_on(rhosvd_ctx* ctx, const rhosvd_tensor* x,
+                              const rhosvd_adaptive_params* ap, void* workspace, size_t ws_bytes,
+                              const rhosvd_output* out, int32_t* ranks_out, int32_t* met_out,
+                              void* stream, Plan* pl) {
+    if (!ctx || !out || !out->core || !out->factors || !workspace || !ranks_out) return RHOSVD_EINVAL;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return RHOSVD_EINVAL;
+    int32_t ks[RHOSVD_MAX_ORDER];
+    rhosvd_params p;
+    int32_t rc = adaptive_problem(x, ap, ks, &p);
+    if (rc != RHOSVD_OK) return rc;
+    Problem pr;
+    rc = validate(x, &p, &pr, true);
+    if (rc != RHOSVD_OK) return rc;
+    pr.kernels = ctx->kernels;
+    for (int n = 0; n < pr.N; ++n)
+        if (!out->factors[n]) return RHOSVD_EINVAL;
+    rc = build_plan(pr, planning_cu(nullptr), pl);
+    if (rc != RHOSVD_OK) return rc;
+    Buffers b;
+    const size_t need = carve(*pl, nullptr, &b);
+    if (ws_bytes < need) return RHOSVD_ENOMEM;
+    carve(*pl, workspace, &b);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = -1;
+    RH_HIP(hipGetDevice(&dev));
+    if (dev != ctx->device) RH_HIP(hipSetDevice(ctx->device));
+    rh::ReportInit ri{};
+    ri.order = pr.N;
+    for (int n = 0; n < pr.N; ++n) ri.k_used[n] = ks[n];
+    rc = RHOSVD_OK;
+    hipError_t he = rh::launch_report_init(b.rep, ri, s);
+    if (he != hipSuccess) rc = hip_fail(he);
+    if (rc == RHOSVD_OK) rc = run_adaptive(ctx, pl, b, x, ap, out, ranks_out, met_out, s);
+    if (rc == RHOSVD_OK) {
+        he = rh::launch_sumsq(pr.dbl, out->core, pl->core_elems, b.part_ss, kSumsqBlocks, s);
+        if (he == hipSuccess) he = rh::launch_reduce_ss(b.part_ss, kSumsqBlocks, &b.rep->norm_core2, s);
+        if (he != hipSuccess) rc = hip_fail(he);
+    }
+    if (rc == RHOSVD_OK) rc = run_residual(*pl, b, x->data, out, s);
+    if (rc == RHOSVD_OK && out->report) {
+        he = rh::launch_copy_bytes(b.rep, out->report, sizeof(rhosvd_report), s);
+        if (he != hipSuccess) rc = hip_fail(he);
+    }
+    if (rc == RHOSVD_OK) {
+        he = hipStreamSynchronize(s);
         if (he != hipSuccess) rc = hip_fail(he);
     }
     if (dev != ctx->device) (void)hipSetDevice(dev);
@@ -847,6 +1192,28 @@ int32_t rhosvd_decompose(rhosvd_ctx* ctx, const rhosvd_tensor* x, const rhosvd_p
     return rc;
 }
 
+int32_t rhosvd_adaptive_workspace_size(const rhosvd_tensor* x, const rhosvd_adaptive_params* p,
+                                       size_t* bytes) {
+    if (!bytes) return RHOSVD_EINVAL;
+    int32_t ks[RHOSVD_MAX_ORDER];
+    rhosvd_params fp;
+    const int32_t rc = adaptive_problem(x, p, ks, &fp);
+    if (rc != RHOSVD_OK) return rc;
+    return rhosvd_workspace_size(x, &fp, bytes);
+}
+
+int32_t rhosvd_decompose_adaptive(rhosvd_ctx* ctx, const rhosvd_tensor* x,
+                                  const rhosvd_adaptive_params* p, void* workspace,
+                                  size_t ws_bytes, const rhosvd_output* out, int32_t* ranks_out,
+                                  int32_t* met_out, void* stream) {
+    Plan* pl = new (std::nothrow) Plan;
+    if (!pl) return RHOSVD_ENOMEM;
+    const int32_t rc = decompose_adaptive_on(ctx, x, p, workspace, ws_bytes, out, ranks_out,
+                                             met_out, stream, pl);
+    delete pl;
+    return rc;
+}
+
 double rhosvd_report_rel_error(const rhosvd_report* r) {
     if (!r || !(r->norm_x2 > 0.0)) return NAN;
     if (r->flags & RHOSVD_FLAG_E_EXPLICIT) return std::sqrt(r->resid2 / r->norm_x2);
@@ -908,10 +1275,45 @@ static int32_t check_view(int32_t dtype, int32_t precision, int64_t L, int64_t I
     return RHOSVD_OK;
 }
 
+static int32_t sketch_step(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t precision,
+                           int64_t L, int64_t I, int64_t T, int32_t K, uint64_t seed, int32_t mode,
+                           int32_t tag, const rh::KrArgs& kr, double* y, double* norm2,
+                           void* workspace, size_t ws_bytes, void* stream);
+
 int32_t rhosvd_sketch(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t precision,
                       int64_t L, int64_t I, int64_t T, int32_t K, uint64_t seed, int32_t mode,
                       int32_t tag, double* y, double* norm2, void* workspace, size_t ws_bytes,
                       void* stream) {
+    return sketch_step(ctx, src, dtype, precision, L, I, T, K, seed, mode, tag, rh::KrArgs{}, y,
+                       norm2, workspace, ws_bytes, stream);
+}
+
+int32_t rhosvd_sketch_kr(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t precision,
+                         int64_t L, int64_t I, int64_t T, int32_t K, const void* const* tabs,
+                         const int64_t* ext, int32_t nq, double* y, double* norm2,
+                         void* workspace, size_t ws_bytes, void* stream) {
+    if (!tabs || !ext || nq < 1 || nq > RHOSVD_MAX_ORDER - 1 || K < 1) return RHOSVD_EINVAL;
+    rh::KrArgs kr{};
+    kr.nq = nq;
+    kr.K = K;
+    kr.J = L * T;
+    int64_t prodx = 1;
+    for (int q = 0; q < nq; ++q) {
+        if (!tabs[q] || ext[q] < 1 || ext[q] > (int64_t(1) << 31) - 1) return RHOSVD_EINVAL;
+        kr.tab[q] = tabs[q];
+        kr.ext[q] = static_cast<int>(ext[q]);
+        prodx *= ext[q];
+        if (prodx > (int64_t(1) << 32)) return RHOSVD_EINVAL;
+    }
+    if (prodx != L * T) return RHOSVD_EINVAL;
+    return sketch_step(ctx, src, dtype, precision, L, I, T, K, 0, 0, 0, kr, y, norm2, workspace,
+                       ws_bytes, stream);
+}
+
+static int32_t sketch_step(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t precision,
+                           int64_t L, int64_t I, int64_t T, int32_t K, uint64_t seed, int32_t mode,
+                           int32_t tag, const rh::KrArgs& kr, double* y, double* norm2,
+                           void* workspace, size_t ws_bytes, void* stream) {
     if (!ctx || !src || !y) return RHOSVD_EINVAL;
     int32_t rc = check_view(dtype, precision, L, I, T, K);
     if (rc != RHOSVD_OK) return rc;
@@ -932,6 +1334,7 @@ int32_t rhosvd_sketch(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t p
     a.seed = seed;
     a.mode = static_cast<uint32_t>(mode);
     a.tag = static_cast<uint32_t>(tag);
+    a.kr = kr;
     RH_HIP(launch_pass(g, a, s));
     RH_HIP(rh::launch_reduce_y(dbl, part, g.grid, static_cast<int>(I), K, g.I_pad, g.K_pad, y, s));
     if (norm2) RH_HIP(rh::launch_reduce_ss(ss, g.grid, norm2, s));

@@ -77,7 +77,10 @@ def test_workspace_size_valid(lib):
     (dict(dims=(10, 10), ranks=(3, 3), order=(0, 0)), L.EINVAL),
     (dict(dims=(10, 10), ranks=(3, 3), order=(1, 2)), L.EINVAL),
     (dict(dims=(10, 10), ranks=(3, 3), algo=7), L.EINVAL),
-    (dict(dims=(10, 10), ranks=(3, 3), flags=2), L.EINVAL),
+    (dict(dims=(10, 10), ranks=(3, 3), flags=4), L.EINVAL),
+    (dict(dims=(10, 10), ranks=(3, 3), algo=L.RP_HOOI, p=0, flags=L.OPT_KR_SKETCH), L.EINVAL),
+    (dict(dims=(10, 10), ranks=(3, 3), algo=L.R_PET, q=0, flags=L.OPT_KR_SKETCH), L.EINVAL),
+    (dict(dims=(10, 10), ranks=(3, 3), algo=L.R_PET, q=1), L.EINVAL),   # R-PET is single pass
     (dict(dims=(10, 10), ranks=(3, 3), flags=0x80000000), L.EINVAL),   # unknown option bits
     (dict(dims=(10, 10), ranks=(3, 3), flags=0x100), L.EINVAL),
     (dict(dims=(10, 10), ranks=(3, 3), dtype=L.F32, prec=L.PREC_F64), L.EINVAL),
@@ -144,3 +147,26 @@ def test_report_layout_matches_header(lib):
 def test_binding_imports_without_gpu():
     from paper_2001_07124_amd import api  # noqa: F401
     assert hasattr(api, "r_sthosvd") and hasattr(api, "Decomposer")
+
+
+def test_structured_sketch_and_r_pet_are_valid(lib):
+    rc, n = _ws(lib, (30, 20, 10), (3, 3, 3), flags=L.OPT_KR_SKETCH)
+    assert rc == L.OK and n > 0
+    rc, n = _ws(lib, (30, 20, 10), (3, 3, 3), algo=L.RP_HOSVD, flags=L.OPT_KR_SKETCH)
+    assert rc == L.OK and n > 0
+    rc, n = _ws(lib, (30, 20, 10), (3, 3, 3), algo=L.R_PET, q=0)
+    assert rc == L.OK and n > 0
+
+
+def test_adaptive_workspace_size(lib):
+    import ctypes
+    dims = (40, 30, 20)
+    dims_c = (ctypes.c_int64 * 3)(*dims)
+    t = L.Tensor(3, dims_c, L.F32, None)
+    n = ctypes.c_size_t(0)
+    ok = L.AdaptiveParams(0.1, 16, 1, 0, L.PREC_F32, 0)
+    assert lib.rhosvd_adaptive_workspace_size(ctypes.byref(t), ctypes.byref(ok), ctypes.byref(n)) == L.OK
+    assert n.value > 0
+    for eps, kmax in ((0.0, 16), (-1.0, 16), (0.1, 0), (0.1, 65)):
+        bad = L.AdaptiveParams(eps, kmax, 1, 0, L.PREC_F32, 0)
+        assert lib.rhosvd_adaptive_workspace_size(ctypes.byref(t), ctypes.byref(bad), ctypes.byref(n)) == L.EINVAL

@@ -8,7 +8,8 @@ replayed from a HIP graph) against the FP64 oracle, item by item (GPU only).
 * graph replays, with other device work and synchronisations between them,
   reproduce the directly enqueued run bit for bit;
 * a sample of the 512-tensor workload (extents 32..256, ranks 4..32, p = 5,
-  q = 1) against the oracle.
+  q = 1) against the oracle (the batch's identity-based E carries the FP32
+  cancellation floor, 1e-7 / E, on top of the 1e-5).
 """
 import numpy as np
 import pytest
@@ -30,7 +31,12 @@ def _items(specs, xs, p=5, q=1, prec=None, seed0=100):
 
 def _check(res, x, ranks, p, q, seed, tol):
     ref = o_rst(x.astype(np.float64), ranks, p, q, seed=seed)
-    assert abs(res.rel_error - ref.rel_error) <= tol["e"], (res.rel_error, ref.rel_error)
+    # the batch reports the identity E = sqrt(||X||^2 - ||G||^2) / ||X|| (no
+    # explicit residual pass): a relative error d of ||G||^2 moves it by about
+    # d / (2 E), and an FP32 core carries d ~ 2e-7, so below E ~ 1e-2 the
+    # bound grows as 1e-7 / E (4e-7 for FP64 data: none at these sizes)
+    e_tol = tol["e"] + (1e-7 / ref.rel_error if x.dtype == np.float32 else 0.0)
+    assert abs(res.rel_error - ref.rel_error) <= e_tol, (res.rel_error, ref.rel_error)
     for n in range(3):
         np.testing.assert_allclose(res.sigma(n), ref.sigma[n], rtol=tol["s"], atol=tol["s"] * ref.sigma[n][0])
         u = res.factors[n].cpu().numpy().astype(np.float64)

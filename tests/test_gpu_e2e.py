@@ -283,3 +283,52 @@ def test_rp_hooi_exact_recovery():
     x, _, _ = tucker_tensor(dims, ranks, seed=44, factors="gaussian", dtype=np.float64)
     res = api.rp_hooi(api.to_device(x), ranks, sweeps=1, seed=2)
     assert res.explicit and res.rel_error <= 1e-12
+
+
+# ---- R-PET (Algorithm 9) ------------------------------------------------------
+
+from oracle.variants import r_pet as o_rpet  # noqa: E402
+
+# (dims, ranks, p): the order-3 100^3 workload shape at reduced size, an
+# order-4 case, and one whose core sketch width 2K + 1 is capped by a mode
+RPET_CASES = [((40, 36, 30), (5, 4, 6), 5), ((14, 12, 11, 9), (3, 3, 2, 3), 2), ((9, 30, 26), (3, 5, 4), 3)]
+
+
+@pytest.mark.parametrize("dims,ranks,p", RPET_CASES)
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16"])
+def test_r_pet_matches_oracle(dims, ranks, p, precision):
+    dtype = np.float64 if precision == "f64" else np.float32
+    x, _, _ = tucker_tensor(dims, ranks, seed=45, noise=0.01, dtype=dtype)
+    res = api.r_pet(api.to_device(x), ranks, p=p, seed=6, precision=precision)
+    ref = o_rpet(x.astype(np.float64), ranks, p, seed=6)
+    core = api.to_numpy_fortran(res.core).astype(np.float64)
+    facs = [f.cpu().numpy().astype(np.float64) for f in res.factors]
+    print(f"[r-pet] {dims} {precision}: E {res.rel_error:.8f} oracle {ref.rel_error:.8f}", flush=True)
+    # the recovered core is not X x_n U_n^T: E is always the explicit residual
+    assert res.explicit
+    if precision == "f64":
+        _compare(res, core, facs, ref, 1e-10, 1e-9, 1e-8)
+        for u, v in zip(facs, ref.factors):
+            np.testing.assert_allclose(u, v, atol=1e-8)
+        np.testing.assert_allclose(core, ref.core, atol=1e-8 * np.max(np.abs(ref.core)))
+    elif precision == "f32":
+        _compare(res, core, facs, ref, 1e-5, 1e-5, 1e-4)
+    else:
+        # bf16 sketch (2^-9 per entry) and split-bf16 products: as the bf16
+        # RP-HOSVD case
+        assert abs(res.rel_error - ref.rel_error) <= 1e-3
+
+
+def test_r_pet_exact_recovery():
+    # an exactly low-rank tensor: the sketches capture the whole range, the
+    # least-squares recovery is exact, so E vanishes to rounding
+    dims, ranks = (30, 26, 22), (4, 3, 5)
+    x, _, _ = tucker_tensor(dims, ranks, seed=46, factors="gaussian", dtype=np.float64)
+    res = api.r_pet(api.to_device(x), ranks, p=3, seed=2, precision="f64")
+    assert res.explicit and res.rel_error <= 1e-12
+
+
+def test_r_pet_rejects_power_iterations():
+    x = api.to_device(np.ones((6, 5, 4), order="F"))
+    with pytest.raises(api.L.RhosvdError):
+        api.decompose(x, (2, 2, 2), algo="r_pet", p=1, q=1)

@@ -8,7 +8,7 @@ definition of the same step:
   power step      A (A^T Q)                             (Algorithm 1 step 2, q > 0)
   mode-n product  oracle.tensor_ops.ttm, Gram B B^T     (Algorithm 1 step 4)
   CholeskyQR2     oracle.rsvd.qr_pos (diag(R) > 0)      (Algorithm 1 step 3)
-  Jacobi EVD      numpy.linalg.eigh                     (Algorithm 1 step 5)
+  symmetric EVD   numpy.linalg.eigh                     (Algorithm 1 step 5)
 Tolerances: FP64 paths 1e-11 relative; FP32 paths are set from the
 accumulation length (J terms of fp32 products): 2e-5 of the column scale.
 """
@@ -285,3 +285,38 @@ def test_fp8_sketch_within_rounding_bound(dims):
     rel = np.linalg.norm(got - want) / np.linalg.norm(want)
     print(f"[fp8] sketch {dims}: relative error {rel:.3e}", flush=True)
     assert rel <= 0.05                          # about u / sqrt(3) for random-sign rounding
+
+
+# ---- modes of 257-512 rows: four waves share each column block -------------
+# Shapes whose mode has more rows than one wave holds (256): the row-split
+# variants of the wave kernels, each wave on its own rows, Z = S^T M summed
+# across the waves.  (300, 9, 40): I = 300 contiguous; (7, 420, 11): I = 420
+# strided (L = 7); (500, 13, 9): the exact 500-row variant at K = 30.
+TALL = [((300, 9, 40), 0, 11), ((300, 9, 40), 0, 40), ((7, 420, 11), 1, 30), ((500, 13, 9), 0, 30)]
+
+
+@pytest.mark.parametrize("dims,n,K", TALL)
+@pytest.mark.parametrize("precision", ["f32", "bf16"])
+def test_tall_mode_steps(dims, n, K, precision):
+    x, _, _ = tucker_tensor(dims, tuple(min(3, d) for d in dims), seed=27, noise=0.3, dtype=np.float32)
+    src = _flat(x, np.float32)
+    x64 = x.astype(np.float64)
+    view = _views(dims)[n][1]
+    rng = np.random.default_rng(7)
+    a = unfold(x64, n)
+    # f32: FP32 products over J terms; bf16: as test_bf16_sketch_power_ttm
+    t_sk, t_pw, t_tt = (2e-5, 3e-5, 2e-5) if precision == "f32" else (1e-2, 2.0 ** -8, 1e-2)
+    y, nrm = api.sketch(src, view, K, seed=5, mode=n, tag=2, want_norm=True, precision=precision)
+    _close_cols(y.cpu().numpy(), a @ philox.omega_unfolding(5, n, 2, x64.shape, K), t_sk)
+    assert abs(nrm.item() - float(np.sum(x64 ** 2))) <= 1e-6 * np.sum(x64 ** 2)
+    q, _ = np.linalg.qr(rng.standard_normal((dims[n], K)))
+    q = q.astype(np.float32)
+    y = api.power(src, view, torch.from_numpy(q).cuda(), precision=precision).cpu().numpy()
+    _close_cols(y, a @ (a.T @ q.astype(np.float64)), t_pw)
+    m = rng.standard_normal((dims[n], K)).astype(np.float32)
+    out, gram, _ = api.ttm(src, view, K, torch.from_numpy(m).cuda(), want_gram=True, precision=precision)
+    want = o_ttm(x64, m.astype(np.float64).T, n)
+    got = out.cpu().numpy().reshape(want.shape, order="F")
+    _close_cols(unfold(got, n).T, unfold(want, n).T, t_tt)
+    b = unfold(want, n)
+    _close_cols(gram.cpu().numpy(), b @ b.T, t_tt)

@@ -131,3 +131,78 @@ def test_r_pet_within_reach_of_rp_hosvd_on_noisy_data():
     b = rp_hosvd(x, (5, 5, 5), 5, 0, seed=9)
     assert b.rel_error <= a.rel_error * (1 + 1e-12) or abs(a.rel_error - b.rel_error) < 1e-3
     assert a.rel_error <= 3 * b.rel_error
+
+
+# ---- structured (Khatri-Rao) sketch, Section 5.1 ---------------------------
+
+from oracle.philox import omega as _omega  # noqa: E402
+from oracle.variants import TAG_KR, kr_tables, omega_kr, r_sthosvd_kr, rp_hosvd_kr  # noqa: E402
+
+
+@pytest.mark.parametrize("shape", [(5, 4, 3), (4, 3, 5, 2)])
+def test_omega_kr_is_the_contraction_with_the_tables(shape):
+    # the sketch W = Z x_{q != n} Gamma_q^T taken column by column: column k
+    # of X_(n) Omega_n contracts every other mode q of X with column k of
+    # Gamma_q (the paper's tensor form, no unfolding or index arithmetic)
+    rng = np.random.default_rng(70)
+    x = rng.standard_normal(shape)
+    K = 3
+    for n in range(len(shape)):
+        tabs = kr_tables(11, n, shape, K)
+        y = unfold(x, n) @ omega_kr(11, n, shape, K)
+        for k in range(K):
+            t = x
+            for q in reversed(range(len(shape))):
+                if q != n:
+                    t = np.tensordot(t, tabs[q][:, k], axes=([q], [0]))
+            np.testing.assert_allclose(y[:, k], t, rtol=1e-12, atol=1e-12)
+
+
+def test_kr_tables_come_from_their_own_streams():
+    shape = (6, 5, 4)
+    t01 = kr_tables(3, 0, shape, 4)[1]
+    np.testing.assert_array_equal(t01, _omega(3, 0 * 3 + 1, TAG_KR, 5, 4))
+    t10 = kr_tables(3, 1, shape, 4)[0]
+    np.testing.assert_array_equal(t10, _omega(3, 1 * 3 + 0, TAG_KR, 6, 4))
+    assert not np.allclose(kr_tables(3, 1, shape, 4)[2], kr_tables(3, 0, shape, 4)[2])
+    assert not np.allclose(kr_tables(4, 0, shape, 4)[1], t01)
+
+
+def test_omega_kr_moments_factor_over_the_tables():
+    # the rows of Omega_n enumerate every combination of table rows once, so
+    # a column's mean and mean square are the products of the tables' own
+    # (a mistake in the index mapping that repeats or skips rows breaks this)
+    shape = (40, 3, 30, 25)
+    K = 6
+    om = omega_kr(5, 1, shape, K)
+    tabs = kr_tables(5, 1, shape, K)
+    for k in range(K):
+        m1 = np.prod([tabs[q][:, k].mean() for q in tabs])
+        m2 = np.prod([(tabs[q][:, k] ** 2).mean() for q in tabs])
+        assert abs(om[:, k].mean() - m1) <= 1e-12
+        assert abs((om[:, k] ** 2).mean() - m2) <= 1e-12 * m2
+    # and the tables themselves are standard normal draws
+    allv = np.concatenate([t.ravel() for t in tabs.values()])
+    assert abs(allv.mean()) < 0.1 and abs(allv.var() - 1.0) < 0.15
+
+
+@pytest.mark.parametrize("dims,ranks", [((14, 12, 10), (3, 4, 2)), ((9, 8, 7, 6), (2, 3, 2, 3))])
+@pytest.mark.parametrize("p,q", [(0, 0), (3, 1)])
+def test_kr_sketch_exact_recovery(dims, ranks, p, q):
+    # a Khatri-Rao sketch of generic tables has full column rank on the range
+    # of a low-rank unfolding, so both algorithms recover exactly
+    x, _, _ = tucker_tensor(dims, ranks, seed=71, factors="gaussian", dtype=np.float64)
+    for res in (r_sthosvd_kr(x, ranks, p, q, seed=3), rp_hosvd_kr(x, ranks, p, q, seed=3)):
+        assert res.rel_error <= 1e-12
+        for u in res.factors:
+            assert np.linalg.norm(u.T @ u - np.eye(u.shape[1]), 2) <= 1e-12
+
+
+def test_kr_sketch_close_to_gaussian_on_noisy_data():
+    # the structured sketch spans the dominant subspace about as well as the
+    # dense Gaussian one (Section 5.1 offers it as a drop-in)
+    from oracle.tucker import r_sthosvd
+    x, _, _ = tucker_tensor((40, 36, 30), (5, 5, 5), seed=72, noise=0.02, dtype=np.float64)
+    a = r_sthosvd_kr(x, (5, 5, 5), 5, 1, seed=3)
+    b = r_sthosvd(x, (5, 5, 5), 5, 1, seed=3)
+    assert abs(a.rel_error - b.rel_error) <= 0.02 * b.rel_error

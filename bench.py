@@ -2,11 +2,13 @@
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision f32]
 
-A step is one whole decomposition (every mode: sketch, power step, CholeskyQR2,
-projection + Gram, Jacobi EVD, factor, truncation) of a tensor already
-resident in HBM.  Prints one JSON line with the tensor throughput (GB/s of
-input per second), the roofline of the dominant kernel measured live with HIP
-events, and the FP64 oracle timed on the host over a bounded sample.
+A step is one whole decomposition (every mode: sketch, power step, QR,
+projection + Gram, FP64 symmetric EVD, factor, truncation) of a tensor
+already resident in HBM.  Prints one JSON line with the tensor throughput
+(GB/s of input per second), the roofline of the dominant kernel measured live
+with HIP events, the whole path's fraction of its HBM roofline, and the FP64
+oracle timed on the host over a bounded sample; beside them the batched
+(512 small tensors) and served (Poisson arrivals) workloads.
 """
 import argparse
 import ctypes

@@ -279,8 +279,11 @@ int32_t rhosvd_decompose_adaptive(rhosvd_ctx* ctx, const rhosvd_tensor* x,
  * RHOSVD_R_STHOSVD in the natural mode order, without
  * RHOSVD_OPT_EXPLICIT_ERROR; one order N and one dtype for the batch; every
  * mode I_n <= 256 and K_n <= RHOSVD_MAX_SKETCH.  Dims, ranks, p, q, seed and
- * precision may differ per item; the streaming passes run the workgroup-
- * tiled FP32/FP64 kernels whatever the precision.  An item's result depends
+ * precision may differ per item.  A pass of an FP32 item runs on the wave
+ * kernels (one 16-column block per wave, up to 64 workgroups per item; the
+ * items of one compute type and shape class share a launch) when its shape
+ * fits them, else on the workgroup-tiled kernels, as do FP64 items.  An
+ * item's result depends
  * only on its own problem and on the context's tuned tile parameters, so it
  * is bitwise the same alone (a batch of one) and in any mix.  The reports
  * hold the identity-based E of Section 5.1 only (no explicit residual pass):
@@ -421,6 +424,18 @@ size_t rhosvd_sketch_all_workspace_size(int32_t order, const int64_t* dims, cons
 int32_t rhosvd_power(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t precision,
                      int64_t L, int64_t I, int64_t T, int32_t K, const void* q_in,
                      double* y, void* workspace, size_t ws_bytes, void* stream);
+
+/* Truncation of R-STHOSVD in the rotated layout (Algorithm 8 step 4 as
+ * Ubar_R^T B, Section 4.1): out[r J + j] = sum_k M(k, r) B(k, j)
+ * for b = B (K x J column-major: the projection's output for one mode) and
+ * m = M (K x R column-major), all device, dtype RHOSVD_F32 or RHOSVD_F64,
+ * out R x J row-major (the next mode first).  Always on the dedicated
+ * truncation kernel (matrix cores in the data's precision), whatever J:
+ * the decompositions use it only where it beats the column kernels.
+ * K <= 64 (FP32) or 32 (FP64), else EUNSUPPORTED; 1 <= R <= K, J >= 1,
+ * else EINVAL.  Stream order; nothing allocated. */
+int32_t rhosvd_truncate_rotated(rhosvd_ctx* ctx, int32_t dtype, const void* b, int32_t K, int64_t J,
+                                const void* m, int32_t R, void* out, void* stream);
 
 /* Mode-n product out = S x_n M^T with M (I x Kout column-major, dtype;
  * NULL means the identity, which needs Kout == I),

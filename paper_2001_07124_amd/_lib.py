@@ -105,6 +105,7 @@ _PROTOS = {
     "rhosvd_sketch_all_workspace_size": (_SZ, [_I32, _P, _P, _I32]),
     "rhosvd_power": (_I32, [_P, _P, _I32, _I32, _I64, _I64, _I64, _I32, _P, _P, _P, _SZ, _P]),
     "rhosvd_ttm": (_I32, [_P, _P, _I32, _I32, _I64, _I64, _I64, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
+    "rhosvd_truncate_rotated": (_I32, [_P, _I32, _P, _I32, _I64, _P, _I32, _P, _P]),
     "rhosvd_orthonormalize": (_I32, [_P, _P, _I64, _I32, _I32, _P, _P, _P, _P]),
     "rhosvd_sym_evd": (_I32, [_P, _P, _I32, _P, _P, _P, _P]),
     "rhosvd_step_workspace_size": (_SZ, [_I64, _I32, _I64]),

@@ -430,6 +430,21 @@ def ttm(src, view, kout, m=None, want_gram=False, want_norm=False, precision=Non
     return out, gram, nrm
 
 
+def truncate_rotated(b, K, J, m):
+    """out (R x J row-major) = M^T B for B = K x J column-major (flat device
+    tensor) and M = K x R (a device matrix), on the rotated truncation
+    kernel."""
+    lib = L.load()
+    dev = b.device
+    R = int(m.shape[1])
+    mc = m.t().contiguous()
+    out = torch.empty(R * int(J), dtype=b.dtype, device=dev)
+    L.check(lib.rhosvd_truncate_rotated(_context(dev.index or 0), _dtype_code(b.dtype), _ptr(b), int(K),
+                                        int(J), _ptr(mc), R, _ptr(out), _stream(None, dev)),
+            "rhosvd_truncate_rotated")
+    return out
+
+
 def orthonormalize(y, dtype=torch.float32):
     """Q of CholeskyQR2 for Y (I x K float64 column-major device matrix)."""
     lib = L.load()

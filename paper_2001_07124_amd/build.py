@@ -26,6 +26,7 @@ SOURCES = {
     "kernels_col.hip": [],
     "kernels_small.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
     "kernels_resid.hip": [],
+    "kernels_trunc.hip": [],
     "kernels_allmode.hip": [],
     "kernels_batch.hip": [],
     "server.hip": [],

@@ -133,6 +133,23 @@ struct WGeom {
 bool plan_wave(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu, WGeom* g);
 hipError_t launch_wave(int op, const WGeom& g, const StreamArgs& a, hipStream_t s);
 
+// One wave-kernel pass of many problems in one launch (device table): job y
+// runs on `units` workgroups of grid x (partial slots 0 .. units - 1).  The
+// batch instantiations are the generic row-block x operand-block bounds of
+// wave_batch_variant (a geometry with another variant is not batched).
+struct WaveJob {
+    WGeom g;
+    StreamArgs a;
+    int units;
+    int want_ss;
+    int want_gram;
+    int pad_;
+};
+int wave_batch_variant(const WGeom& g);   // 0..3, or -1
+bool wave_batch_ct(int op, int ct);       // the compute type has batched instantiations
+hipError_t launch_wave_batch(int op, int ct, int variant, const WaveJob* jobs, int njobs,
+                             int max_units, size_t lds, hipStream_t s);
+
 // Geometry of a column-block pass (kernels_col.hip): contiguous unfolding
 // (L = 1), bf16 matrix cores, blocks of 32 columns, nch 32-row chunks and nb
 // 16-column blocks of the K-wide operand.  Sketch: CT_BF16; power step and
@@ -150,6 +167,21 @@ struct ColGeom {
 
 bool plan_col(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu, ColGeom* g);
 hipError_t launch_col(int op, const ColGeom& g, const StreamArgs& a, hipStream_t s);
+
+// Truncation in the rotated layout (kernels_trunc.hip): out[r J + j] =
+// sum_k M(k, r) B(k, j) for B K x J and M K x R column-major, K <= 64 (32
+// for FP64), in the tensor's precision with one column per lane.
+struct TruncGeom {
+    int K, R, rb, grid;          // rb: row tiles of 16 outputs
+    int64_t J;
+    size_t lds_bytes;
+};
+// the rotated truncation kernel's geometry (K = I rows of B, R outputs, T
+// columns); false when it does not take the shape or, unless any_size, when
+// the column kernels are faster there
+bool plan_trunc(bool dbl, int64_t I, int64_t T, int R, int num_cu, bool any_size, TruncGeom* g);
+hipError_t launch_trunc(bool dbl, const TruncGeom& g, const void* B, const void* M, void* out,
+                        hipStream_t s);
 
 // Fixed-order reductions of per-workgroup partials.
 hipError_t launch_reduce_y(bool dbl, const void* part, int G, int I, int K, int I_pad, int K_pad,

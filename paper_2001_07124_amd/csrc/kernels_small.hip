@@ -1029,7 +1029,7 @@ hipError_t launch_hqr_fwd(const double* y, int I, int K, bool dbl, void* q_out, 
 // U = Q V[:, :R] (V = identity when use_v == 0), canonical signs (each
 // column's largest-magnitude entry positive, the lowest row on ties),
 // M = V_R with the same signs (K x R), sigma = sqrt(max(lambda, 0))[:R].
-// Q (I x K column-major, T) is staged row-major with pitch K16 (zero padded
+// Q (I x K column-major, T) is staged row-major with pitch K16 + 1 (zero padded
 // to I16 rows) at Qs (LDS, or global scratch when it does not fit); U is
 // formed on the f64 matrix cores in place of Q, one 16-row block per wave at
 // a time.  Vs: K x K column-major (LDS), lamS: K (LDS).
@@ -1040,10 +1040,13 @@ __device__ void factor_step(int K, int K16, int I, int I16, int R, int use_v, co
                             double* __restrict__ sigma) {
     __shared__ double sgn[RHOSVD_MAX_K];
     const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
+    // odd row pitch: a column walk (consecutive rows, one column) spreads
+    // over the LDS banks instead of hitting the same two
+    const int QP = K16 + 1;
     // the padding first, then Q in its own column-major order (coalesced),
     // 32 loads in flight per thread (one round up to 8192 elements)
-    for (int e = tid; e < I16 * K16; e += kBlock) {
-        const int i = e / K16, k = e - i * K16;
+    for (int e = tid; e < I16 * QP; e += kBlock) {
+        const int i = e / QP, k = e - i * QP;
         if (i >= I || k >= K) Qs[e] = 0.0;
     }
     const int n = I * K;
@@ -1058,7 +1061,7 @@ __device__ void factor_step(int K, int K16, int I, int I16, int R, int use_v, co
         const int dk = kBlock / I, di = kBlock - dk * I;
 #pragma unroll
         for (int u = 0; u < 32; ++u) {
-            if (e0 + u * kBlock < n) Qs[i * K16 + k] = static_cast<double>(v[u]);
+            if (e0 + u * kBlock < n) Qs[i * QP + k] = static_cast<double>(v[u]);
             i += di;
             k += dk;
             if (i >= I) {
@@ -1085,7 +1088,7 @@ __device__ void factor_step(int K, int K16, int I, int I16, int R, int use_v, co
                 vb[rb][st] = b;
             }
         for (int ib = wave; ib < nib; ib += kBlock / kWave) {
-            const double* qa = Qs + (16 * ib + m) * K16 + kq;
+            const double* qa = Qs + (16 * ib + m) * QP + kq;
             double a[16];
 #pragma unroll
             for (int st = 0; st < 16; ++st) a[st] = st < nst ? qa[4 * st] : 0.0;
@@ -1105,7 +1108,7 @@ __device__ void factor_step(int K, int K16, int I, int I16, int R, int use_v, co
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int row = 16 * ib + Mma<double>::row(kq, r), col = 16 * rb + m;
-                        if (col < R) Qs[row * K16 + col] = acc[rb][r];
+                        if (col < R) Qs[row * QP + col] = acc[rb][r];
                     }
                 }
             }
@@ -1116,7 +1119,7 @@ __device__ void factor_step(int K, int K16, int I, int I16, int R, int use_v, co
         double best = -1.0;
         int bi = 0x7fffffff;
         for (int i = lane; i < I; i += kWave) {
-            const double a = fabs(Qs[i * K16 + r]);
+            const double a = fabs(Qs[i * QP + r]);
             if (a > best) {
                 best = a;
                 bi = i;
@@ -1131,12 +1134,12 @@ __device__ void factor_step(int K, int K16, int I, int I16, int R, int use_v, co
                 bi = oi;
             }
         }
-        if (lane == 0) sgn[r] = (Qs[bi * K16 + r] < 0.0) ? -1.0 : 1.0;
+        if (lane == 0) sgn[r] = (Qs[bi * QP + r] < 0.0) ? -1.0 : 1.0;
     }
     __syncthreads();
     for (int e = tid; e < I * R; e += kBlock) {
         const int r = e / I, i = e - r * I;
-        u_out[e] = static_cast<T>(sgn[r] * Qs[i * K16 + r]);
+        u_out[e] = static_cast<T>(sgn[r] * Qs[i * QP + r]);
     }
     for (int e = tid; e < K * R; e += kBlock) {
         const int r = e / K, k = e - r * K;
@@ -1187,7 +1190,7 @@ __device__ __forceinline__ void evd_tri_body(const double* __restrict__ cin, int
     const int K16 = (K + 15) & ~15, I16 = (I + 15) & ~15;
     double* Vs = shd;                                  // K x K, column r = r-th largest
     double* lamS = Vs + static_cast<size_t>(K) * K;    // K, descending
-    double* Qst = lamS + K + (K & 1);                  // I16 x K16 when staged
+    double* Qst = lamS + K + (K & 1);                  // I16 x (K16 + 1) when staged
     __shared__ double stats[2];                        // norm(T), pivmin
     const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
     for (int e = tid; e < kTriP * kTriP; e += kBlock) hv[e] = 0.0;
@@ -1578,13 +1581,13 @@ __global__ __launch_bounds__(kBlock) void k_evd_factor_batch(const EvdJob* __res
 static size_t evd_lds_bytes(int K, int64_t I, bool factor, bool staged) {
     const size_t K16 = (K + 15) & ~15, I16 = (I + 15) & ~static_cast<int64_t>(15);
     const size_t tri = evd_tri_lds_doubles(K);
-    const size_t fac = factor ? static_cast<size_t>(K) * K + K + (K & 1) + (staged ? I16 * K16 : 0) : 0;
+    const size_t fac = factor ? static_cast<size_t>(K) * K + K + (K & 1) + (staged ? I16 * (K16 + 1) : 0) : 0;
     const size_t d = tri > fac ? tri : fac;
     return (d * sizeof(double) + 15) & ~static_cast<size_t>(15);
 }
 
 size_t evd_qwork_doubles(int K, int64_t I) {
-    return static_cast<size_t>((I + 15) & ~static_cast<int64_t>(15)) * ((K + 15) & ~15);
+    return static_cast<size_t>((I + 15) & ~static_cast<int64_t>(15)) * (((K + 15) & ~15) + 1);
 }
 
 template <typename T, bool FACTOR>

@@ -240,15 +240,21 @@ __device__ __forceinline__ void load_block(const WGeom& g, const float* __restri
     const int64_t j0 = blk * 16;
     const bool cok = j0 + l16 < J;
     if (g.vec4) {
-        const float* __restrict__ colp = src + (j0 + l16) * static_cast<int64_t>(I);
+        // buffer loads over the block's 16 contiguous columns: one uniform
+        // 64-bit base, 32-bit lane offsets, columns past J read as zero
+        // (outside the range); 16 I floats < 2^31 bytes for I <= 512
+        const int64_t ncol = J - j0 < 16 ? (J > j0 ? J - j0 : 0) : 16;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float*>(src + j0 * static_cast<int64_t>(I)), static_cast<short>(0),
+            static_cast<int>(ncol * I * 4), 0x00020000);
+        const int cbase = l16 * I * 4;
 #pragma unroll
         for (int f = 0; f < MAXIB; ++f) {
             if (f < IB) {
                 const int i0 = 16 * (fb0 + f) + 4 * quad;
-                if (cok && i0 < I)
-                    sf[f] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(colp + i0));
-                else
-                    sf[f] = zero4<f32x4>();
+                const f32x4 v = __builtin_bit_cast(
+                    f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, cbase + 4 * i0, 0, 0));
+                sf[f] = i0 < I ? v : zero4<f32x4>();
             }
         }
     } else {
@@ -275,8 +281,8 @@ __device__ __forceinline__ void load_block(const WGeom& g, const float* __restri
 // the K-wide operand; EXACT variants fix IB = IBT and NB = NBT at compile
 // time (no masks, no spare accumulators).
 template <int OP, int CT, int IBT, int NBT, bool EXACT, int RS>
-__global__ __launch_bounds__(kBlock, 1) void k_wave(WGeom g, StreamArgs a, int want_ss,
-                                                    int want_gram) {
+__device__ __forceinline__ void wave_body(const WGeom& g, const StreamArgs& a, int want_ss,
+                                          int want_gram, int bidx, int nwg) {
     constexpr int DCT = Sides<CT>::data;    // streamed tensor
     constexpr int OCT = Sides<CT>::op;      // K-wide operand
     typedef FragT<DCT> F;
@@ -337,10 +343,10 @@ __global__ __launch_bounds__(kBlock, 1) void k_wave(WGeom g, StreamArgs a, int w
 
     const float* __restrict__ src = static_cast<const float*>(a.src);
     // RS = 1: one block per wave; RS = 4: one block per workgroup
-    const int64_t wid = RS == 1 ? static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + wave
-                                : static_cast<int64_t>(blockIdx.x);
-    const int64_t nw = RS == 1 ? static_cast<int64_t>(gridDim.x) * (kBlock / kWave)
-                               : static_cast<int64_t>(gridDim.x);
+    const int64_t wid = RS == 1 ? static_cast<int64_t>(bidx) * (kBlock / kWave) + wave
+                                : static_cast<int64_t>(bidx);
+    const int64_t nw = RS == 1 ? static_cast<int64_t>(nwg) * (kBlock / kWave)
+                               : static_cast<int64_t>(nwg);
     const bool jal = (J & 3) == 0;
     f32x4* xr = reinterpret_cast<f32x4*>(smem + g.xr_off);   // [2][RS][NBT][64] when RS > 1
     int par = 0;
@@ -519,7 +525,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_wave(WGeom g, StreamArgs a, int w
     // ---- cross-wave reduction (fixed order) and the per-workgroup partials
     __syncthreads();
     float* red = reinterpret_cast<float*>(smem);
-    const size_t gidx = blockIdx.x;
+    const size_t gidx = static_cast<size_t>(bidx);
     const int I_pad = IB * 16, K_pad = NB * 16;
     if (OP != OP_TTM && RS > 1) {
         // the waves hold disjoint rows: each writes its own
@@ -583,6 +589,20 @@ __global__ __launch_bounds__(kBlock, 1) void k_wave(WGeom g, StreamArgs a, int w
             a.part_ss[gidx] = s;
         }
     }
+}
+
+template <int OP, int CT, int IBT, int NBT, bool EXACT, int RS>
+__global__ __launch_bounds__(kBlock, 1) void k_wave(WGeom g, StreamArgs a, int want_ss,
+                                                    int want_gram) {
+    wave_body<OP, CT, IBT, NBT, EXACT, RS>(g, a, want_ss, want_gram, blockIdx.x, gridDim.x);
+}
+
+// Many problems: job blockIdx.y on workgroups 0 .. units - 1 of grid x.
+template <int OP, int CT, int IBT, int NBT>
+__global__ __launch_bounds__(kBlock, 1) void k_wave_batch(const WaveJob* __restrict__ jobs) {
+    const WaveJob& j = jobs[blockIdx.y];      // read in place: uniform, scalar loads
+    if (static_cast<int>(blockIdx.x) >= j.units) return;
+    wave_body<OP, CT, IBT, NBT, false, 1>(j.g, j.a, j.want_ss, j.want_gram, blockIdx.x, j.units);
 }
 
 // ---------------------------------------------------------------------------
@@ -740,6 +760,62 @@ hipError_t launch_wave(int op, const WGeom& g, const StreamArgs& a, hipStream_t 
     if (op == OP_SKETCH) return launch_wave_op<OP_SKETCH>(g, a, s);
     if (op == OP_POWER) return launch_wave_op<OP_POWER>(g, a, s);
     return launch_wave_op<OP_TTM>(g, a, s);
+}
+
+// Batched instantiations: the generic bounds (row blocks, operand blocks) of
+// the short-mode kernel, smallest first, for the compute types of the FP32
+// and bf16 paths (the sketch in FP32 or bf16, the other passes in FP32 or
+// split bf16).
+static const int kBatchShapes[][2] = {{4, 4}, {8, 4}, {16, 2}, {16, 4}};
+constexpr int kNumBatchShapes = 4;
+
+int wave_batch_variant(const WGeom& g) {
+    if (g.rs != 1) return -1;
+    for (int v = 0; v < kNumBatchShapes; ++v)
+        if (g.IB <= kBatchShapes[v][0] && g.NB <= kBatchShapes[v][1]) return v;
+    return -1;
+}
+
+template <int OP, int CT, int IBT, int NBT>
+static hipError_t launch_wave_batch_t(const WaveJob* jobs, int njobs, int max_units, size_t lds,
+                                      hipStream_t s) {
+    hipLaunchKernelGGL((k_wave_batch<OP, CT, IBT, NBT>), dim3(max_units, njobs), dim3(kBlock), lds, s,
+                       jobs);
+    return hipGetLastError();
+}
+
+template <int OP, int CT>
+static hipError_t launch_wave_batch_v(int variant, const WaveJob* jobs, int njobs, int max_units,
+                                      size_t lds, hipStream_t s) {
+    switch (variant) {
+        case 0: return launch_wave_batch_t<OP, CT, 4, 4>(jobs, njobs, max_units, lds, s);
+        case 1: return launch_wave_batch_t<OP, CT, 8, 4>(jobs, njobs, max_units, lds, s);
+        case 2: return launch_wave_batch_t<OP, CT, 16, 2>(jobs, njobs, max_units, lds, s);
+        case 3: return launch_wave_batch_t<OP, CT, 16, 4>(jobs, njobs, max_units, lds, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_wave_batch(int op, int ct, int variant, const WaveJob* jobs, int njobs,
+                             int max_units, size_t lds, hipStream_t s) {
+    if (njobs < 1 || max_units < 1 || lds + kStaticLdsMargin > kLdsLimit) return hipErrorInvalidValue;
+    if (op == OP_SKETCH) {
+        if (ct == CT_F32) return launch_wave_batch_v<OP_SKETCH, CT_F32>(variant, jobs, njobs, max_units, lds, s);
+        if (ct == CT_BF16) return launch_wave_batch_v<OP_SKETCH, CT_BF16>(variant, jobs, njobs, max_units, lds, s);
+    } else if (op == OP_POWER) {
+        if (ct == CT_F32) return launch_wave_batch_v<OP_POWER, CT_F32>(variant, jobs, njobs, max_units, lds, s);
+        if (ct == CT_BF16X3) return launch_wave_batch_v<OP_POWER, CT_BF16X3>(variant, jobs, njobs, max_units, lds, s);
+    } else {
+        if (ct == CT_F32) return launch_wave_batch_v<OP_TTM, CT_F32>(variant, jobs, njobs, max_units, lds, s);
+        if (ct == CT_BF16X3) return launch_wave_batch_v<OP_TTM, CT_BF16X3>(variant, jobs, njobs, max_units, lds, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// The compute types that have batched instantiations for a pass.
+bool wave_batch_ct(int op, int ct) {
+    if (op == OP_SKETCH) return ct == CT_F32 || ct == CT_BF16;
+    return ct == CT_F32 || ct == CT_BF16X3;
 }
 
 }  // namespace rh

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <vector>
 
 #include "internal.hpp"
@@ -143,6 +144,8 @@ struct Step {
     int K, R;
     bool capped;
     Pass gs, gp, gt, gtr;
+    bool trunc_rot = false;       // the rotated truncation on its own kernel
+    rh::TruncGeom tg{};
 };
 
 struct Plan {
@@ -332,6 +335,8 @@ int32_t build_plan(const Problem& pr, int num_cu, Plan* pl) {
             if (pr.q > 0) track_stream(pl, st.gp, false);
             track_stream(pl, st.gt, true);
             track_stream(pl, st.gtr, false);
+            st.trunc_rot = pl->rotated && pr.kernels == RHOSVD_KERNELS_AUTO &&
+                           rh::plan_trunc(pr.dbl, st.K, st.T, st.R, num_cu, false, &st.tg);
             const int64_t IK = st.I * st.K;
             if (IK > pl->maxIK) pl->maxIK = IK;
             if (static_cast<int64_t>(st.K) * st.K > pl->maxKK) pl->maxKK = static_cast<int64_t>(st.K) * st.K;
@@ -673,8 +678,12 @@ int32_t run_r_sthosvd(const Plan& pl, const Buffers& b, const void* x, const rho
         RH_HIP(rh::launch_evd_factor(dbl, b.C, st.K, &b.rep->flags, b.qT, st.I, st.R, 1,
                                      out->factors[st.n], b.M, &b.rep->sigma[st.n][0], b.u64, s));
         void* dst = (si == N - 1) ? out->core : ((si % 2 == 0) ? b.ping : b.pong);
-        rc = ttm(pl, st.gtr, b.B, b.M, dst, nullptr, s, pl.rotated ? 1 : 0);
-        if (rc != RHOSVD_OK) return rc;
+        if (st.trunc_rot) {
+            RH_HIP(rh::launch_trunc(dbl, st.tg, b.B, b.M, dst, s));
+        } else {
+            rc = ttm(pl, st.gtr, b.B, b.M, dst, nullptr, s, pl.rotated ? 1 : 0);
+            if (rc != RHOSVD_OK) return rc;
+        }
         src = dst;
     }
     (void)e;
@@ -1031,8 +1040,13 @@ int32_t run_adaptive(rhosvd_ctx* ctx, Plan* pl, const Buffers& b, const rhosvd_t
             return RHOSVD_EUNSUPPORTED;
         void* dst = (n == N - 1) ? out->core : ((n % 2 == 0) ? b.ping : b.pong);
         if (n < N - 1 && R * T > ((n % 2 == 0) ? pl->ping : pl->pong)) return RHOSVD_EUNSUPPORTED;
-        rc = ttm(*pl, gtr, b.B, b.M, dst, nullptr, s, 1);
-        if (rc != RHOSVD_OK) return rc;
+        rh::TruncGeom tg;
+        if (pr.kernels == RHOSVD_KERNELS_AUTO && rh::plan_trunc(dbl, K, T, R, cu, false, &tg)) {
+            RH_HIP(rh::launch_trunc(dbl, tg, b.B, b.M, dst, s));
+        } else {
+            rc = ttm(*pl, gtr, b.B, b.M, dst, nullptr, s, 1);
+            if (rc != RHOSVD_OK) return rc;
+        }
         src = dst;
         d[n] = R;
     }
@@ -1448,6 +1462,17 @@ int32_t rhosvd_ttm(rhosvd_ctx* ctx, const void* src, int32_t dtype, int32_t prec
     return RHOSVD_OK;
 }
 
+int32_t rhosvd_truncate_rotated(rhosvd_ctx* ctx, int32_t dtype, const void* b, int32_t K, int64_t J,
+                                const void* m, int32_t R, void* out, void* stream) {
+    if (!ctx || !b || !m || !out) return RHOSVD_EINVAL;
+    if (dtype != RHOSVD_F32 && dtype != RHOSVD_F64) return RHOSVD_EINVAL;
+    if (K < 1 || R < 1 || R > K || J < 1) return RHOSVD_EINVAL;
+    rh::TruncGeom tg;
+    if (!rh::plan_trunc(dtype == RHOSVD_F64, K, J, R, ctx->num_cu, true, &tg)) return RHOSVD_EUNSUPPORTED;
+    RH_HIP(rh::launch_trunc(dtype == RHOSVD_F64, tg, b, m, out, static_cast<hipStream_t>(stream)));
+    return RHOSVD_OK;
+}
+
 int32_t rhosvd_orthonormalize(rhosvd_ctx* ctx, const double* y, int64_t I, int32_t K,
                               int32_t dtype, void* q_out, double* work, uint32_t* flags,
                               void* stream) {
@@ -1484,16 +1509,39 @@ namespace {
 
 constexpr int kBatchUnits = 64;          // most workgroups per item per pass
 
-enum BatchKind { BK_STREAM, BK_REDUCE, BK_QR, BK_EVD, BK_INIT, BK_NORMX, BK_FINISH };
+enum BatchKind { BK_STREAM, BK_REDUCE, BK_QR, BK_EVD, BK_INIT, BK_NORMX, BK_FINISH, BK_WAVE };
 
 struct BatchLaunch {
     int kind = 0, op = 0, njobs = 0, sel = 0;
+    int ct = 0, var = 0;              // BK_WAVE: compute type and shape of the instantiation
     size_t lds = 0, off = 0;
 };
 
-// Per pass of an item: re-plan the tiled geometry with the tuned tile width
-// cap and tiles per workgroup.
-void batch_pass(Pass* p, int op, int elem, int64_t I, int64_t T, int K, int cmax, int tpu) {
+// Per pass of an item: the wave kernel when an FP32 item's shape has a
+// batched instantiation (one 16-column block per wave, up to kBatchUnits
+// workgroups), else the tiled geometry with the tuned tile width cap and
+// tiles per workgroup.  Either depends on the item's own shape only.
+void batch_pass(Pass* p, int op, bool dbl, int ct, int elem, int64_t I, int64_t T, int K, int cmax,
+                int tpu) {
+    p->op = op;
+    p->dbl = dbl;
+    p->I = I;
+    p->K = K;
+    if (op == rh::OP_SKETCH && ct == rh::CT_FP8) ct = rh::CT_BF16;
+    rh::WGeom wg;
+    if (!dbl && rh::wave_batch_ct(op, ct) && rh::plan_wave(op, ct, 1, I, T, K, 256, &wg) &&
+        rh::wave_batch_variant(wg) >= 0) {
+        int64_t units = (wg.nblocks + 3) / 4;
+        if (units > kBatchUnits) units = kBatchUnits;
+        if (units < 1) units = 1;
+        wg.grid = static_cast<int>(units);
+        p->wg = wg;
+        p->kind = PASS_WAVE;
+        p->grid = wg.grid;
+        p->I_pad = wg.IB * 16;
+        p->K_pad = wg.NB * 16;
+        return;
+    }
     rh::StreamGeom g;
     if (!rh::plan_stream(op, elem, 1, I, T, K, 256, &g, cmax)) return;
     int64_t units = (g.ntiles + tpu - 1) / tpu;
@@ -1508,13 +1556,14 @@ void batch_pass(Pass* p, int op, int elem, int64_t I, int64_t T, int K, int cmax
 }
 
 void batch_geometry(Plan* pl, int cmax, int tpu) {
-    const int elem = static_cast<int>(pl->pr.elem);
-    for (int s = 0; s < pl->pr.N; ++s) {
+    const Problem& pr = pl->pr;
+    const int elem = static_cast<int>(pr.elem);
+    for (int s = 0; s < pr.N; ++s) {
         Step& st = pl->st[s];
-        batch_pass(&st.gs, rh::OP_SKETCH, elem, st.I, st.T, st.K, cmax, tpu);
-        batch_pass(&st.gp, rh::OP_POWER, elem, st.I, st.T, st.K, cmax, tpu);
-        batch_pass(&st.gt, rh::OP_TTM, elem, st.I, st.T, st.K, cmax, tpu);
-        batch_pass(&st.gtr, rh::OP_TTM, elem, st.K, st.T, st.R, cmax, tpu);
+        batch_pass(&st.gs, rh::OP_SKETCH, pr.dbl, pr.ct_sketch, elem, st.I, st.T, st.K, cmax, tpu);
+        batch_pass(&st.gp, rh::OP_POWER, pr.dbl, pr.ct_power, elem, st.I, st.T, st.K, cmax, tpu);
+        batch_pass(&st.gt, rh::OP_TTM, pr.dbl, pr.ct_ttm, elem, st.I, st.T, st.K, cmax, tpu);
+        batch_pass(&st.gtr, rh::OP_TTM, pr.dbl, pr.ct_trunc, elem, st.K, st.T, st.R, cmax, tpu);
     }
 }
 
@@ -1576,6 +1625,48 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
         L.off = tw->put(jobs);
         B->prog.push_back(L);
     };
+    // one pass of every item: the tiled ones in one launch, the wave ones in
+    // one launch per (compute type, shape) of the batched instantiations
+    struct PassJob {
+        const Pass* p;
+        rh::StreamArgs a;
+    };
+    auto add_pass = [&](int op, const std::vector<PassJob>& jobs) {
+        std::vector<rh::StreamJob> tiled;
+        std::map<std::pair<int, int>, std::vector<rh::WaveJob>> wave;
+        for (const PassJob& pj : jobs) {
+            if (pj.p->kind == PASS_WAVE) {
+                rh::WaveJob w{};
+                w.g = pj.p->wg;
+                w.a = pj.a;
+                w.units = pj.p->grid;
+                w.want_ss = pj.a.part_ss != nullptr;
+                w.want_gram = pj.a.part_g != nullptr;
+                wave[{pj.p->wg.ct, rh::wave_batch_variant(pj.p->wg)}].push_back(w);
+            } else {
+                rh::StreamJob j{};
+                j.g = pj.p->sg;
+                j.units = pj.p->grid;
+                j.a = pj.a;
+                tiled.push_back(j);
+            }
+        }
+        add_stream(op, tiled);
+        for (auto& kv : wave) {
+            BatchLaunch L;
+            L.kind = BK_WAVE;
+            L.op = op;
+            L.ct = kv.first.first;
+            L.var = kv.first.second;
+            L.njobs = static_cast<int>(kv.second.size());
+            for (auto& w : kv.second) {
+                L.sel = std::max(L.sel, w.units);
+                L.lds = std::max(L.lds, w.g.lds_bytes);
+            }
+            L.off = tw->put(kv.second);
+            B->prog.push_back(L);
+        }
+    };
     auto add_reduce = [&](std::vector<rh::ReduceJob>& jobs) {
         if (jobs.empty()) return;
         BatchLaunch L;
@@ -1624,7 +1715,7 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
     }
     for (int s = 0; s < N; ++s) {
         // sketch, reduction, (norm of X), QR
-        std::vector<rh::StreamJob> sj;
+        std::vector<PassJob> sj;
         std::vector<rh::ReduceJob> rj;
         std::vector<rh::QrJob> qj;
         std::vector<rh::SumJob> nj;
@@ -1632,9 +1723,7 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
             const Plan& pl = *B->plans[i];
             const Step& st = pl.st[s];
             const Buffers& b = bufs[i];
-            rh::StreamJob j{};
-            j.g = st.gs.sg;
-            j.units = st.gs.grid;
+            PassJob j{&st.gs, rh::StreamArgs{}};
             j.a.src = cur[i];
             j.a.part_y = b.part;
             j.a.part_ss = s == 0 ? b.part_ss : nullptr;
@@ -1647,7 +1736,7 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
             qj.push_back(rh::QrJob{b.y, b.q64, b.qT, static_cast<int>(st.I), st.K, B->dbl ? 1 : 0});
             if (s == 0) nj.push_back(rh::SumJob{b.part_ss, b.rep, st.gs.grid});
         }
-        add_stream(rh::OP_SKETCH, sj);
+        add_pass(rh::OP_SKETCH, sj);
         add_reduce(rj);
         if (s == 0) {
             BatchLaunch L;
@@ -1659,7 +1748,7 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
         add_qr(qj);
         // power steps (items with more power steps than it)
         for (int it = 0; it < B->maxq; ++it) {
-            std::vector<rh::StreamJob> pj;
+            std::vector<PassJob> pj;
             std::vector<rh::ReduceJob> prj;
             std::vector<rh::QrJob> pqj;
             for (int i = 0; i < n; ++i) {
@@ -1667,9 +1756,7 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
                 if (pl.pr.q <= it) continue;
                 const Step& st = pl.st[s];
                 const Buffers& b = bufs[i];
-                rh::StreamJob j{};
-                j.g = st.gp.sg;
-                j.units = st.gp.grid;
+                PassJob j{&st.gp, rh::StreamArgs{}};
                 j.a.src = cur[i];
                 j.a.mat = b.qT;
                 j.a.part_y = b.part;
@@ -1679,21 +1766,19 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
                 pqj.push_back(rh::QrJob{b.y, b.q64, b.qT, static_cast<int>(st.I), st.K,
                                         B->dbl ? 1 : 0});
             }
-            add_stream(rh::OP_POWER, pj);
+            add_pass(rh::OP_POWER, pj);
             add_reduce(prj);
             add_qr(pqj);
         }
         // projection B = Q^T S_(n) with its Gram, the Gram reduction
-        std::vector<rh::StreamJob> tj;
+        std::vector<PassJob> tj;
         std::vector<rh::ReduceJob> gj;
         std::vector<rh::EvdJob> ej;
         for (int i = 0; i < n; ++i) {
             const Plan& pl = *B->plans[i];
             const Step& st = pl.st[s];
             const Buffers& b = bufs[i];
-            rh::StreamJob j{};
-            j.g = st.gt.sg;
-            j.units = st.gt.grid;
+            PassJob j{&st.gt, rh::StreamArgs{}};
             j.a.src = cur[i];
             j.a.mat = b.qT;
             j.a.out = b.B;
@@ -1716,7 +1801,7 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
             e.staged = rh::evd_factor_staged(st.K, st.I) ? 1 : 0;
             ej.push_back(e);
         }
-        add_stream(rh::OP_TTM, tj);
+        add_pass(rh::OP_TTM, tj);
         add_reduce(gj);
         for (int kb = 8; kb <= 64; kb += 8) {
             std::vector<rh::EvdJob> sub;
@@ -1736,15 +1821,13 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
             B->prog.push_back(L);
         }
         // truncation S <- Ubar_R^T B, written rotated
-        std::vector<rh::StreamJob> rj2;
+        std::vector<PassJob> rj2;
         for (int i = 0; i < n; ++i) {
             const Plan& pl = *B->plans[i];
             const Step& st = pl.st[s];
             const Buffers& b = bufs[i];
             void* dst = (s == N - 1) ? B->core[i] : ((s % 2 == 0) ? b.ping : b.pong);
-            rh::StreamJob j{};
-            j.g = st.gtr.sg;
-            j.units = st.gtr.grid;
+            PassJob j{&st.gtr, rh::StreamArgs{}};
             j.a.src = b.B;
             j.a.mat = b.M;
             j.a.out = dst;
@@ -1752,7 +1835,7 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
             rj2.push_back(j);
             cur[i] = dst;
         }
-        add_stream(rh::OP_TTM, rj2);
+        add_pass(rh::OP_TTM, rj2);
     }
     {
         std::vector<rh::FinishJob> fj(n);
@@ -1795,6 +1878,10 @@ hipError_t run_program(const rhosvd_batch* B, hipStream_t s) {
             case BK_FINISH:
                 e = rh::launch_batch_finish(B->dbl, static_cast<const rh::FinishJob*>(t), L.njobs, s);
                 break;
+            case BK_WAVE:
+                e = rh::launch_wave_batch(L.op, L.ct, L.var, static_cast<const rh::WaveJob*>(t),
+                                          L.njobs, L.sel, L.lds, s);
+                break;
             default:
                 e = hipErrorInvalidValue;
         }
@@ -1806,7 +1893,9 @@ hipError_t run_program(const rhosvd_batch* B, hipStream_t s) {
 // Upper bound of the tables: every launch holds at most one job per item.
 size_t tables_bound(int n, int N, int maxq) {
     const size_t per_item_jobs = static_cast<size_t>(N) * (7 + 3 * maxq) + 3;
-    return (per_item_jobs * n * sizeof(rh::StreamJob) + 256 * (N * (12 + 8 * maxq) + 8) + 4095) &
+    // a pass may split into one tiled and four wave launches per compute type
+    const size_t job = std::max(sizeof(rh::StreamJob), sizeof(rh::WaveJob));
+    return (per_item_jobs * n * job + 256 * (N * (12 + 8 * maxq) * 9 + 8) + 4095) &
            ~static_cast<size_t>(4095);
 }
 
@@ -1822,6 +1911,7 @@ int32_t time_candidate(rhosvd_batch* B, int cmax, int tpu, hipStream_t s, float*
         Buffers b;
         carve(pl, B->ws + B->region[i], &b);
         const Step& st = pl.st[0];
+        if (st.gs.kind != PASS_TILED) continue;       // the wave kernels take no tile parameters
         rh::StreamJob j{};
         j.g = st.gs.sg;
         j.units = st.gs.grid;
@@ -1833,6 +1923,10 @@ int32_t time_candidate(rhosvd_batch* B, int cmax, int tpu, hipStream_t s, float*
         jobs.push_back(j);
         lds = std::max(lds, j.g.lds_bytes);
         maxu = std::max(maxu, j.units);
+    }
+    if (jobs.empty()) {
+        *ms = 0.0f;
+        return RHOSVD_OK;
     }
     RH_HIP(hipMemcpy(B->ws, jobs.data(), jobs.size() * sizeof(rh::StreamJob), hipMemcpyHostToDevice));
     hipEvent_t e0, e1;

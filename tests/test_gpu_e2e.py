@@ -85,6 +85,28 @@ def test_fp64_matches_oracle(dims, ranks, p, q, algo):
     np.testing.assert_allclose(core, ref.core, atol=1e-7 * np.max(np.abs(ref.core)))
 
 
+# wide ranks: the rotated truncation with one to four row tiles of 16 and
+# sketch widths up to 62 (FP32), up to 32 in FP64, and a width past 32 there
+WIDE = [((72, 66, 60), (40, 50, 26), 12, 1), ((48, 40, 36), (28, 14, 30), 4, 0), ((40, 30, 20), (9, 3, 12), 3, 1)]
+
+
+@pytest.mark.parametrize("dims,ranks,p,q", WIDE)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_wide_ranks_match_oracle(dims, ranks, p, q, dtype):
+    x, _, _ = tucker_tensor(dims, ranks, seed=35, noise=0.05, dtype=dtype)
+    res, core, facs = _run("r_sthosvd", x, ranks, p, q, seed=6)
+    ref = o_rst(x.astype(np.float64), ranks, p, q, seed=6)
+    if dtype == np.float64:
+        _compare(res, core, facs, ref, 1e-10, 1e-9, 1e-8)
+        np.testing.assert_allclose(core, ref.core, atol=1e-7 * np.max(np.abs(ref.core)))
+    else:
+        # the core through the reconstruction, which does not depend on the
+        # basis chosen within a cluster of close singular values
+        _compare(res, core, facs, ref, 1e-5, 1e-5, 1e-4)
+        xh, xo = tucker_to_full(core, facs), tucker_to_full(ref.core, ref.factors)
+        assert np.sqrt(frob2(xh - xo) / frob2(xo)) <= 1e-4
+
+
 @pytest.mark.parametrize("algo", ["r_sthosvd", "rp_hosvd"])
 @pytest.mark.parametrize("p,q", [(0, 0), (5, 1)])
 def test_exact_recovery(algo, p, q):

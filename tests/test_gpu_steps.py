@@ -320,3 +320,38 @@ def test_tall_mode_steps(dims, n, K, precision):
     _close_cols(unfold(got, n).T, unfold(want, n).T, t_tt)
     b = unfold(want, n)
     _close_cols(gram.cpu().numpy(), b @ b.T, t_tt)
+
+
+# (K, R, J): every row-tile count (R up to 16, 32, 48, 64) and step bound
+# (K up to 16, 32, 48, 64), a ragged last chunk, one column, one whole
+# chunk, and enough columns for several chunks per wave of the full grid
+TRUNC_CASES = [(35, 25, 8013), (16, 16, 1000), (32, 20, 777), (48, 40, 3001), (64, 64, 5000),
+               (64, 50, 64), (7, 3, 1), (35, 25, 600011), (13, 13, 129)]
+
+
+@pytest.mark.parametrize("K,R,J", TRUNC_CASES + [(32, 30, 2500), (12, 5, 130), (3, 1, 70)])
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_truncate_rotated(K, R, J, dtype):
+    """Algorithm 8 step 4 in the rotated layout: out = M^T B, row r of out
+    contiguous, on the truncation kernel, against the float64 product."""
+    if dtype == np.float64 and K > 32:
+        pytest.skip("FP64 truncation kernel takes K <= 32")
+    rng = np.random.default_rng(K * 1000 + R + J)
+    b = rng.standard_normal((K, J)).astype(dtype)
+    m = rng.standard_normal((K, R)).astype(dtype)
+    bd = torch.from_numpy(np.ascontiguousarray(b.reshape(-1, order="F"))).cuda()
+    out = api.truncate_rotated(bd, K, J, torch.from_numpy(m).cuda())
+    got = out.cpu().numpy().astype(np.float64).reshape(R, J)
+    want = m.astype(np.float64).T @ b.astype(np.float64)
+    # a sum of K products in the data's precision: K eps sum |m| |b| bounds it
+    bound = K * (6e-8 if dtype == np.float32 else 1.2e-16) * (np.abs(m).T @ np.abs(b)) + 1e-300
+    assert np.all(np.abs(got - want) <= bound)
+
+
+def test_truncate_rotated_rejects():
+    b = torch.zeros(65 * 10, dtype=torch.float32, device="cuda")
+    with pytest.raises(api.L.RhosvdError):
+        api.truncate_rotated(b, 65, 10, torch.zeros(65, 3, dtype=torch.float32, device="cuda"))
+    b = torch.zeros(33 * 10, dtype=torch.float64, device="cuda")
+    with pytest.raises(api.L.RhosvdError):
+        api.truncate_rotated(b, 33, 10, torch.zeros(33, 3, dtype=torch.float64, device="cuda"))

@@ -828,22 +828,22 @@ __device__ __forceinline__ double wave_total(double v) {
 
 // ---------------------------------------------------------------------------
 // Householder QR of Y (I x K column-major FP64, K <= I <= 16 RPL, K <= 64) in
-// one workgroup (Golub & Van Loan, Matrix Computations, 5.2.1, with the
-// backward accumulation of Q of 5.1.6).  Column c = 16 s + 4 g + w lives in
-// wave w, lane group g (lanes 16 g .. 16 g + 15, one DPP row) and register
-// slot s; lane 16 g + t holds its rows t + 16 r (r < RPL = 16 or 32).  A column's dot product is
-// then one reduction within a DPP row, and one reduction serves the four
-// columns of a slot together.  Column step j: its group forms the reflector
-// H_j = I - tau v v^T (v_j = A(j,j) - alpha, v_i = A(i,j) below, alpha =
-// -sign(A(j,j)) norm(A(j:,j))) and broadcasts v through LDS; every wave
-// applies H_j to its columns past j.  The outer loop runs over the slots
-// (unrolled), the inner over the 16 columns of a slot, so register indices
-// are constants (row j sits in register r = j / 16 = the slot) and the
-// slots before the current one drop out at compile time.  Then Q =
-// H_0 ... H_{K-1} [I_K; 0] backwards, each wave on its own columns from the
-// stored reflectors (no barriers), and columns with alpha < 0 negated:
-// diag(R) >= 0, the same Q as CholeskyQR for full-rank Y.  One barrier per
-// column step; LDS: K x 16 RPL doubles of reflectors.
+// one workgroup of W waves (Golub & Van Loan, Matrix Computations, 5.2.1, with
+// the backward accumulation of Q of 5.1.6).  Column c = 4 W s + W g + w lives
+// in wave w, lane group g (lanes 16 g .. 16 g + 15, one DPP row) and register
+// slot s; lane 16 g + t holds its rows t + 16 r (r < RPL = 16 or 32).  A
+// column's dot product is then one reduction within a DPP row, and one
+// reduction serves the four columns of a slot in a wave together.  Column
+// step j: its group forms the reflector H_j = I - tau v v^T (v_j = A(j,j) -
+// alpha, v_i = A(i,j) below, alpha = -sign(A(j,j)) norm(A(j:,j))) and
+// broadcasts v through LDS; every wave applies H_j to its columns past j.  The
+// loops over slots and 16-column sub-blocks are unrolled, the inner one over
+// 16 columns is not, so register indices are constants (row j sits in
+// register j / 16) and the slots before the current one drop out at compile
+// time.  Then Q = H_0 ... H_{K-1} [I_K; 0] backwards, each wave on its own
+// columns from the stored reflectors (no barriers), and columns with
+// alpha < 0 negated: diag(R) >= 0, the same Q as CholeskyQR for full-rank Y.
+// One barrier per column step; LDS: K x 16 RPL doubles of reflectors.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double row16_total(double v) {
     v += dpp_d<0xB1>(v);    // quad_perm [1, 0, 3, 2]
@@ -853,73 +853,82 @@ __device__ __forceinline__ double row16_total(double v) {
     return v;
 }
 
-template <int NS, int RPL>
+template <int W, int NS, int RPL>
 __device__ __forceinline__ void hqr_body(const double* __restrict__ y, int I, int K,
                                          double* __restrict__ q64, void* q_out, int dbl) {
     extern __shared__ __align__(16) double shd[];
     constexpr int VP = 16 * RPL;                   // rows held: 16 lanes x RPL
+    constexpr int SW = 4 * W;                      // columns per slot
+    constexpr int SB = SW / 16;                    // 16-column sub-blocks of a slot
+    static_assert(W >= 4 && W % 4 == 0, "a slot holds whole 16-column sub-blocks");
     double* V = shd;                               // reflector j at V[j * VP + row]
     __shared__ double tau_s[RHOSVD_MAX_K], alpha_s[RHOSVD_MAX_K];
     const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
     const int g = lane >> 4, t = lane & 15;
-    const int cw = 4 * g + wave;                   // column within a slot
+    const int cw = W * g + wave;                   // column within a slot
     double a[NS][RPL];
 #pragma unroll
     for (int m = 0; m < NS; ++m)
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
-            const int c = 16 * m + cw, row = t + 16 * r;
+            const int c = SW * m + cw, row = t + 16 * r;
             a[m][r] = (c < K && row < I) ? y[static_cast<size_t>(c) * I + row] : 0.0;
         }
+    // column step j = SW m + 16 rb + jc (row j sits in register SB m + rb of
+    // lane jc of its group: a compile-time index)
 #pragma unroll
     for (int m = 0; m < NS; ++m) {
-#pragma unroll 1
-        for (int jc = 0; jc < 16; ++jc) {          // jc = 4 og + ow
-            const int j = 16 * m + jc;
-            if (j >= K) break;
-            const int ow = jc & 3, og = jc >> 2;
-            if (wave == ow) {
-                double s4[4] = {0.0, 0.0, 0.0, 0.0};     // four independent chains
 #pragma unroll
-                for (int r = 0; r < RPL; ++r) {
-                    const double x = t + 16 * r >= j ? a[m][r] : 0.0;
-                    s4[r & 3] = fma(x, x, s4[r & 3]);
-                }
-                const double s2 = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-                const double n2 = readlane_d(row16_total(s2), 16 * og);
-                const double ajj = readlane_d(a[m][m], 16 * og + jc);   // row j: t = jc, r = m
-                const double alpha = (ajj > 0.0 ? -1.0 : 1.0) * sqrt(n2);
-                const double v0 = ajj - alpha;
-                const double vn2 = fma(v0, v0, n2 - ajj * ajj);
-                const double tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
-                if (g == og) {
+        for (int rb = 0; rb < SB; ++rb) {
+#pragma unroll 1
+            for (int jc = 0; jc < 16; ++jc) {
+                const int js = 16 * rb + jc;           // column within the slot: W og + ow
+                const int j = SW * m + js;
+                if (j >= K) break;                     // uniform
+                const int ow = js % W, og = js / W;
+                if (wave == ow) {
+                    double s4[4] = {0.0, 0.0, 0.0, 0.0};     // four independent chains
 #pragma unroll
                     for (int r = 0; r < RPL; ++r) {
-                        const int row = t + 16 * r;
-                        V[j * VP + row] = row == j ? v0 : (row > j ? a[m][r] : 0.0);
+                        const double x = t + 16 * r >= j ? a[m][r] : 0.0;
+                        s4[r & 3] = fma(x, x, s4[r & 3]);
+                    }
+                    const double s2 = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+                    const double n2 = readlane_d(row16_total(s2), 16 * og);
+                    const double ajj = readlane_d(a[m][SB * m + rb], 16 * og + jc);
+                    const double alpha = (ajj > 0.0 ? -1.0 : 1.0) * sqrt(n2);
+                    const double v0 = ajj - alpha;
+                    const double vn2 = fma(v0, v0, n2 - ajj * ajj);
+                    const double tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+                    if (g == og) {
+#pragma unroll
+                        for (int r = 0; r < RPL; ++r) {
+                            const int row = t + 16 * r;
+                            V[j * VP + row] = row == j ? v0 : (row > j ? a[m][r] : 0.0);
+                        }
+                    }
+                    if (lane == 0) {
+                        tau_s[j] = tau;
+                        alpha_s[j] = alpha;
                     }
                 }
-                if (lane == 0) {
-                    tau_s[j] = tau;
-                    alpha_s[j] = alpha;
+                __syncthreads();
+                const double tau = tau_s[j];
+                double v[RPL];
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) v[r] = V[j * VP + t + 16 * r];
+                // columns past j: every later slot, and in slot m the columns
+                // after js (columns past K are zero and stay zero)
+#pragma unroll
+                for (int mm = m; mm < NS; ++mm) {
+                    double d4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) d4[r & 3] = fma(v[r], a[mm][r], d4[r & 3]);
+                    double d = row16_total((d4[0] + d4[1]) + (d4[2] + d4[3])) * tau;
+                    if (mm == m) d = cw > js ? d : 0.0;
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) a[mm][r] = fma(-d, v[r], a[mm][r]);
                 }
-            }
-            __syncthreads();
-            const double tau = tau_s[j];
-            double v[RPL];
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) v[r] = V[j * VP + t + 16 * r];
-            // columns past j: every later slot, and in slot m the columns
-            // after jc (columns past K are zero and stay zero)
-#pragma unroll
-            for (int mm = m; mm < NS; ++mm) {
-                double d4[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int r = 0; r < RPL; ++r) d4[r & 3] = fma(v[r], a[mm][r], d4[r & 3]);
-                double d = row16_total((d4[0] + d4[1]) + (d4[2] + d4[3])) * tau;
-                if (mm == m) d = cw > jc ? d : 0.0;
-#pragma unroll
-                for (int r = 0; r < RPL; ++r) a[mm][r] = fma(-d, v[r], a[mm][r]);
             }
         }
     }
@@ -930,34 +939,38 @@ __device__ __forceinline__ void hqr_body(const double* __restrict__ y, int I, in
     for (int m = 0; m < NS; ++m)
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
-            const int c = 16 * m + cw;
+            const int c = SW * m + cw;
             q[m][r] = (c < K && t + 16 * r == c) ? 1.0 : 0.0;
         }
 #pragma unroll
     for (int m = NS - 1; m >= 0; --m) {
+#pragma unroll
+        for (int rb = SB - 1; rb >= 0; --rb) {
 #pragma unroll 1
-        for (int jc = 15; jc >= 0; --jc) {
-            const int j = 16 * m + jc;
-            if (j >= K) continue;
-            const double tau = tau_s[j];
-            double v[RPL];
+            for (int jc = 15; jc >= 0; --jc) {
+                const int js = 16 * rb + jc;
+                const int j = SW * m + js;
+                if (j >= K) continue;
+                const double tau = tau_s[j];
+                double v[RPL];
 #pragma unroll
-            for (int r = 0; r < RPL; ++r) v[r] = V[j * VP + t + 16 * r];
+                for (int r = 0; r < RPL; ++r) v[r] = V[j * VP + t + 16 * r];
 #pragma unroll
-            for (int mm = m; mm < NS; ++mm) {
-                double d4[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int mm = m; mm < NS; ++mm) {
+                    double d4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int r = 0; r < RPL; ++r) d4[r & 3] = fma(v[r], q[mm][r], d4[r & 3]);
-                double d = row16_total((d4[0] + d4[1]) + (d4[2] + d4[3])) * tau;
-                if (mm == m) d = cw >= jc ? d : 0.0;
+                    for (int r = 0; r < RPL; ++r) d4[r & 3] = fma(v[r], q[mm][r], d4[r & 3]);
+                    double d = row16_total((d4[0] + d4[1]) + (d4[2] + d4[3])) * tau;
+                    if (mm == m) d = cw >= js ? d : 0.0;
 #pragma unroll
-                for (int r = 0; r < RPL; ++r) q[mm][r] = fma(-d, v[r], q[mm][r]);
+                    for (int r = 0; r < RPL; ++r) q[mm][r] = fma(-d, v[r], q[mm][r]);
+                }
             }
         }
     }
 #pragma unroll
     for (int m = 0; m < NS; ++m) {
-        const int c = 16 * m + cw;
+        const int c = SW * m + cw;
         if (c < K) {
             const double sg = alpha_s[c] < 0.0 ? -1.0 : 1.0;
 #pragma unroll
@@ -977,27 +990,31 @@ __device__ __forceinline__ void hqr_body(const double* __restrict__ y, int I, in
     }
 }
 
-template <int NS, int RPL>
-__global__ __launch_bounds__(kBlock) void k_hqr(const double* __restrict__ y, int I, int K,
+// W = 4 waves: measured at I = 200, K = 35, 44 us against 48 (8 waves) and
+// 50 (16 waves): the column steps are bound by the reflector's broadcast and
+// the barrier, which more waves make slower, not by the updates they share
+template <int W, int NS, int RPL>
+__global__ __launch_bounds__(64 * W) void k_hqr(const double* __restrict__ y, int I, int K,
                                                 double* __restrict__ q64, void* q_out, int dbl) {
-    hqr_body<NS, RPL>(y, I, K, q64, q_out, dbl);
+    hqr_body<W, NS, RPL>(y, I, K, q64, q_out, dbl);
 }
 
 // One QR per workgroup from a device table (many small problems in one launch).
 template <int NS, int RPL>
 __global__ __launch_bounds__(kBlock) void k_hqr_batch(const QrJob* __restrict__ jobs) {
     const QrJob j = jobs[blockIdx.x];
-    hqr_body<NS, RPL>(j.y, j.I, j.K, j.q64, j.q_out, j.dbl);
+    hqr_body<kBlock / kWave, NS, RPL>(j.y, j.I, j.K, j.q64, j.q_out, j.dbl);
 }
 
 static hipError_t launch_hqr(const double* y, int I, int K, bool dbl, void* q_out, double* q64,
                              hipStream_t s) {
+    constexpr int W = kBlock / kWave;
     const int rpl = I <= 256 ? 16 : 32;
     const size_t lds = static_cast<size_t>(K) * 16 * rpl * sizeof(double);
     const int d = dbl ? 1 : 0;
-#define RH_HQR_CASE(N, R)                                                                        \
-    case N:                                                                                      \
-        hipLaunchKernelGGL((k_hqr<N, R>), dim3(1), dim3(kBlock), lds, s, y, I, K, q64, q_out, d); \
+#define RH_HQR_CASE(N, R)                                                                           \
+    case N:                                                                                         \
+        hipLaunchKernelGGL((k_hqr<W, N, R>), dim3(1), dim3(kBlock), lds, s, y, I, K, q64, q_out, d); \
         break;
     if (rpl == 16) {
         switch ((K + 15) / 16) {
@@ -1033,34 +1050,41 @@ hipError_t launch_hqr_fwd(const double* y, int I, int K, bool dbl, void* q_out, 
 // to I16 rows) at Qs (LDS, or global scratch when it does not fit); U is
 // formed on the f64 matrix cores in place of Q, one 16-row block per wave at
 // a time.  Vs: K x K column-major (LDS), lamS: K (LDS).
-template <typename T>
+// Elements tid + u kBlock (u < QN) of Q, loaded early in the EVD kernel so
+// that their latency is hidden behind the tridiagonal phases: 32 per thread,
+// 8 for K > 48, whose eigenvector phases need the registers.
+template <int KB>
+constexpr int q_prefetch() { return KB > 48 ? 8 : 32; }
+
+template <typename T, int QN>
 __device__ void factor_step(int K, int K16, int I, int I16, int R, int use_v, const double* Vs,
                             const double* lamS, const T* __restrict__ q, double* Qs,
                             T* __restrict__ u_out, T* __restrict__ m_out,
-                            double* __restrict__ sigma) {
+                            double* __restrict__ sigma, const T (&qpre)[QN]) {
     __shared__ double sgn[RHOSVD_MAX_K];
     const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
     // odd row pitch: a column walk (consecutive rows, one column) spreads
     // over the LDS banks instead of hitting the same two
     const int QP = K16 + 1;
-    // the padding first, then Q in its own column-major order (coalesced),
-    // 32 loads in flight per thread (one round up to 8192 elements)
-    for (int e = tid; e < I16 * QP; e += kBlock) {
-        const int i = e / QP, k = e - i * QP;
-        if (i >= I || k >= K) Qs[e] = 0.0;
-    }
+    // the padding first (rows I.. as one range, then columns K.. of each
+    // row), then Q in its own column-major order (coalesced): the first
+    // round from the registers loaded early, later ones (past QN kBlock
+    // elements) with QN loads in flight per thread
+    for (int e = I * QP + tid; e < I16 * QP; e += kBlock) Qs[e] = 0.0;
+    for (int i = tid; i < I; i += kBlock)
+        for (int k = K; k < QP; ++k) Qs[i * QP + k] = 0.0;
     const int n = I * K;
-    for (int e0 = tid; e0 < n; e0 += 32 * kBlock) {
-        T v[32];
+    for (int e0 = tid; e0 < n; e0 += QN * kBlock) {
+        T v[QN];
 #pragma unroll
-        for (int u = 0; u < 32; ++u) {
+        for (int u = 0; u < QN; ++u) {
             const int e = e0 + u * kBlock;
-            v[u] = q[e < n ? e : n - 1];
+            v[u] = e0 == tid ? qpre[u] : q[e < n ? e : n - 1];
         }
         int k = e0 / I, i = e0 - k * I;
         const int dk = kBlock / I, di = kBlock - dk * I;
 #pragma unroll
-        for (int u = 0; u < 32; ++u) {
+        for (int u = 0; u < QN; ++u) {
             if (e0 + u * kBlock < n) Qs[i * QP + k] = static_cast<double>(v[u]);
             i += di;
             k += dk;
@@ -1115,18 +1139,25 @@ __device__ void factor_step(int K, int K16, int I, int I16, int R, int use_v, co
         }
     }
     __syncthreads();
-    for (int r = wave; r < R; r += kBlock / kWave) {
+    {
+        // canonical signs, every column at once: four consecutive threads per
+        // column (R <= 64), each scanning rows sub, sub + 4, ... in ascending
+        // order (a strict > keeps the lowest row among equal magnitudes), then
+        // the quad combined with the same rule
+        const int r = tid >> 2, sub = tid & 3;
         double best = -1.0;
         int bi = 0x7fffffff;
-        for (int i = lane; i < I; i += kWave) {
-            const double a = fabs(Qs[i * QP + r]);
-            if (a > best) {
-                best = a;
-                bi = i;
+        if (r < R) {
+            for (int i = sub; i < I; i += 4) {
+                const double a = fabs(Qs[i * QP + r]);
+                if (a > best) {
+                    best = a;
+                    bi = i;
+                }
             }
         }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
+        for (int o = 1; o < 4; o <<= 1) {
             const double ob = __shfl_xor(best, o, kWave);
             const int oi = __shfl_xor(bi, o, kWave);
             if (ob > best || (ob == best && oi < bi)) {
@@ -1134,7 +1165,7 @@ __device__ void factor_step(int K, int K16, int I, int I16, int R, int use_v, co
                 bi = oi;
             }
         }
-        if (lane == 0) sgn[r] = (Qs[bi * QP + r] < 0.0) ? -1.0 : 1.0;
+        if (sub == 0 && r < R) sgn[r] = (Qs[bi * QP + r] < 0.0) ? -1.0 : 1.0;
     }
     __syncthreads();
     for (int e = tid; e < I * R; e += kBlock) {
@@ -1295,6 +1326,18 @@ __device__ __forceinline__ void evd_tri_body(const double* __restrict__ cin, int
             stats[1] = 2.2250738585072014e-308 * emax;
         }
     }
+    // the factor step's first round of Q (waves 1-3 load it while wave 0
+    // tridiagonalises; used only after the last phase)
+    constexpr int QN = q_prefetch<KB>();
+    T qpre[QN];
+    if constexpr (FACTOR) {
+        const int n = I * K;
+#pragma unroll
+        for (int u = 0; u < QN; ++u) {
+            const int e = tid + u * kBlock;
+            qpre[u] = q[e < n ? e : n - 1];
+        }
+    }
     __syncthreads();
 
     // ---- 2. eigenvalues by multisection (all threads; 7 lanes per eigenvalue) ----
@@ -1349,23 +1392,24 @@ __device__ __forceinline__ void evd_tri_body(const double* __restrict__ cin, int
     }
     __syncthreads();
 
-    // ---- 3-4. eigenvectors (wave 0, lane j = eigenvalue j) ----
+    // ---- 3-4. eigenvectors (wave 0, lane j = eigenvalue j); the check (5)
+    // runs in wave 1 beside the back-transformation in wave 0 ----
+    const double tn = stats[0];
+    const double ctol = kClusterGap * tn;                      // cluster distance
+    const int jl = lane < K ? lane : K - 1;
+    const double lj = lam[jl];
+    // cluster id: the number of gaps above ctol below this eigenvalue;
+    // mates: bit m set when eigenvalue m has a later member of its cluster
+    int cid = 0;
+    for (int q = 1; q <= jl; ++q) cid += (lam[q] - lam[q - 1] > ctol) ? 1 : 0;
+    const bool has_mate = lane + 1 < K && (lam[lane + 1] - lam[lane] <= ctol);
+    const uint64_t mates = __ballot(has_mate);
+    double z[KB];
     if (wave == 0) {
-        const double tn = stats[0];
         const double tiny = 2.2e-16 * fmax(tn, 1e-300);      // pivot floor of T - lambda I
-        const double ctol = kClusterGap * tn;                  // cluster distance
-        const int jl = lane < K ? lane : K - 1;
-        const double lj = lam[jl];
-        // cluster id: the number of gaps above ctol below this eigenvalue;
-        // mates: bit m set when eigenvalue m has a later member of its cluster
-        int cid = 0;
-        for (int q = 1; q <= jl; ++q) cid += (lam[q] - lam[q - 1] > ctol) ? 1 : 0;
-        const bool has_mate = lane + 1 < K && (lam[lane + 1] - lam[lane] <= ctol);
-        uint64_t mates = __ballot(has_mate);
         double* u1 = lu;
         double* u2 = lu + K * kWave;
         double* u3 = lu + 2 * K * kWave;
-        double z[KB];
         {
             double s2 = 0.0;
 #pragma unroll
@@ -1467,57 +1511,63 @@ __device__ __forceinline__ void evd_tri_body(const double* __restrict__ cin, int
             for (int i = 0; i < KB; ++i) z[i] *= inv;
             if (__ballot(!conv) == 0ull) break;           // wave-uniform
         }
+        // the vectors for the check
+        if (lane < K) {
+#pragma unroll
+            for (int i = 0; i < KB; ++i) zs[lane * kTriP + i] = z[i];
+        }
+    }
+    __syncthreads();
+    if (wave == 1) {
         // convergence check: residual norm(T z - lambda z) against norm(T),
         // and orthogonality to the neighbouring vectors and to the cluster's
         // (vectors of eigenvalues further apart than the cluster distance
         // are orthogonal to about eps norm(T) / gap by construction)
-        {
-            double tz[KB];
+        double zc[KB];
 #pragma unroll
-            for (int i = 0; i < KB; ++i) {
-                double t = 0.0;
-                if (i < K) {
-                    t = dd[i] * z[i];
-                    if (i > 0) t = fma(ee[i - 1], z[i - 1], t);
-                    if (i + 1 < KB && i + 1 < K) t = fma(ee[i], z[i + 1], t);
-                }
-                tz[i] = t;
+        for (int i = 0; i < KB; ++i) zc[i] = zs[jl * kTriP + i];
+        double tz[KB];
+#pragma unroll
+        for (int i = 0; i < KB; ++i) {
+            double t = 0.0;
+            if (i < K) {
+                t = dd[i] * zc[i];
+                if (i > 0) t = fma(ee[i - 1], zc[i - 1], t);
+                if (i + 1 < KB && i + 1 < K) t = fma(ee[i], zc[i + 1], t);
             }
-            double res = 0.0;
-#pragma unroll
-            for (int i = 0; i < KB; ++i) res = fmax(res, fabs(fma(-lj, z[i], tz[i])));
-            if (lane < K) {
-#pragma unroll
-                for (int i = 0; i < KB; ++i) zs[lane * kTriP + i] = z[i];
-            }
-            // cluster of this eigenvalue: [cs, ce] from the mates mask
-            int cs = jl, ce = jl;
-            while (cs > 0 && ((mates >> (cs - 1)) & 1ull)) --cs;
-            while (ce + 1 < K && ((mates >> ce) & 1ull)) ++ce;
-            const int mlo = cs < jl - 1 ? cs : (jl > 0 ? jl - 1 : 0);
-            const int mhi = ce > jl + 1 ? ce : (jl + 1 < K ? jl + 1 : K - 1);
-            double orth = 0.0;
-#pragma unroll 1
-            for (int m = mlo; m <= mhi; ++m) {
-                double dq[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int i = 0; i < KB; i += 2) {
-                    const double2 c2 = *reinterpret_cast<const double2*>(zs + m * kTriP + i);
-                    dq[i & 3] = fma(c2.x, z[i], dq[i & 3]);
-                    dq[(i + 1) & 3] = fma(c2.y, z[i + 1], dq[(i + 1) & 3]);
-                }
-                const double dot = (dq[0] + dq[1]) + (dq[2] + dq[3]);
-                orth = fmax(orth, fabs(dot - (m == jl ? 1.0 : 0.0)));
-            }
-            if (lane >= K) res = orth = 0.0;
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                res = fmax(res, __shfl_xor(res, o, kWave));
-                orth = fmax(orth, __shfl_xor(orth, o, kWave));
-            }
-            const bool bad = !(res <= 1e-10 * tn) || !(orth <= 1e-10);
-            if (lane == 0 && flags && bad) atomicOr(flags, RHOSVD_FLAG_EVD_NOCONV);
+            tz[i] = t;
         }
+        double res = 0.0;
+#pragma unroll
+        for (int i = 0; i < KB; ++i) res = fmax(res, fabs(fma(-lj, zc[i], tz[i])));
+        // cluster of this eigenvalue: [cs, ce] from the mates mask
+        int cs = jl, ce = jl;
+        while (cs > 0 && ((mates >> (cs - 1)) & 1ull)) --cs;
+        while (ce + 1 < K && ((mates >> ce) & 1ull)) ++ce;
+        const int mlo = cs < jl - 1 ? cs : (jl > 0 ? jl - 1 : 0);
+        const int mhi = ce > jl + 1 ? ce : (jl + 1 < K ? jl + 1 : K - 1);
+        double orth = 0.0;
+#pragma unroll 1
+        for (int m = mlo; m <= mhi; ++m) {
+            double dq[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int i = 0; i < KB; i += 2) {
+                const double2 c2 = *reinterpret_cast<const double2*>(zs + m * kTriP + i);
+                dq[i & 3] = fma(c2.x, zc[i], dq[i & 3]);
+                dq[(i + 1) & 3] = fma(c2.y, zc[i + 1], dq[(i + 1) & 3]);
+            }
+            const double dot = (dq[0] + dq[1]) + (dq[2] + dq[3]);
+            orth = fmax(orth, fabs(dot - (m == jl ? 1.0 : 0.0)));
+        }
+        if (lane >= K) res = orth = 0.0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            res = fmax(res, __shfl_xor(res, o, kWave));
+            orth = fmax(orth, __shfl_xor(orth, o, kWave));
+        }
+        const bool bad = !(res <= 1e-10 * tn) || !(orth <= 1e-10);
+        if (lane == 0 && flags && bad) atomicOr(flags, RHOSVD_FLAG_EVD_NOCONV);
+    } else if (wave == 0) {
         // back-transformation z <- H_0 ... H_{K-3} z (rows of hv are zero
         // at indices <= k and past K)
 #pragma unroll 1
@@ -1530,27 +1580,29 @@ __device__ __forceinline__ void evd_tri_body(const double* __restrict__ cin, int
 #pragma unroll
             for (int i = 0; i < KB; ++i) z[i] = fma(-w, hv[k * kTriP + i], z[i]);
         }
-        if (lane < K) {
-            const int col = K - 1 - lane;
+    }
+    // the eigenpairs' region overlaps zs: written once the check is done
+    __syncthreads();
+    if (wave == 0 && lane < K) {
+        const int col = K - 1 - lane;
 #pragma unroll
-            for (int i = 0; i < KB; ++i) {
-                if (i < K) {
-                    if (FACTOR)
-                        Vs[static_cast<size_t>(col) * K + i] = z[i];
-                    else
-                        v_out[static_cast<size_t>(col) * K + i] = z[i];
-                }
+        for (int i = 0; i < KB; ++i) {
+            if (i < K) {
+                if (FACTOR)
+                    Vs[static_cast<size_t>(col) * K + i] = z[i];
+                else
+                    v_out[static_cast<size_t>(col) * K + i] = z[i];
             }
-            if (FACTOR)
-                lamS[col] = lj;
-            else
-                lam_out[col] = lj;
         }
+        if (FACTOR)
+            lamS[col] = lj;
+        else
+            lam_out[col] = lj;
     }
     if constexpr (FACTOR) {
         __syncthreads();
-        factor_step<T>(K, K16, I, I16, R, use_v, Vs, lamS, q, staged ? Qst : qwork, u_out, m_out,
-                       sigma);
+        factor_step<T, QN>(K, K16, I, I16, R, use_v, Vs, lamS, q, staged ? Qst : qwork, u_out,
+                           m_out, sigma, qpre);
     }
 }
 

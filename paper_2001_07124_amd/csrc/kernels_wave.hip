@@ -612,14 +612,14 @@ __global__ __launch_bounds__(kBlock, 1) void k_wave_batch(const WaveJob* __restr
 // bounded generic ones.  C3-like modes use (13, 3) (I = 200, K = 35) and the
 // truncation (3, 2) (I = K = 35, R = 25).
 static const int kExact[][2] = {{13, 3}, {3, 2}, {13, 2}, {7, 1}};
-static const int kGeneric[][2] = {{4, 4}, {8, 4}, {16, 2}, {16, 4}};
-constexpr int kNumExact = 4, kNumGeneric = 4;
+static const int kGeneric[][2] = {{4, 4}, {8, 4}, {16, 2}, {16, 3}, {16, 4}};
+constexpr int kNumExact = 4, kNumGeneric = 5;
 // Tall modes, four waves per block (row blocks per wave, operand blocks):
 // an exact 500-row case (IB = 32, NB = 2), then bounded generic ones.
 static const int kTall[][3] = {{8, 2, 1}, {8, 2, 0}, {6, 3, 0}};
 constexpr int kNumTall = 3;
 constexpr int kTallRS = 4;
-constexpr int kTallVariant0 = 8;    // variant index of kTall[0]
+constexpr int kTallVariant0 = 9;    // variant index of kTall[0]
 
 static bool plan_wave_tall(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu,
                            WGeom* g);
@@ -739,7 +739,8 @@ static hipError_t launch_wave_ct(const WGeom& g, const StreamArgs& a, hipStream_
         case 4: return launch_wave_t<OP, CT, 4, 4, false>(g, a, s);
         case 5: return launch_wave_t<OP, CT, 8, 4, false>(g, a, s);
         case 6: return launch_wave_t<OP, CT, 16, 2, false>(g, a, s);
-        case 7: return launch_wave_t<OP, CT, 16, 4, false>(g, a, s);
+        case 7: return launch_wave_t<OP, CT, 16, 3, false>(g, a, s);
+        case 8: return launch_wave_t<OP, CT, 16, 4, false>(g, a, s);
         case kTallVariant0 + 0: return launch_wave_t<OP, CT, 8, 2, true, kTallRS>(g, a, s);
         case kTallVariant0 + 1: return launch_wave_t<OP, CT, 8, 2, false, kTallRS>(g, a, s);
         default: return launch_wave_t<OP, CT, 6, 3, false, kTallRS>(g, a, s);
@@ -766,8 +767,8 @@ hipError_t launch_wave(int op, const WGeom& g, const StreamArgs& a, hipStream_t 
 // the short-mode kernel, smallest first, for the compute types of the FP32
 // and bf16 paths (the sketch in FP32 or bf16, the other passes in FP32 or
 // split bf16).
-static const int kBatchShapes[][2] = {{4, 4}, {8, 4}, {16, 2}, {16, 4}};
-constexpr int kNumBatchShapes = 4;
+static const int kBatchShapes[][2] = {{4, 4}, {8, 4}, {16, 2}, {16, 3}, {16, 4}};
+constexpr int kNumBatchShapes = 5;
 
 int wave_batch_variant(const WGeom& g) {
     if (g.rs != 1) return -1;
@@ -791,7 +792,8 @@ static hipError_t launch_wave_batch_v(int variant, const WaveJob* jobs, int njob
         case 0: return launch_wave_batch_t<OP, CT, 4, 4>(jobs, njobs, max_units, lds, s);
         case 1: return launch_wave_batch_t<OP, CT, 8, 4>(jobs, njobs, max_units, lds, s);
         case 2: return launch_wave_batch_t<OP, CT, 16, 2>(jobs, njobs, max_units, lds, s);
-        case 3: return launch_wave_batch_t<OP, CT, 16, 4>(jobs, njobs, max_units, lds, s);
+        case 3: return launch_wave_batch_t<OP, CT, 16, 3>(jobs, njobs, max_units, lds, s);
+        case 4: return launch_wave_batch_t<OP, CT, 16, 4>(jobs, njobs, max_units, lds, s);
         default: return hipErrorInvalidValue;
     }
 }

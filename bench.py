@@ -69,10 +69,11 @@ def oracle_rel_error(workload):
     return float(np.load(path, allow_pickle=False)["rel_error"])
 
 
-def bench_batched(dev, steps, seed=1, count=512):
+def bench_batched(dev, steps, prec, seed=1, count=512):
     """512 order-3 FP32 tensors (extents 32..256, exact ranks 4..32, noise
-    1e-4; R-STHOSVD at the true ranks, p = 5, q = 1): one graph launch per
-    batch, against the same tensors decomposed by 512 sequential calls."""
+    1e-4; R-STHOSVD at the true ranks, p = 5, q = 1) on the given precision
+    path: one graph launch per batch, against the same tensors decomposed by
+    512 sequential calls."""
     import torch
     from paper_2001_07124_amd import api
     from paper_2001_07124_amd.inputs import batch_specs, batch_tensors
@@ -83,7 +84,7 @@ def bench_batched(dev, steps, seed=1, count=512):
     torch.cuda.synchronize()
     nbytes = float(sum(x.nbytes for x in xs))
     log(f"[bench] batch: {count} tensors, {nbytes / 1e9:.2f} GB, generated in {time.perf_counter() - t0:.1f}s")
-    items = [(xd, r, 5, 1, i, "f32") for i, (xd, (d, r)) in enumerate(zip(xds, specs))]
+    items = [(xd, r, 5, 1, i, prec) for i, (xd, (d, r)) in enumerate(zip(xds, specs))]
     s = torch.cuda.Stream(dev)
     t0 = time.perf_counter()
     b = api.Batch(items, autotune=True, stream=s)
@@ -102,7 +103,7 @@ def bench_batched(dev, steps, seed=1, count=512):
     ms = e0.elapsed_time(e1) / steps
     errs = [r.rel_error for r in b.results]
     # the same work as independent single decompositions, one after another
-    decs = [api.Decomposer(d, r, p=5, q=1, seed=i, dtype=torch.float32, precision="f32", device=dev)
+    decs = [api.Decomposer(d, r, p=5, q=1, seed=i, dtype=torch.float32, precision=prec, device=dev)
             for i, (d, r) in enumerate(specs)]
     for dec, xd in zip(decs, xds):
         dec.run(xd, stream=s)
@@ -113,13 +114,17 @@ def bench_batched(dev, steps, seed=1, count=512):
     e1.record(s)
     s.synchronize()
     ms_seq = e0.elapsed_time(e1)
-    log(f"[bench] batch: {ms:.3f} ms per batch ({b.launches} launches, one graph), "
+    log(f"[bench] batch ({prec}): {ms:.3f} ms per batch ({b.launches} launches, one graph), "
         f"sequential {ms_seq:.3f} ms")
-    out = {"workload": f"batch_{count}_order3_32to256_r4to32", "tensors": count,
+    # the same per-item algorithmic bytes as the headline's path roofline
+    alg = sum(sum(m["bytes"] for m in algorithmic_counts(d, r, 5, 1, 4)) for d, r in specs)
+    out = {"workload": f"batch_{count}_order3_32to256_r4to32", "precision": prec, "tensors": count,
            "tensor_GB": round(nbytes / 1e9, 3), "ms_per_batch": round(ms, 3),
            "value": round(nbytes / (ms * 1e-3) / 1e9, 2), "unit": "GB/s",
            "launches_per_batch": b.launches, "graph": True,
            "sequential_ms": round(ms_seq, 3), "speedup_vs_sequential": round(ms_seq / ms, 2),
+           "algorithmic_bytes": alg, "hbm_roofline_ms": round(alg / (HBM_PEAK_GBPS * 1e9) * 1e3, 4),
+           "hbm_roofline_frac": round(alg / (HBM_PEAK_GBPS * 1e9) * 1e3 / ms, 4),
            "rel_error_median": float(np.median(errs)), "rel_error_max": float(np.max(errs)),
            "plan_and_tune_s": round(t_plan, 2)}
     b.close()
@@ -413,7 +418,7 @@ def main():
     }
     if not args.no_batch:
         log("[bench] batched workload")
-        out["batched"] = bench_batched(dev, max(3, args.steps // 2))
+        out["batched"] = bench_batched(dev, max(3, args.steps // 2), prec if elem == 4 else "f32")
     if not args.no_serve:
         log("[bench] serving workload")
         out["serving"] = bench_serving(dev)

@@ -280,7 +280,7 @@ int32_t rhosvd_decompose_adaptive(rhosvd_ctx* ctx, const rhosvd_tensor* x,
  * RHOSVD_OPT_EXPLICIT_ERROR; one order N and one dtype for the batch; every
  * mode I_n <= 256 and K_n <= RHOSVD_MAX_SKETCH.  Dims, ranks, p, q, seed and
  * precision may differ per item.  A pass of an FP32 item runs on the wave
- * kernels (one 16-column block per wave, up to 64 workgroups per item; the
+ * kernels (one 16-column block per wave, up to 16 workgroups per item; the
  * items of one compute type and shape class share a launch) when its shape
  * fits them, else on the workgroup-tiled kernels, as do FP64 items.  An
  * item's result depends

@@ -4,7 +4,9 @@ replayed from a HIP graph) against the FP64 oracle, item by item (GPU only).
 * every item of a seeded batch of uneven order-3 shapes matches the oracle's
   R-STHOSVD as a single decomposition does (FP32: E 1e-5, sigma 1e-5,
   projectors 1e-4; FP64: E 1e-10, sigma 1e-9, projectors 1e-8);
-* an item computes the same bits alone (a batch of one) as in the mix;
+* bf16-path items against the oracle within the lone bf16 path's bounds;
+* an item computes the same bits alone (a batch of one) as in the mix (FP32
+  and bf16 paths);
 * graph replays, with other device work and synchronisations between them,
   reproduce the directly enqueued run bit for bit;
 * a sample of the 512-tensor workload (extents 32..256, ranks 4..32, p = 5,
@@ -61,10 +63,33 @@ def test_batch_items_match_oracle(dtype):
         _check(b.results[i], x, ranks, 5, 1, 100 + i, TOL[dtype])
 
 
-def test_batch_alone_equals_in_the_mix():
+def test_batch_bf16_items_match_oracle():
+    """The bf16 path in the batch (bf16 sketch, split-bf16 power step,
+    projection and truncation on the wave kernels): the bounds of the lone
+    bf16 decompositions (E 1e-4, sigma 1e-3, projectors 1e-2 with q = 1)."""
+    specs = batch_specs(count=20, seed=17, dim_range=(24, 200), rank_range=(3, 12))
+    xs = batch_tensors(specs, seed=17, noise=1e-2, dtype=np.float32)
+    b = api.Batch(_items(specs, xs, prec="bf16"))
+    b.run(use_graph=False)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i, ((dims, ranks), x) in enumerate(zip(specs, xs)):
+        ref = o_rst(x.astype(np.float64), ranks, 5, 1, seed=100 + i)
+        res = b.results[i]
+        worst = max(worst, abs(res.rel_error - ref.rel_error))
+        assert abs(res.rel_error - ref.rel_error) <= 1e-4 + 1e-7 / ref.rel_error, (i, res.rel_error, ref.rel_error)
+        for n in range(3):
+            np.testing.assert_allclose(res.sigma(n), ref.sigma[n], rtol=1e-3, atol=1e-3 * ref.sigma[n][0])
+            u = res.factors[n].cpu().numpy().astype(np.float64)
+            assert np.linalg.norm(u @ u.T - ref.factors[n] @ ref.factors[n].T, 2) <= 1e-2
+    print(f"[batch] bf16: {len(specs)} items, {b.launches} launches, worst |dE| {worst:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("prec", [None, "bf16"])
+def test_batch_alone_equals_in_the_mix(prec):
     specs = batch_specs(count=16, seed=8, dim_range=(20, 80), rank_range=(3, 9))
     xs = batch_tensors(specs, seed=8, noise=1e-2, dtype=np.float32)
-    items = _items(specs, xs)
+    items = _items(specs, xs, prec=prec)
     mix = api.Batch(items)
     mix.run(use_graph=False)
     torch.cuda.synchronize()

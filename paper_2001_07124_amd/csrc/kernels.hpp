@@ -168,6 +168,21 @@ struct ColGeom {
 bool plan_col(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu, ColGeom* g);
 hipError_t launch_col(int op, const ColGeom& g, const StreamArgs& a, hipStream_t s);
 
+// The column kernels over a batch: job y on workgroups 0 .. units - 1 of
+// grid x.  plan_col_batch plans a contiguous unfolding (L = 1) on one of the
+// batched shapes (g->variant indexes them); the bf16 sketch and the split
+// power step / mode-n product only.  flag: the sketch's sum of squares, or
+// the mode-n product's Gram.
+struct ColJob {
+    ColGeom g;
+    StreamArgs a;
+    int units;
+    int pad_;
+};
+bool plan_col_batch(int op, int ct, int64_t I, int64_t T, int K, ColGeom* g);
+hipError_t launch_col_batch(int op, int shape, bool flag, const ColJob* jobs, int njobs, int max_units,
+                            size_t lds, hipStream_t s);
+
 // Truncation in the rotated layout (kernels_trunc.hip): out[r J + j] =
 // sum_k M(k, r) B(k, j) for B K x J and M K x R column-major, K <= 64 (32
 // for FP64), in the tensor's precision with one column per lane.

@@ -222,7 +222,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const float* src, i
 // enters Z = S^T M split (hi*lo + lo*hi + hi*hi) instead of rounded (hi*lo +
 // hi*hi); in the sketch (FP8), e4m3 inputs instead of bf16.
 template <int OP, int NCH, int NB, bool FLAG, bool VAR>
-__global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a) {
+__device__ __forceinline__ void col_body(const ColGeom& g, const StreamArgs& a, int bidx, int nwg) {
     constexpr bool SPLIT = VAR && OP != OP_SKETCH;
     constexpr bool FP8 = VAR && OP == OP_SKETCH;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -294,8 +294,8 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
     double ss = 0.0;
 
     const float* __restrict__ src = static_cast<const float*>(a.src);
-    const int64_t wid = static_cast<int64_t>(blockIdx.x) * kColWaves + wave;
-    const int64_t nw = static_cast<int64_t>(gridDim.x) * kColWaves;
+    const int64_t wid = static_cast<int64_t>(bidx) * kColWaves + wave;
+    const int64_t nw = static_cast<int64_t>(nwg) * kColWaves;
     const bool jal = (J & 3) == 0;
     const int voff = (c16 * I + 8 * grp) * 4;       // bytes: column c16 of half 0, row 8 grp
     const int half1 = 16 * I * 4;                   // bytes to column half 1
@@ -596,7 +596,7 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
     // ---- cross-wave reduction (fixed order) and the per-workgroup partials
     __syncthreads();
     float* red = reinterpret_cast<float*>(smem);
-    const size_t gidx = blockIdx.x;
+    const size_t gidx = static_cast<size_t>(bidx);
     const int I_pad = 32 * NCH, K_pad = 16 * NB;
     if (OP != OP_TTM && g.red3) {
         // waves 1..3 store their accumulators (16-byte pieces) in regions
@@ -679,6 +679,20 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
     }
 }
 
+template <int OP, int NCH, int NB, bool FLAG, bool VAR>
+__global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a) {
+    col_body<OP, NCH, NB, FLAG, VAR>(g, a, blockIdx.x, gridDim.x);
+}
+
+// Many problems: job blockIdx.y on workgroups 0 .. units - 1 of grid x (the
+// job read in place: uniform, scalar loads).
+template <int OP, int NCH, int NB, bool FLAG, bool VAR>
+__global__ __launch_bounds__(kColThreads, 1) void k_col_batch(const ColJob* __restrict__ jobs) {
+    const ColJob& j = jobs[blockIdx.y];
+    if (static_cast<int>(blockIdx.x) >= j.units) return;
+    col_body<OP, NCH, NB, FLAG, VAR>(j.g, j.a, blockIdx.x, j.units);
+}
+
 // ---------------------------------------------------------------------------
 // Planning and dispatch: (32-row chunks, 16-column operand blocks) shapes,
 // exact ones first; a shape runs on the smallest instantiation that covers it.
@@ -686,7 +700,13 @@ __global__ __launch_bounds__(kColThreads, 1) void k_col(ColGeom g, StreamArgs a)
 static const int kColShapes[][2] = {{7, 3}, {2, 2}, {1, 2}, {2, 4}, {4, 2}, {4, 4}, {8, 2}, {8, 4}};
 constexpr int kNumColShapes = 8;
 
-bool plan_col(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu, ColGeom* g) {
+// The batched instantiations: generic shapes only (a shape runs every
+// geometry it covers).
+static const int kColBatchShapes[][2] = {{2, 2}, {4, 2}, {8, 2}, {4, 4}, {8, 4}};
+constexpr int kNumColBatchShapes = 5;
+
+static bool plan_col_in(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu,
+                        const int (*shapes)[2], int nshapes, ColGeom* g) {
     if (L != 1 || I < 1 || I > 256 || T < 1 || K < 1 || K > 64) return false;
     if (op == OP_SKETCH ? (ct != CT_BF16 && ct != CT_FP8) : (ct != CT_BF16X2 && ct != CT_BF16X3))
         return false;
@@ -694,15 +714,15 @@ bool plan_col(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu
     g->fp8 = (op == OP_SKETCH && ct == CT_FP8) ? 1 : 0;
     const int nch = static_cast<int>((I + 31) / 32), nb = (K + 15) / 16;
     int var = -1, best = 1 << 30;
-    for (int v = 0; v < kNumColShapes; ++v) {
-        const int c = kColShapes[v][0], b = kColShapes[v][1];
+    for (int v = 0; v < nshapes; ++v) {
+        const int c = shapes[v][0], b = shapes[v][1];
         if (c >= nch && b >= nb && c * b < best) {
             best = c * b;
             var = v;
         }
     }
     if (var < 0) return false;
-    const int NCH = kColShapes[var][0], NB = kColShapes[var][1];
+    const int NCH = shapes[var][0], NB = shapes[var][1];
     g->I = I;
     g->J = T;
     g->K = K;
@@ -739,6 +759,17 @@ bool plan_col(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu
     g->I_pad = 32 * NCH;
     g->K_pad = 16 * NB;
     return true;
+}
+
+bool plan_col(int op, int ct, int64_t L, int64_t I, int64_t T, int K, int num_cu, ColGeom* g) {
+    return plan_col_in(op, ct, L, I, T, K, num_cu, kColShapes, kNumColShapes, g);
+}
+
+bool plan_col_batch(int op, int ct, int64_t I, int64_t T, int K, ColGeom* g) {
+    // the sketch on e4m3 and the split-free (BF16X2) passes have no batched
+    // instantiation
+    if (op == OP_SKETCH ? ct != CT_BF16 : ct != CT_BF16X3) return false;
+    return plan_col_in(op, ct, 1, I, T, K, 256, kColBatchShapes, kNumColBatchShapes, g);
 }
 
 template <int OP, int NCH, int NB, bool VAR>
@@ -781,6 +812,41 @@ hipError_t launch_col(int op, const ColGeom& g, const StreamArgs& a, hipStream_t
     if (op == OP_SKETCH) return launch_col_op<OP_SKETCH>(g, a, s);
     if (op == OP_POWER) return launch_col_op<OP_POWER>(g, a, s);
     return launch_col_op<OP_TTM>(g, a, s);
+}
+
+template <int OP, int NCH, int NB, bool FLAG, bool VAR>
+static hipError_t launch_col_batch_t(const ColJob* jobs, int njobs, int max_units, size_t lds,
+                                     hipStream_t s) {
+    hipLaunchKernelGGL((k_col_batch<OP, NCH, NB, FLAG, VAR>), dim3(max_units, njobs), dim3(kColThreads),
+                       lds, s, jobs);
+    return hipGetLastError();
+}
+
+// (op, flag) of the batched kinds: sketch with or without the sum of squares
+// (bf16), the power step (split), the mode-n product with or without its
+// Gram (split)
+template <int OP, bool FLAG, bool VAR>
+static hipError_t launch_col_batch_k(int shape, const ColJob* jobs, int njobs, int max_units,
+                                     size_t lds, hipStream_t s) {
+    switch (shape) {
+        case 0: return launch_col_batch_t<OP, 2, 2, FLAG, VAR>(jobs, njobs, max_units, lds, s);
+        case 1: return launch_col_batch_t<OP, 4, 2, FLAG, VAR>(jobs, njobs, max_units, lds, s);
+        case 2: return launch_col_batch_t<OP, 8, 2, FLAG, VAR>(jobs, njobs, max_units, lds, s);
+        case 3: return launch_col_batch_t<OP, 4, 4, FLAG, VAR>(jobs, njobs, max_units, lds, s);
+        case 4: return launch_col_batch_t<OP, 8, 4, FLAG, VAR>(jobs, njobs, max_units, lds, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_col_batch(int op, int shape, bool flag, const ColJob* jobs, int njobs, int max_units,
+                            size_t lds, hipStream_t s) {
+    if (njobs < 1 || max_units < 1 || lds + kStaticLdsMargin > kLdsLimit) return hipErrorInvalidValue;
+    if (op == OP_SKETCH)
+        return flag ? launch_col_batch_k<OP_SKETCH, true, false>(shape, jobs, njobs, max_units, lds, s)
+                    : launch_col_batch_k<OP_SKETCH, false, false>(shape, jobs, njobs, max_units, lds, s);
+    if (op == OP_POWER) return launch_col_batch_k<OP_POWER, false, true>(shape, jobs, njobs, max_units, lds, s);
+    return flag ? launch_col_batch_k<OP_TTM, true, true>(shape, jobs, njobs, max_units, lds, s)
+                : launch_col_batch_k<OP_TTM, false, true>(shape, jobs, njobs, max_units, lds, s);
 }
 
 }  // namespace rh

@@ -1514,11 +1514,12 @@ constexpr int kBatchUnits = 64;          // most workgroups per item per pass
 // against 26.8 / 30.6 with 64 and 29.1 (FP32) with 8
 constexpr int kBatchWaveUnits = 16;
 
-enum BatchKind { BK_STREAM, BK_REDUCE, BK_QR, BK_EVD, BK_INIT, BK_NORMX, BK_FINISH, BK_WAVE };
+enum BatchKind { BK_STREAM, BK_REDUCE, BK_QR, BK_EVD, BK_INIT, BK_NORMX, BK_FINISH, BK_WAVE, BK_COL };
 
 struct BatchLaunch {
     int kind = 0, op = 0, njobs = 0, sel = 0;
-    int ct = 0, var = 0;              // BK_WAVE: compute type and shape of the instantiation
+    int ct = 0, var = 0;              // BK_WAVE: compute type and shape of the instantiation;
+                                      // BK_COL: flag (Gram / sum of squares) and shape
     size_t lds = 0, off = 0;
 };
 
@@ -1533,6 +1534,21 @@ void batch_pass(Pass* p, int op, bool dbl, int ct, int elem, int64_t I, int64_t 
     p->I = I;
     p->K = K;
     if (op == rh::OP_SKETCH && ct == rh::CT_FP8) ct = rh::CT_BF16;
+    // bf16-path passes of modes up to 256 rows on the column kernels (32
+    // columns per wave), as a single decomposition runs them
+    rh::ColGeom cg;
+    if (!dbl && rh::plan_col_batch(op, ct, I, T, K, &cg)) {
+        int64_t units = (cg.nblocks + 3) / 4;
+        if (units > kBatchWaveUnits) units = kBatchWaveUnits;
+        if (units < 1) units = 1;
+        cg.grid = static_cast<int>(units);
+        p->cg = cg;
+        p->kind = PASS_COL;
+        p->grid = cg.grid;
+        p->I_pad = cg.I_pad;
+        p->K_pad = cg.K_pad;
+        return;
+    }
     rh::WGeom wg;
     if (!dbl && rh::wave_batch_ct(op, ct) && rh::plan_wave(op, ct, 1, I, T, K, 256, &wg) &&
         rh::wave_batch_variant(wg) >= 0) {
@@ -1639,8 +1655,17 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
     auto add_pass = [&](int op, const std::vector<PassJob>& jobs) {
         std::vector<rh::StreamJob> tiled;
         std::map<std::pair<int, int>, std::vector<rh::WaveJob>> wave;
+        std::map<std::pair<int, int>, std::vector<rh::ColJob>> col;
         for (const PassJob& pj : jobs) {
-            if (pj.p->kind == PASS_WAVE) {
+            if (pj.p->kind == PASS_COL) {
+                rh::ColJob c{};
+                c.g = pj.p->cg;
+                c.a = pj.a;
+                c.units = pj.p->grid;
+                const int flag = (op == rh::OP_SKETCH) ? (pj.a.part_ss != nullptr)
+                                                       : (op == rh::OP_TTM && pj.a.part_g != nullptr);
+                col[{flag, pj.p->cg.variant}].push_back(c);
+            } else if (pj.p->kind == PASS_WAVE) {
                 rh::WaveJob w{};
                 w.g = pj.p->wg;
                 w.a = pj.a;
@@ -1657,6 +1682,20 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
             }
         }
         add_stream(op, tiled);
+        for (auto& kv : col) {
+            BatchLaunch L;
+            L.kind = BK_COL;
+            L.op = op;
+            L.ct = kv.first.first;
+            L.var = kv.first.second;
+            L.njobs = static_cast<int>(kv.second.size());
+            for (auto& c : kv.second) {
+                L.sel = std::max(L.sel, c.units);
+                L.lds = std::max(L.lds, c.g.lds_bytes);
+            }
+            L.off = tw->put(kv.second);
+            B->prog.push_back(L);
+        }
         for (auto& kv : wave) {
             BatchLaunch L;
             L.kind = BK_WAVE;
@@ -1887,6 +1926,10 @@ hipError_t run_program(const rhosvd_batch* B, hipStream_t s) {
                 e = rh::launch_wave_batch(L.op, L.ct, L.var, static_cast<const rh::WaveJob*>(t),
                                           L.njobs, L.sel, L.lds, s);
                 break;
+            case BK_COL:
+                e = rh::launch_col_batch(L.op, L.var, L.ct != 0, static_cast<const rh::ColJob*>(t),
+                                         L.njobs, L.sel, L.lds, s);
+                break;
             default:
                 e = hipErrorInvalidValue;
         }
@@ -1898,9 +1941,10 @@ hipError_t run_program(const rhosvd_batch* B, hipStream_t s) {
 // Upper bound of the tables: every launch holds at most one job per item.
 size_t tables_bound(int n, int N, int maxq) {
     const size_t per_item_jobs = static_cast<size_t>(N) * (7 + 3 * maxq) + 3;
-    // a pass may split into one tiled and four wave launches per compute type
-    const size_t job = std::max(sizeof(rh::StreamJob), sizeof(rh::WaveJob));
-    return (per_item_jobs * n * job + 256 * (N * (12 + 8 * maxq) * 9 + 8) + 4095) &
+    // a pass may split into one tiled launch, five wave launches per compute
+    // type and ten column-kernel launches (shape x flag)
+    const size_t job = std::max({sizeof(rh::StreamJob), sizeof(rh::WaveJob), sizeof(rh::ColJob)});
+    return (per_item_jobs * n * job + 256 * (N * (12 + 8 * maxq) * 20 + 8) + 4095) &
            ~static_cast<size_t>(4095);
 }
 

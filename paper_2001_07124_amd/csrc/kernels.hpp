@@ -197,6 +197,22 @@ struct TruncGeom {
 bool plan_trunc(bool dbl, int64_t I, int64_t T, int R, int num_cu, bool any_size, TruncGeom* g);
 hipError_t launch_trunc(bool dbl, const TruncGeom& g, const void* B, const void* M, void* out,
                         hipStream_t s);
+// Many truncations in one launch: job y on workgroups 0 .. units - 1 of
+// grid x; every job of a launch has (R + 15) / 16 = rt and trunc_kqm(K) = kqm;
+// lds: the largest trunc lds_bytes among them.
+struct TruncJob {
+    const void* b;
+    const void* m;
+    void* out;
+    int K, R;
+    int64_t J;
+    int units;
+    int pad_;
+};
+int trunc_kqm(int K);
+size_t trunc_lds_bytes(int K, bool dbl);
+hipError_t launch_trunc_batch(bool dbl, int rt, int kqm, const TruncJob* jobs, int njobs, int max_units,
+                              size_t lds, hipStream_t s);
 
 // Fixed-order reductions of per-workgroup partials.
 hipError_t launch_reduce_y(bool dbl, const void* part, int G, int I, int K, int I_pad, int K_pad,

@@ -32,8 +32,9 @@ __host__ __device__ inline size_t trunc_lds_elems(int K) { return 4 * trunc_slic
 // RT row tiles of 16 output rows (R <= 16 RT), KQM >= ceil(K / 4) steps;
 // a chunk is 64 K <= 256 KQM elements, NL 16-byte pieces per lane
 template <typename T, int RT, int KQM>
-__global__ __launch_bounds__(kBlock) void k_trunc_rot(const T* __restrict__ B, const T* __restrict__ M,
-                                                      T* __restrict__ out, int K, int R, int64_t J) {
+__device__ __forceinline__ void trunc_body(const T* __restrict__ B, const T* __restrict__ M,
+                                           T* __restrict__ out, int K, int R, int64_t J, int bidx,
+                                           int nwg) {
     typedef __attribute__((ext_vector_type(4))) float vf4;
     typedef typename Mma<T>::acc_t acc_t;
     extern __shared__ __align__(16) unsigned char tsm[];
@@ -61,8 +62,8 @@ __global__ __launch_bounds__(kBlock) void k_trunc_rot(const T* __restrict__ B, c
     constexpr int NL = 4 * KQM / EPV;
     const int64_t nchunks = (J + 63) / 64;
     const int64_t total = J * K;                         // elements of B
-    const int64_t wstride = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
-    int64_t c = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + wave;
+    const int64_t wstride = static_cast<int64_t>(nwg) * (kBlock / kWave);
+    int64_t c = static_cast<int64_t>(bidx) * (kBlock / kWave) + wave;
     const int pieces = 64 * K / EPV;                     // per chunk (64 K is a multiple of EPV)
     T buf[NL * EPV];
     auto load = [&](int64_t cc) {
@@ -149,6 +150,21 @@ __global__ __launch_bounds__(kBlock) void k_trunc_rot(const T* __restrict__ B, c
     }
 }
 
+template <typename T, int RT, int KQM>
+__global__ __launch_bounds__(kBlock) void k_trunc_rot(const T* __restrict__ B, const T* __restrict__ M,
+                                                      T* __restrict__ out, int K, int R, int64_t J) {
+    trunc_body<T, RT, KQM>(B, M, out, K, R, J, blockIdx.x, gridDim.x);
+}
+
+// Many truncations: job blockIdx.y on workgroups 0 .. units - 1 of grid x.
+template <typename T, int RT, int KQM>
+__global__ __launch_bounds__(kBlock) void k_trunc_batch(const TruncJob* __restrict__ jobs) {
+    const TruncJob& j = jobs[blockIdx.y];
+    if (static_cast<int>(blockIdx.x) >= j.units) return;
+    trunc_body<T, RT, KQM>(static_cast<const T*>(j.b), static_cast<const T*>(j.m), static_cast<T*>(j.out),
+                           j.K, j.R, j.J, blockIdx.x, j.units);
+}
+
 bool plan_trunc(bool dbl, int64_t I, int64_t T, int R, int num_cu, bool any_size, TruncGeom* g) {
     // I = K rows of B: FP32 up to K = 64 (four row tiles), FP64 up to K = 32
     if (I < 1 || I > (dbl ? 32 : 64) || R < 1 || R > I || T < 1) return false;
@@ -204,6 +220,46 @@ hipError_t launch_trunc(bool dbl, const TruncGeom& g, const void* B, const void*
     if (kq <= 8) return launch_trunc_q<float, 8>(g, B, M, out, s);
     if (kq <= 12) return launch_trunc_q<float, 12>(g, B, M, out, s);
     if (kq <= 16) return launch_trunc_q<float, 16>(g, B, M, out, s);
+    return hipErrorInvalidValue;
+}
+
+// step bound of the batched instantiations: the smallest of 4, 8, 12, 16
+// with 4 KQM >= K
+size_t trunc_lds_bytes(int K, bool dbl) { return trunc_lds_elems(K) * (dbl ? 8 : 4); }
+
+int trunc_kqm(int K) {
+    const int kq = (K + 3) / 4;
+    return kq <= 4 ? 4 : kq <= 8 ? 8 : kq <= 12 ? 12 : 16;
+}
+
+template <typename T, int RT, int KQM>
+static void launch_trunc_batch_k(const TruncJob* jobs, int njobs, int max_units, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_trunc_batch<T, RT, KQM>), dim3(max_units, njobs), dim3(kBlock), lds, s, jobs);
+}
+
+template <typename T, int KQM>
+static hipError_t launch_trunc_batch_q(int rt, const TruncJob* jobs, int njobs, int max_units, size_t lds,
+                                       hipStream_t s) {
+    if (rt < 1 || 16 * rt > 4 * KQM) return hipErrorInvalidValue;
+    if (rt == 1) launch_trunc_batch_k<T, 1, KQM>(jobs, njobs, max_units, lds, s);
+    if constexpr (KQM >= 8) if (rt == 2) launch_trunc_batch_k<T, 2, KQM>(jobs, njobs, max_units, lds, s);
+    if constexpr (KQM >= 12) if (rt == 3) launch_trunc_batch_k<T, 3, KQM>(jobs, njobs, max_units, lds, s);
+    if constexpr (KQM >= 16) if (rt == 4) launch_trunc_batch_k<T, 4, KQM>(jobs, njobs, max_units, lds, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_trunc_batch(bool dbl, int rt, int kqm, const TruncJob* jobs, int njobs, int max_units,
+                              size_t lds, hipStream_t s) {
+    if (njobs < 1 || max_units < 1 || lds + kStaticLdsMargin > kLdsLimit) return hipErrorInvalidValue;
+    if (dbl) {
+        if (kqm == 4) return launch_trunc_batch_q<double, 4>(rt, jobs, njobs, max_units, lds, s);
+        if (kqm == 8) return launch_trunc_batch_q<double, 8>(rt, jobs, njobs, max_units, lds, s);
+        return hipErrorInvalidValue;
+    }
+    if (kqm == 4) return launch_trunc_batch_q<float, 4>(rt, jobs, njobs, max_units, lds, s);
+    if (kqm == 8) return launch_trunc_batch_q<float, 8>(rt, jobs, njobs, max_units, lds, s);
+    if (kqm == 12) return launch_trunc_batch_q<float, 12>(rt, jobs, njobs, max_units, lds, s);
+    if (kqm == 16) return launch_trunc_batch_q<float, 16>(rt, jobs, njobs, max_units, lds, s);
     return hipErrorInvalidValue;
 }
 

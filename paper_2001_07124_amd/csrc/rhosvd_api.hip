@@ -69,7 +69,7 @@ constexpr double kAllModeNormalsPerElement = 4.0;
 //   COL    contiguous unfolding (L = 1), bf16 matrix cores (kernels_col.hip)
 //   WAVE   any view, FP32 data, wave-private blocks (kernels_wave.hip)
 //   TILED  anything, FP32 or FP64 data, workgroup tiles (kernels.hip)
-enum PassKind { PASS_TILED = 0, PASS_WAVE = 1, PASS_COL = 2 };
+enum PassKind { PASS_TILED = 0, PASS_WAVE = 1, PASS_COL = 2, PASS_TRUNC = 3 };
 
 struct Pass {
     int op = 0;
@@ -78,6 +78,7 @@ struct Pass {
     rh::StreamGeom sg{};
     rh::WGeom wg{};
     rh::ColGeom cg{};
+    rh::TruncGeom tg{};               // PASS_TRUNC (batch only): the rotated truncation kernel
     int grid = 0, I_pad = 0, K_pad = 0, K = 0;
     int64_t I = 0;
 };
@@ -1514,12 +1515,13 @@ constexpr int kBatchUnits = 64;          // most workgroups per item per pass
 // against 26.8 / 30.6 with 64 and 29.1 (FP32) with 8
 constexpr int kBatchWaveUnits = 16;
 
-enum BatchKind { BK_STREAM, BK_REDUCE, BK_QR, BK_EVD, BK_INIT, BK_NORMX, BK_FINISH, BK_WAVE, BK_COL };
+enum BatchKind { BK_STREAM, BK_REDUCE, BK_QR, BK_EVD, BK_INIT, BK_NORMX, BK_FINISH, BK_WAVE, BK_COL, BK_TRUNC };
 
 struct BatchLaunch {
     int kind = 0, op = 0, njobs = 0, sel = 0;
     int ct = 0, var = 0;              // BK_WAVE: compute type and shape of the instantiation;
-                                      // BK_COL: flag (Gram / sum of squares) and shape
+                                      // BK_COL: flag (Gram / sum of squares) and shape;
+                                      // BK_TRUNC: row tiles and step bound
     size_t lds = 0, off = 0;
 };
 
@@ -1584,7 +1586,25 @@ void batch_geometry(Plan* pl, int cmax, int tpu) {
         batch_pass(&st.gs, rh::OP_SKETCH, pr.dbl, pr.ct_sketch, elem, st.I, st.T, st.K, cmax, tpu);
         batch_pass(&st.gp, rh::OP_POWER, pr.dbl, pr.ct_power, elem, st.I, st.T, st.K, cmax, tpu);
         batch_pass(&st.gt, rh::OP_TTM, pr.dbl, pr.ct_ttm, elem, st.I, st.T, st.K, cmax, tpu);
-        batch_pass(&st.gtr, rh::OP_TTM, pr.dbl, pr.ct_trunc, elem, st.K, st.T, st.R, cmax, tpu);
+        // the truncation (rotated: the batch requires it) on its own kernel
+        rh::TruncGeom tg;
+        if (rh::plan_trunc(pr.dbl, st.K, st.T, st.R, 256, true, &tg)) {
+            Pass* p = &st.gtr;
+            p->op = rh::OP_TTM;
+            p->dbl = pr.dbl;
+            p->I = st.K;
+            p->K = st.R;
+            int64_t units = ((st.T + 63) / 64 + 3) / 4;
+            if (units > kBatchWaveUnits) units = kBatchWaveUnits;
+            if (units < 1) units = 1;
+            tg.grid = static_cast<int>(units);
+            p->tg = tg;
+            p->kind = PASS_TRUNC;
+            p->grid = tg.grid;
+            p->I_pad = p->K_pad = 0;
+        } else {
+            batch_pass(&st.gtr, rh::OP_TTM, pr.dbl, pr.ct_trunc, elem, st.K, st.T, st.R, cmax, tpu);
+        }
     }
 }
 
@@ -1656,8 +1676,19 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
         std::vector<rh::StreamJob> tiled;
         std::map<std::pair<int, int>, std::vector<rh::WaveJob>> wave;
         std::map<std::pair<int, int>, std::vector<rh::ColJob>> col;
+        std::map<std::pair<int, int>, std::vector<rh::TruncJob>> trunc;
         for (const PassJob& pj : jobs) {
-            if (pj.p->kind == PASS_COL) {
+            if (pj.p->kind == PASS_TRUNC) {
+                rh::TruncJob t{};
+                t.b = pj.a.src;
+                t.m = pj.a.mat;
+                t.out = pj.a.out;
+                t.K = pj.p->tg.K;
+                t.R = pj.p->tg.R;
+                t.J = pj.p->tg.J;
+                t.units = pj.p->grid;
+                trunc[{pj.p->tg.rb, rh::trunc_kqm(t.K)}].push_back(t);
+            } else if (pj.p->kind == PASS_COL) {
                 rh::ColJob c{};
                 c.g = pj.p->cg;
                 c.a = pj.a;
@@ -1682,6 +1713,21 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
             }
         }
         add_stream(op, tiled);
+        for (auto& kv : trunc) {
+            BatchLaunch L;
+            L.kind = BK_TRUNC;
+            L.op = op;
+            L.ct = kv.first.first;
+            L.var = kv.first.second;
+            L.njobs = static_cast<int>(kv.second.size());
+            for (auto& t : kv.second) {
+                L.sel = std::max(L.sel, t.units);
+                const size_t lds = rh::trunc_lds_bytes(t.K, B->dbl);
+                L.lds = std::max(L.lds, lds);
+            }
+            L.off = tw->put(kv.second);
+            B->prog.push_back(L);
+        }
         for (auto& kv : col) {
             BatchLaunch L;
             L.kind = BK_COL;
@@ -1929,6 +1975,10 @@ hipError_t run_program(const rhosvd_batch* B, hipStream_t s) {
             case BK_COL:
                 e = rh::launch_col_batch(L.op, L.var, L.ct != 0, static_cast<const rh::ColJob*>(t),
                                          L.njobs, L.sel, L.lds, s);
+                break;
+            case BK_TRUNC:
+                e = rh::launch_trunc_batch(B->dbl, L.ct, L.var, static_cast<const rh::TruncJob*>(t),
+                                           L.njobs, L.sel, L.lds, s);
                 break;
             default:
                 e = hipErrorInvalidValue;

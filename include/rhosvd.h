@@ -279,13 +279,17 @@ int32_t rhosvd_decompose_adaptive(rhosvd_ctx* ctx, const rhosvd_tensor* x,
  * RHOSVD_R_STHOSVD in the natural mode order, without
  * RHOSVD_OPT_EXPLICIT_ERROR; one order N and one dtype for the batch; every
  * mode I_n <= 256 and K_n <= RHOSVD_MAX_SKETCH.  Dims, ranks, p, q, seed and
- * precision may differ per item.  A pass of an FP32 item runs on the wave
- * kernels (one 16-column block per wave, up to 16 workgroups per item; the
- * items of one compute type and shape class share a launch) when its shape
- * fits them, else on the workgroup-tiled kernels, as do FP64 items.  An
- * item's result depends
- * only on its own problem and on the context's tuned tile parameters, so it
- * is bitwise the same alone (a batch of one) and in any mix.  The reports
+ * precision may differ per item.  Up to 16 workgroups per item and pass;
+ * the items of one kernel instantiation share a launch.  The sketch, power
+ * step and projection of a bf16-path item (RHOSVD_PREC_BF16, and
+ * RHOSVD_PREC_FP8E4M3 with a bf16 sketch) run on the column kernels (32
+ * columns per wave), of an RHOSVD_PREC_F32 item on the wave kernels (16
+ * columns per wave) when its shape fits them, else, as do FP64 items, on
+ * the workgroup-tiled kernels; every truncation runs on the rotated
+ * truncation kernel (K_n <= 64, 32 for FP64) or else with the passes.  An
+ * item's result depends only on its own problem and on the context's tuned
+ * tile parameters, so it is bitwise the same alone (a batch of one) and in
+ * any mix.  The reports
  * hold the identity-based E of Section 5.1 only (no explicit residual pass):
  * with FP32 data it cannot resolve errors below about 1e-3.
  *

@@ -63,13 +63,16 @@ def test_batch_items_match_oracle(dtype):
         _check(b.results[i], x, ranks, 5, 1, 100 + i, TOL[dtype])
 
 
-def test_batch_bf16_items_match_oracle():
-    """The bf16 path in the batch (bf16 sketch, split-bf16 power step,
-    projection and truncation on the wave kernels): the bounds of the lone
-    bf16 decompositions (E 1e-4, sigma 1e-3, projectors 1e-2 with q = 1)."""
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_batch_bf16_items_match_oracle(prec):
+    """The bf16 path in the batch (bf16 sketch, split-bf16 power step and
+    projection on the batched column kernels, the truncation on the batched
+    truncation kernel; e4m3 items take the bf16 sketch there): the bounds of
+    the lone bf16 decompositions (E 1e-4, sigma 1e-3, projectors 1e-2 with
+    q = 1)."""
     specs = batch_specs(count=20, seed=17, dim_range=(24, 200), rank_range=(3, 12))
     xs = batch_tensors(specs, seed=17, noise=1e-2, dtype=np.float32)
-    b = api.Batch(_items(specs, xs, prec="bf16"))
+    b = api.Batch(_items(specs, xs, prec=prec))
     b.run(use_graph=False)
     torch.cuda.synchronize()
     worst = 0.0
@@ -82,7 +85,7 @@ def test_batch_bf16_items_match_oracle():
             np.testing.assert_allclose(res.sigma(n), ref.sigma[n], rtol=1e-3, atol=1e-3 * ref.sigma[n][0])
             u = res.factors[n].cpu().numpy().astype(np.float64)
             assert np.linalg.norm(u @ u.T - ref.factors[n] @ ref.factors[n].T, 2) <= 1e-2
-    print(f"[batch] bf16: {len(specs)} items, {b.launches} launches, worst |dE| {worst:.2e}", flush=True)
+    print(f"[batch] {prec}: {len(specs)} items, {b.launches} launches, worst |dE| {worst:.2e}", flush=True)
 
 
 @pytest.mark.parametrize("prec", [None, "bf16"])

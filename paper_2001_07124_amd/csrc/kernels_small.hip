@@ -66,19 +66,35 @@ __global__ __launch_bounds__(kBlock) void k_reduce_parts(const T* __restrict__ p
     reduce_parts_body<T>(part, G, I, K, I_pad, K_pad, y, blockIdx.x);
 }
 
-// Workgroup (x, y): block x of job y (blocks past the job's I K / 16 return).
+// Batch: the items' passes have few partials (at most the workgroups per
+// item), so each thread sums one element's G partials itself, in ascending
+// order with eight loads in flight; workgroup (x, y) takes elements
+// 256 x .. 256 x + 255 of job y (blocks past the job's I K return).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_reduce_parts_batch(const ReduceJob* __restrict__ jobs) {
-    const ReduceJob j = jobs[blockIdx.y];
-    if (static_cast<int>(blockIdx.x) * 16 >= j.I * j.K) return;
-    reduce_parts_body<T>(static_cast<const T*>(j.part), j.G, j.I, j.K, j.I_pad, j.K_pad, j.y,
-                         blockIdx.x);
+    const ReduceJob& j = jobs[blockIdx.y];
+    const int e = static_cast<int>(blockIdx.x) * kBlock + static_cast<int>(threadIdx.x);
+    if (e >= j.I * j.K) return;
+    const int k = e / j.I, i = e - k * j.I;
+    const size_t stride = static_cast<size_t>(j.K_pad) * j.I_pad;
+    const T* __restrict__ p = static_cast<const T*>(j.part) + static_cast<size_t>(k) * j.I_pad + i;
+    double sum = 0.0;
+    int g = 0;
+    for (; g + 8 <= j.G; g += 8) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = static_cast<double>(p[(g + u) * stride]);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sum += a[u];
+    }
+    for (; g < j.G; ++g) sum += static_cast<double>(p[g * stride]);
+    j.y[e] = sum;
 }
 
 hipError_t launch_reduce_parts_batch(bool dbl, const ReduceJob* jobs, int njobs, int max_elems,
                                      hipStream_t s) {
     if (njobs < 1 || max_elems < 1) return hipErrorInvalidValue;
-    const dim3 grid((max_elems + 15) / 16, njobs);
+    const dim3 grid((max_elems + kBlock - 1) / kBlock, njobs);
     if (dbl)
         hipLaunchKernelGGL(k_reduce_parts_batch<double>, grid, dim3(kBlock), 0, s, jobs);
     else

@@ -279,8 +279,10 @@ int32_t rhosvd_decompose_adaptive(rhosvd_ctx* ctx, const rhosvd_tensor* x,
  * RHOSVD_R_STHOSVD in the natural mode order, without
  * RHOSVD_OPT_EXPLICIT_ERROR; one order N and one dtype for the batch; every
  * mode I_n <= 256 and K_n <= RHOSVD_MAX_SKETCH.  Dims, ranks, p, q, seed and
- * precision may differ per item.  Up to 16 workgroups per item and pass;
- * the items of one kernel instantiation share a launch.  The sketch, power
+ * precision may differ per item.  Up to 16 workgroups per item and pass
+ * (12 on the column and truncation kernels, each with at least 16 column
+ * blocks); the items of one kernel instantiation share a launch, the largest
+ * first.  The sketch, power
  * step and projection of a bf16-path item (RHOSVD_PREC_BF16, and
  * RHOSVD_PREC_FP8E4M3 with a bf16 sketch) run on the column kernels (32
  * columns per wave), of an RHOSVD_PREC_F32 item on the wave kernels (16

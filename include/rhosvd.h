@@ -316,8 +316,12 @@ int32_t rhosvd_batch_bind(rhosvd_batch* batch, void* workspace, size_t ws_bytes,
 
 /* Enqueue the whole batch on `stream`.  use_graph != 0 and a non-null
  * stream: the first call captures the launch sequence into a HIP graph,
- * every call launches that graph (one launch); otherwise the launches are
- * enqueued directly.  Inputs and outputs are the recorded ones. */
+ * every call launches that graph (one launch); the launches of one step that
+ * serve different kernel instantiations (disjoint items) are parallel
+ * branches of the graph, captured through side streams of default priority
+ * that the batch creates on that first call and keeps.  Otherwise the
+ * launches are enqueued directly, one after another.  Inputs and outputs are
+ * the recorded ones. */
 int32_t rhosvd_batch_run(rhosvd_batch* batch, int32_t use_graph, void* stream);
 
 /* Number of kernel launches in one run of the batch (0 before binding). */

@@ -1526,6 +1526,9 @@ enum BatchKind { BK_STREAM, BK_REDUCE, BK_QR, BK_EVD, BK_INIT, BK_NORMX, BK_FINI
 
 struct BatchLaunch {
     int kind = 0, op = 0, njobs = 0, sel = 0;
+    int grp = 0;                      // launches of one pass, QR or EVD step (disjoint
+                                      // items, so independent of each other) share a
+                                      // nonzero group
     int ct = 0, var = 0;              // BK_WAVE: compute type and shape of the instantiation;
                                       // BK_COL: flag (Gram / sum of squares) and shape;
                                       // BK_TRUNC: row tiles and step bound
@@ -1631,10 +1634,18 @@ struct rhosvd_batch {
     std::vector<BatchLaunch> prog;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // side streams (default priority) and events that fork the launches of one
+    // group into parallel branches of the captured graph
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> joins;
+    hipEvent_t fork = nullptr;
     ~rhosvd_batch() {
         for (Plan* p : plans) delete p;
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        for (hipStream_t t : side) (void)hipStreamDestroy(t);
+        for (hipEvent_t e : joins) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
     }
 };
 
@@ -1660,11 +1671,13 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
     std::vector<Buffers> bufs(n);
     for (int i = 0; i < n; ++i) carve(*B->plans[i], B->ws + B->region[i], &bufs[i]);
     std::vector<const void*> cur(B->x.begin(), B->x.end());
+    int cur_grp = 0;
     auto add_stream = [&](int op, std::vector<rh::StreamJob>& jobs) {
         if (jobs.empty()) return;
         BatchLaunch L;
         L.kind = BK_STREAM;
         L.op = op;
+        L.grp = cur_grp;
         L.njobs = static_cast<int>(jobs.size());
         for (auto& j : jobs) {
             L.sel = std::max(L.sel, j.units);
@@ -1680,6 +1693,7 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
         rh::StreamArgs a;
     };
     auto add_pass = [&](int op, const std::vector<PassJob>& jobs) {
+        ++cur_grp;
         std::vector<rh::StreamJob> tiled;
         std::map<std::pair<int, int>, std::vector<rh::WaveJob>> wave;
         std::map<std::pair<int, int>, std::vector<rh::ColJob>> col;
@@ -1727,6 +1741,7 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
             BatchLaunch L;
             L.kind = BK_TRUNC;
             L.op = op;
+            L.grp = cur_grp;
             L.ct = kv.first.first;
             L.var = kv.first.second;
             L.njobs = static_cast<int>(kv.second.size());
@@ -1745,6 +1760,7 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
             BatchLaunch L;
             L.kind = BK_COL;
             L.op = op;
+            L.grp = cur_grp;
             L.ct = kv.first.first;
             L.var = kv.first.second;
             L.njobs = static_cast<int>(kv.second.size());
@@ -1762,6 +1778,7 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
             BatchLaunch L;
             L.kind = BK_WAVE;
             L.op = op;
+            L.grp = cur_grp;
             L.ct = kv.first.first;
             L.var = kv.first.second;
             L.njobs = static_cast<int>(kv.second.size());
@@ -1783,6 +1800,7 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
         B->prog.push_back(L);
     };
     auto add_qr = [&](std::vector<rh::QrJob>& jobs) {
+        ++cur_grp;
         for (int ns = 1; ns <= 4; ++ns) {
             std::vector<rh::QrJob> sub;
             size_t lds = 0;
@@ -1794,6 +1812,7 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
             if (sub.empty()) continue;
             BatchLaunch L;
             L.kind = BK_QR;
+            L.grp = cur_grp;
             L.njobs = static_cast<int>(sub.size());
             L.sel = ns;
             L.lds = lds;
@@ -1909,6 +1928,7 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
         }
         add_pass(rh::OP_TTM, tj);
         add_reduce(gj);
+        ++cur_grp;
         for (int kb = 8; kb <= 64; kb += 8) {
             std::vector<rh::EvdJob> sub;
             size_t lds = 0;
@@ -1920,6 +1940,7 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
             if (sub.empty()) continue;
             BatchLaunch L;
             L.kind = BK_EVD;
+            L.grp = cur_grp;
             L.njobs = static_cast<int>(sub.size());
             L.sel = kb;
             L.lds = lds;
@@ -1955,51 +1976,90 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
     }
 }
 
-hipError_t run_program(const rhosvd_batch* B, hipStream_t s) {
-    for (const BatchLaunch& L : B->prog) {
-        const void* t = B->ws + L.off;
+hipError_t launch_one(const rhosvd_batch* B, const BatchLaunch& L, hipStream_t s) {
+    const void* t = B->ws + L.off;
+    hipError_t e = hipSuccess;
+    switch (L.kind) {
+        case BK_STREAM:
+            e = rh::launch_stream_batch(L.op, B->dbl, static_cast<const rh::StreamJob*>(t),
+                                        L.njobs, L.sel, L.lds, s);
+            break;
+        case BK_REDUCE:
+            e = rh::launch_reduce_parts_batch(B->dbl, static_cast<const rh::ReduceJob*>(t),
+                                              L.njobs, L.sel, s);
+            break;
+        case BK_QR:
+            e = rh::launch_hqr_batch(static_cast<const rh::QrJob*>(t), L.njobs, L.sel, L.lds, s);
+            break;
+        case BK_EVD:
+            e = rh::launch_evd_factor_batch(B->dbl, static_cast<const rh::EvdJob*>(t), L.njobs,
+                                            L.sel, L.lds, s);
+            break;
+        case BK_INIT:
+            e = rh::launch_batch_report_init(static_cast<const rh::ReportJob*>(t), L.njobs, s);
+            break;
+        case BK_NORMX:
+            e = rh::launch_batch_norm_x(static_cast<const rh::SumJob*>(t), L.njobs, s);
+            break;
+        case BK_FINISH:
+            e = rh::launch_batch_finish(B->dbl, static_cast<const rh::FinishJob*>(t), L.njobs, s);
+            break;
+        case BK_WAVE:
+            e = rh::launch_wave_batch(L.op, L.ct, L.var, static_cast<const rh::WaveJob*>(t),
+                                      L.njobs, L.sel, L.lds, s);
+            break;
+        case BK_COL:
+            e = rh::launch_col_batch(L.op, L.var, L.ct != 0, static_cast<const rh::ColJob*>(t),
+                                     L.njobs, L.sel, L.lds, s);
+            break;
+        case BK_TRUNC:
+            e = rh::launch_trunc_batch(B->dbl, L.ct, L.var, static_cast<const rh::TruncJob*>(t),
+                                       L.njobs, L.sel, L.lds, s);
+            break;
+        default:
+            e = hipErrorInvalidValue;
+    }
+    return e;
+}
+
+// Longest run of consecutive launches of one group.
+size_t longest_group(const rhosvd_batch* B) {
+    size_t best = 1;
+    for (size_t i = 0; i < B->prog.size();) {
+        size_t j = i + 1;
+        while (j < B->prog.size() && B->prog[i].grp != 0 && B->prog[j].grp == B->prog[i].grp) ++j;
+        best = std::max(best, j - i);
+        i = j;
+    }
+    return best;
+}
+
+// The program on stream s.  With fork (the side streams and events exist for
+// the longest group), the launches of a group after its first go to side
+// streams that wait for s and that s waits for afterwards: captured, they are
+// parallel branches of the graph, so one launch's tail overlaps the others.
+hipError_t run_program(const rhosvd_batch* B, hipStream_t s, bool fork) {
+    const size_t n = B->prog.size();
+    for (size_t i = 0; i < n;) {
+        size_t j = i + 1;
+        while (j < n && B->prog[i].grp != 0 && B->prog[j].grp == B->prog[i].grp) ++j;
         hipError_t e = hipSuccess;
-        switch (L.kind) {
-            case BK_STREAM:
-                e = rh::launch_stream_batch(L.op, B->dbl, static_cast<const rh::StreamJob*>(t),
-                                            L.njobs, L.sel, L.lds, s);
-                break;
-            case BK_REDUCE:
-                e = rh::launch_reduce_parts_batch(B->dbl, static_cast<const rh::ReduceJob*>(t),
-                                                  L.njobs, L.sel, s);
-                break;
-            case BK_QR:
-                e = rh::launch_hqr_batch(static_cast<const rh::QrJob*>(t), L.njobs, L.sel, L.lds, s);
-                break;
-            case BK_EVD:
-                e = rh::launch_evd_factor_batch(B->dbl, static_cast<const rh::EvdJob*>(t), L.njobs,
-                                                L.sel, L.lds, s);
-                break;
-            case BK_INIT:
-                e = rh::launch_batch_report_init(static_cast<const rh::ReportJob*>(t), L.njobs, s);
-                break;
-            case BK_NORMX:
-                e = rh::launch_batch_norm_x(static_cast<const rh::SumJob*>(t), L.njobs, s);
-                break;
-            case BK_FINISH:
-                e = rh::launch_batch_finish(B->dbl, static_cast<const rh::FinishJob*>(t), L.njobs, s);
-                break;
-            case BK_WAVE:
-                e = rh::launch_wave_batch(L.op, L.ct, L.var, static_cast<const rh::WaveJob*>(t),
-                                          L.njobs, L.sel, L.lds, s);
-                break;
-            case BK_COL:
-                e = rh::launch_col_batch(L.op, L.var, L.ct != 0, static_cast<const rh::ColJob*>(t),
-                                         L.njobs, L.sel, L.lds, s);
-                break;
-            case BK_TRUNC:
-                e = rh::launch_trunc_batch(B->dbl, L.ct, L.var, static_cast<const rh::TruncJob*>(t),
-                                           L.njobs, L.sel, L.lds, s);
-                break;
-            default:
-                e = hipErrorInvalidValue;
+        if (fork && j - i > 1 && j - i - 1 <= B->side.size()) {
+            e = hipEventRecord(B->fork, s);
+            for (size_t k = i + 1; k < j && e == hipSuccess; ++k) {
+                hipStream_t t = B->side[k - i - 1];
+                e = hipStreamWaitEvent(t, B->fork, 0);
+                if (e == hipSuccess) e = launch_one(B, B->prog[k], t);
+                if (e == hipSuccess) e = hipEventRecord(B->joins[k - i - 1], t);
+            }
+            if (e == hipSuccess) e = launch_one(B, B->prog[i], s);
+            for (size_t k = i + 1; k < j && e == hipSuccess; ++k)
+                e = hipStreamWaitEvent(s, B->joins[k - i - 1], 0);
+        } else {
+            for (size_t k = i; k < j && e == hipSuccess; ++k) e = launch_one(B, B->prog[k], s);
         }
         if (e != hipSuccess) return e;
+        i = j;
     }
     return hipSuccess;
 }
@@ -2197,12 +2257,25 @@ int32_t rhosvd_batch_run(rhosvd_batch* B, int32_t use_graph, void* stream) {
     if (dev != B->ctx->device) RH_HIP(hipSetDevice(B->ctx->device));
     hipError_t e = hipSuccess;
     if (!use_graph || !s) {
-        e = run_program(B, s);
+        e = run_program(B, s, false);
     } else {
         if (!B->exec) {
-            e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            // side streams and events for the longest group, made before the capture
+            const size_t need = longest_group(B) - 1;
+            while (e == hipSuccess && B->side.size() < need) {
+                hipStream_t t = nullptr;
+                e = hipStreamCreateWithFlags(&t, hipStreamNonBlocking);
+                if (e == hipSuccess) B->side.push_back(t);
+            }
+            while (e == hipSuccess && B->joins.size() < need) {
+                hipEvent_t ev = nullptr;
+                e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+                if (e == hipSuccess) B->joins.push_back(ev);
+            }
+            if (e == hipSuccess && !B->fork) e = hipEventCreateWithFlags(&B->fork, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                const hipError_t er = run_program(B, s);
+                const hipError_t er = run_program(B, s, true);
                 hipGraph_t g = nullptr;
                 e = hipStreamEndCapture(s, &g);
                 if (er != hipSuccess) e = er;

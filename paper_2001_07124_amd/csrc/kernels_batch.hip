@@ -52,12 +52,25 @@ __global__ __launch_bounds__(kBlock) void k_batch_finish(const FinishJob* __rest
     __shared__ double red[kBlock];
     const FinishJob& j = jobs[blockIdx.x];
     const T* core = static_cast<const T*>(j.core);
-    double s = 0.0;
-    for (int64_t e = threadIdx.x; e < j.core_elems; e += kBlock) {
-        const double v = static_cast<double>(core[e]);
-        s = fma(v, v, s);
+    // eight loads in flight per thread, four accumulation chains (fixed order)
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t n = j.core_elems;
+    int64_t e = threadIdx.x;
+    for (; e + 7 * kBlock < n; e += 8 * kBlock) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = core[e + u * kBlock];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double d = static_cast<double>(v[u]);
+            s4[u & 3] = fma(d, d, s4[u & 3]);
+        }
     }
-    red[threadIdx.x] = s;
+    for (; e < n; e += kBlock) {
+        const double d = static_cast<double>(core[e]);
+        s4[0] = fma(d, d, s4[0]);
+    }
+    red[threadIdx.x] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
@@ -66,10 +79,21 @@ __global__ __launch_bounds__(kBlock) void k_batch_finish(const FinishJob* __rest
     if (threadIdx.x == 0) j.rep->norm_core2 = red[0];
     __syncthreads();
     if (j.out_report) {
-        const unsigned char* src = reinterpret_cast<const unsigned char*>(j.rep);
-        unsigned char* dst = static_cast<unsigned char*>(j.out_report);
-        for (int e = threadIdx.x; e < static_cast<int>(sizeof(rhosvd_report)); e += kBlock)
-            dst[e] = src[e];
+        // 8-byte words when both ends allow them (the report's size is a
+        // multiple of 8); the pointers do not alias, so every load of a thread
+        // is issued before its stores
+        constexpr int kWords = static_cast<int>(sizeof(rhosvd_report) / 8);
+        static_assert(sizeof(rhosvd_report) % 8 == 0, "the report is copied in 8-byte words");
+        if (((reinterpret_cast<uintptr_t>(j.rep) | reinterpret_cast<uintptr_t>(j.out_report)) & 7) == 0) {
+            const uint64_t* __restrict__ src = reinterpret_cast<const uint64_t*>(j.rep);
+            uint64_t* __restrict__ dst = static_cast<uint64_t*>(j.out_report);
+            for (int e = threadIdx.x; e < kWords; e += kBlock) dst[e] = src[e];
+        } else {
+            const unsigned char* __restrict__ src = reinterpret_cast<const unsigned char*>(j.rep);
+            unsigned char* __restrict__ dst = static_cast<unsigned char*>(j.out_report);
+            for (int e = threadIdx.x; e < static_cast<int>(sizeof(rhosvd_report)); e += kBlock)
+                dst[e] = src[e];
+        }
     }
 }
 

@@ -1521,6 +1521,11 @@ constexpr int kBatchWaveUnits = 16;
 // jobs in item order
 constexpr int kBatchColUnits = 12;
 constexpr int kBatchColMinBlocks = 16;
+// most parallel branches of one group in the captured graph: the largest
+// launches get one each, the smallest follow one another on the caller's
+// stream (with up to ten branches the graph's tenth launch waited for all
+// the others)
+constexpr size_t kBatchBranches = 8;
 
 enum BatchKind { BK_STREAM, BK_REDUCE, BK_QR, BK_EVD, BK_INIT, BK_NORMX, BK_FINISH, BK_WAVE, BK_COL, BK_TRUNC };
 
@@ -1529,6 +1534,7 @@ struct BatchLaunch {
     int grp = 0;                      // launches of one pass, QR or EVD step (disjoint
                                       // items, so independent of each other) share a
                                       // nonzero group
+    double work = 0.0;                // size estimate that orders a group's launches
     int ct = 0, var = 0;              // BK_WAVE: compute type and shape of the instantiation;
                                       // BK_COL: flag (Gram / sum of squares) and shape;
                                       // BK_TRUNC: row tiles and step bound
@@ -1672,12 +1678,18 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
     for (int i = 0; i < n; ++i) carve(*B->plans[i], B->ws + B->region[i], &bufs[i]);
     std::vector<const void*> cur(B->x.begin(), B->x.end());
     int cur_grp = 0;
+    // a group's launches (the tail of the program from `start`) by decreasing size
+    auto order_group = [&](size_t start) {
+        std::stable_sort(B->prog.begin() + static_cast<std::ptrdiff_t>(start), B->prog.end(),
+                         [](const BatchLaunch& a, const BatchLaunch& b) { return a.work > b.work; });
+    };
     auto add_stream = [&](int op, std::vector<rh::StreamJob>& jobs) {
         if (jobs.empty()) return;
         BatchLaunch L;
         L.kind = BK_STREAM;
         L.op = op;
         L.grp = cur_grp;
+        L.work = static_cast<double>(jobs.size());
         L.njobs = static_cast<int>(jobs.size());
         for (auto& j : jobs) {
             L.sel = std::max(L.sel, j.units);
@@ -1694,6 +1706,7 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
     };
     auto add_pass = [&](int op, const std::vector<PassJob>& jobs) {
         ++cur_grp;
+        const size_t start = B->prog.size();
         std::vector<rh::StreamJob> tiled;
         std::map<std::pair<int, int>, std::vector<rh::WaveJob>> wave;
         std::map<std::pair<int, int>, std::vector<rh::ColJob>> col;
@@ -1746,6 +1759,7 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
             L.var = kv.first.second;
             L.njobs = static_cast<int>(kv.second.size());
             for (auto& t : kv.second) {
+                L.work += static_cast<double>(t.K) * static_cast<double>(t.J);
                 L.sel = std::max(L.sel, t.units);
                 const size_t lds = rh::trunc_lds_bytes(t.K, B->dbl);
                 L.lds = std::max(L.lds, lds);
@@ -1765,6 +1779,7 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
             L.var = kv.first.second;
             L.njobs = static_cast<int>(kv.second.size());
             for (auto& c : kv.second) {
+                L.work += static_cast<double>(c.g.I) * static_cast<double>(c.g.J);
                 L.sel = std::max(L.sel, c.units);
                 L.lds = std::max(L.lds, c.g.lds_bytes);
             }
@@ -1783,12 +1798,14 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
             L.var = kv.first.second;
             L.njobs = static_cast<int>(kv.second.size());
             for (auto& w : kv.second) {
+                L.work += static_cast<double>(w.g.I) * static_cast<double>(w.g.J);
                 L.sel = std::max(L.sel, w.units);
                 L.lds = std::max(L.lds, w.g.lds_bytes);
             }
             L.off = tw->put(kv.second);
             B->prog.push_back(L);
         }
+        order_group(start);
     };
     auto add_reduce = [&](std::vector<rh::ReduceJob>& jobs) {
         if (jobs.empty()) return;
@@ -1801,6 +1818,7 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
     };
     auto add_qr = [&](std::vector<rh::QrJob>& jobs) {
         ++cur_grp;
+        const size_t start = B->prog.size();
         for (int ns = 1; ns <= 4; ++ns) {
             std::vector<rh::QrJob> sub;
             size_t lds = 0;
@@ -1813,12 +1831,14 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
             BatchLaunch L;
             L.kind = BK_QR;
             L.grp = cur_grp;
+            L.work = static_cast<double>(sub.size()) * ns;
             L.njobs = static_cast<int>(sub.size());
             L.sel = ns;
             L.lds = lds;
             L.off = tw->put(sub);
             B->prog.push_back(L);
         }
+        order_group(start);
     };
     // report initialisation
     {
@@ -1929,6 +1949,7 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
         add_pass(rh::OP_TTM, tj);
         add_reduce(gj);
         ++cur_grp;
+        const size_t evd_start = B->prog.size();
         for (int kb = 8; kb <= 64; kb += 8) {
             std::vector<rh::EvdJob> sub;
             size_t lds = 0;
@@ -1941,12 +1962,14 @@ void build_program(rhosvd_batch* B, TableWriter* tw) {
             BatchLaunch L;
             L.kind = BK_EVD;
             L.grp = cur_grp;
+            L.work = static_cast<double>(sub.size()) * kb;
             L.njobs = static_cast<int>(sub.size());
             L.sel = kb;
             L.lds = lds;
             L.off = tw->put(sub);
             B->prog.push_back(L);
         }
+        order_group(evd_start);
         // truncation S <- Ubar_R^T B, written rotated
         std::vector<PassJob> rj2;
         for (int i = 0; i < n; ++i) {
@@ -2034,27 +2057,31 @@ size_t longest_group(const rhosvd_batch* B) {
     return best;
 }
 
-// The program on stream s.  With fork (the side streams and events exist for
-// the longest group), the launches of a group after its first go to side
-// streams that wait for s and that s waits for afterwards: captured, they are
-// parallel branches of the graph, so one launch's tail overlaps the others.
+// The program on stream s.  With fork (the side streams and events exist),
+// the largest launches of a group (up to kBatchBranches - 1) go to side
+// streams that wait for s and that s waits for afterwards, and the others run
+// one after another on s: captured, they are parallel branches of the graph,
+// so one launch's tail overlaps the others.
 hipError_t run_program(const rhosvd_batch* B, hipStream_t s, bool fork) {
     const size_t n = B->prog.size();
     for (size_t i = 0; i < n;) {
         size_t j = i + 1;
         while (j < n && B->prog[i].grp != 0 && B->prog[j].grp == B->prog[i].grp) ++j;
         hipError_t e = hipSuccess;
-        if (fork && j - i > 1 && j - i - 1 <= B->side.size()) {
+        // the group's largest launches (it is ordered by size) on side
+        // branches, the rest one after another on s
+        const size_t nside = std::min(j - i, kBatchBranches) - 1;
+        if (fork && nside > 0 && nside <= B->side.size()) {
             e = hipEventRecord(B->fork, s);
-            for (size_t k = i + 1; k < j && e == hipSuccess; ++k) {
-                hipStream_t t = B->side[k - i - 1];
+            for (size_t k = 0; k < nside && e == hipSuccess; ++k) {
+                hipStream_t t = B->side[k];
                 e = hipStreamWaitEvent(t, B->fork, 0);
-                if (e == hipSuccess) e = launch_one(B, B->prog[k], t);
-                if (e == hipSuccess) e = hipEventRecord(B->joins[k - i - 1], t);
+                if (e == hipSuccess) e = launch_one(B, B->prog[i + k], t);
+                if (e == hipSuccess) e = hipEventRecord(B->joins[k], t);
             }
-            if (e == hipSuccess) e = launch_one(B, B->prog[i], s);
-            for (size_t k = i + 1; k < j && e == hipSuccess; ++k)
-                e = hipStreamWaitEvent(s, B->joins[k - i - 1], 0);
+            for (size_t k = i + nside; k < j && e == hipSuccess; ++k) e = launch_one(B, B->prog[k], s);
+            for (size_t k = 0; k < nside && e == hipSuccess; ++k)
+                e = hipStreamWaitEvent(s, B->joins[k], 0);
         } else {
             for (size_t k = i; k < j && e == hipSuccess; ++k) e = launch_one(B, B->prog[k], s);
         }
@@ -2261,7 +2288,7 @@ int32_t rhosvd_batch_run(rhosvd_batch* B, int32_t use_graph, void* stream) {
     } else {
         if (!B->exec) {
             // side streams and events for the longest group, made before the capture
-            const size_t need = longest_group(B) - 1;
+            const size_t need = std::min(longest_group(B), kBatchBranches) - 1;
             while (e == hipSuccess && B->side.size() < need) {
                 hipStream_t t = nullptr;
                 e = hipStreamCreateWithFlags(&t, hipStreamNonBlocking);

@@ -10,7 +10,7 @@ replayed from a HIP graph) against the FP64 oracle, item by item (GPU only).
 * graph replays (the launches of one step for different kernel
   instantiations on parallel branches), with other device work and
   synchronisations between them, reproduce the directly enqueued run bit for
-  bit, on the FP32 and bf16 paths;
+  bit, on the FP32, bf16 and FP64 paths;
 * a sample of the 512-tensor workload (extents 32..256, ranks 4..32, p = 5,
   q = 1) against the oracle (the batch's identity-based E carries the FP32
   cancellation floor, 1e-7 / E, on top of the 1e-5).
@@ -109,13 +109,13 @@ def test_batch_alone_equals_in_the_mix(prec):
         assert torch.equal(a.report_buf, m.report_buf)
 
 
-@pytest.mark.parametrize("prec", [None, "bf16"])
-def test_batch_graph_replays_match_eager(prec):
+@pytest.mark.parametrize("dtype,prec", [(np.float32, None), (np.float32, "bf16"), (np.float64, None)])
+def test_batch_graph_replays_match_eager(dtype, prec):
     # extents up to 160 and ranks up to 12: several kernel shapes per pass
     # and several QR / EVD templates per step, so the graph holds parallel
     # branches (the launches of one step for different instantiations)
     specs = batch_specs(count=16, seed=9, dim_range=(24, 160), rank_range=(3, 12))
-    xs = batch_tensors(specs, seed=9, noise=1e-2, dtype=np.float32)
+    xs = batch_tensors(specs, seed=9, noise=1e-2, dtype=dtype)
     b = api.Batch(_items(specs, xs, prec=prec))
     b.run(use_graph=False)
     torch.cuda.synchronize()
